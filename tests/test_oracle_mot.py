@@ -1,0 +1,136 @@
+"""Pins of the oracle's direct marching-on-in-time (eqs. bie_disc, linear, App. A)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import elemint, mot
+from oracle.bspline import weights
+
+
+def _raw(geom, d, cdt, gstar, fam):
+    """Raw X^{(gamma)}_ij, gamma = 1..gstar (not kappa-summed), family index fam."""
+    X = np.zeros((gstar + 1, geom.ns, geom.ns))
+    for i in range(geom.ns):
+        for j in range(geom.ns):
+            V = geom.tris[j].reshape(3, 3)
+            for gm in range(1, gstar + 1):
+                X[gm, i, j] = elemint.elem(geom.x[i], geom.n[i], V, geom.n[j], gm * cdt, d, cdt,
+                                           self_pair=(i == j))[fam]
+    return X
+
+
+@pytest.mark.parametrize("d,bie", [(1, 1), (2, 1), (2, 0)])
+def test_tau_sigma_form_equals_compact_form(d, bie):
+    """App. A: with beta* truncation, sum (U tau~ - W sigma~) == sum_beta (C_U q - C_W u)."""
+    xyz, tri = synth.icosphere(1)
+    cdt = 0.5
+    m = mot.DirectMOT(xyz, tri, 1.0, cdt, d, bie, 0)
+    g = m.geom
+    gstar = int(math.ceil(2.0 / cdt)) + d + 1          # diameter 2
+    XU = _raw(g, d, cdt, gstar, 2 if bie else 0)
+    XW = _raw(g, d, cdt, gstar, 3 if bie else 1)
+    w = weights(d)
+    rng = np.random.default_rng(3)
+    nt = 20
+    u = rng.standard_normal((nt, g.ns))
+    q = rng.standard_normal((nt, g.ns))
+    for alpha in (3, 9, 17):
+        ref = m.history_rhs(alpha, u, q)
+        bstar = max(alpha - gstar, 0)
+        b = np.zeros(g.ns)
+        for bp in range(bstar, alpha):
+            kmax = min(d + 1, bp - bstar)
+            ks = range(1, kmax + 1) if bp == alpha - 1 else range(0, kmax + 1)
+            tau = sum(w[k] * q[bp - k] for k in ks)
+            sig = sum(w[k] * u[bp - k] for k in ks)
+            b += XU[alpha - bp] @ tau - XW[alpha - bp] @ sig
+        assert np.max(np.abs(b - ref)) <= 1e-12 * np.max(np.abs(ref)), alpha
+
+
+def _pulsating(level, d, bie, dt_scale=1.0):
+    xyz, tri = synth.icosphere(level)
+    dt = synth.mean_edge_length(xyz, tri) * dt_scale
+    nt = int(math.ceil(10.0 / dt))
+    m = mot.DirectMOT(xyz, tri, 1.0, dt, d, bie, mot.DIRICHLET)
+    f = lambda t: np.exp(-(t - 4.0) ** 2 / 0.5)
+    fp = lambda t: -(t - 4.0) / 0.25 * f(t)
+    beta = np.arange(nt - 1)
+    ubar = f(dt * (beta + (d + 1) / 2.0))[:, None] * np.ones((1, m.ns))   # Greville quasi-interpolant
+    u, q = m.run(nt, None, ubar)
+    qrec = mot.reconstruct(q, d)
+    ta = dt * np.arange(1, nt)
+    qex = (f(ta) + fp(ta))[:, None] * np.ones_like(qrec)   # d/dn u, n into the sphere, u = f(t-(r-1))/r
+    return np.linalg.norm(qrec - qex) / np.linalg.norm(qex)
+
+
+def test_pulsating_sphere_bm_d2_converges_in_h():
+    e2 = _pulsating(2, 2, mot.BMBIE)
+    e3 = _pulsating(3, 2, mot.BMBIE)
+    assert e2 < 0.12 and e3 < 0.06 and e2 / e3 > 1.6, (e2, e3)
+
+
+def test_pulsating_sphere_bm_d1_converges_in_dt():
+    e1 = _pulsating(2, 1, mot.BMBIE, 1.0)
+    e2 = _pulsating(2, 1, mot.BMBIE, 0.5)
+    assert e1 < 0.3 and e2 < 0.16 and e1 / e2 > 1.6, (e1, e2)
+
+
+def _late_over_peak(d, bie, bc, nt):
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    inc = synth.incident_params(xyz, seed=0)
+    m = mot.DirectMOT(xyz, tri, 1.0, dt, d, bie, bc)
+    F = mot.incident(m.geom, inc, 1.0, dt, nt, bie)
+    u, q = m.run(nt, F)
+    x = np.abs(q if bc == mot.DIRICHLET else u).max(axis=1)
+    return x[-10:].max() / max(x[: nt // 3].max(), 1e-300), x.max()
+
+
+def test_stability_pattern_tables_2_and_3():
+    """Qualitative pattern of Tables 2-3 on a small sphere: OBIE with d=2 diverges for
+    both conditions; the BMBIE decays for d=1 (Dirichlet) and d=1,2 (Neumann); the
+    BMBIE with d=2 does not settle for the Dirichlet problem."""
+    late, peak = _late_over_peak(2, mot.OBIE, mot.DIRICHLET, 64)
+    assert peak > 1e6
+    late, peak = _late_over_peak(2, mot.OBIE, mot.NEUMANN, 100)
+    assert peak > 1e6
+    assert _late_over_peak(1, mot.BMBIE, mot.DIRICHLET, 128)[0] < 1e-3
+    assert _late_over_peak(2, mot.BMBIE, mot.DIRICHLET, 128)[0] > 0.1
+    assert _late_over_peak(1, mot.BMBIE, mot.NEUMANN, 128)[0] < 1e-8
+    assert _late_over_peak(2, mot.BMBIE, mot.NEUMANN, 128)[0] < 1e-8
+
+
+def _extinction_residual(level, d, bie):
+    xyz, tri = synth.icosphere(level)
+    dt = synth.mean_edge_length(xyz, tri)
+    nt = int(math.ceil(9.0 / dt))
+    m = mot.DirectMOT(xyz, tri, 1.0, dt, d, bie, mot.DIRICHLET)
+    inc = synth.incident_params(xyz, seed=1)
+    g = m.geom
+    k = inc["dir"]
+    # incident traces, quasi-interpolated in time at Greville points
+    tb = dt * (np.arange(nt - 1) + (d + 1) / 2.0)[:, None]
+    p = tb - (g.x @ k + inc["rb"])[None, :] - inc["t0"]
+    sg, w = inc["sigma"], 2 * math.pi * inc["f0"]
+    env = np.exp(-p * p / (2 * sg * sg))
+    uin = env * np.cos(w * p)
+    gp = env * (-p / (sg * sg) * np.cos(w * p) - w * np.sin(w * p))
+    qin = gp * (-(g.n @ k))[None, :]
+    F = mot.incident(g, inc, 1.0, dt, nt, bie)
+    res = []
+    for alpha in range(1, nt):
+        r = F[alpha - 1] + m.history_rhs(alpha, uin, qin) + m.CU[1] @ qin[alpha - 1] - m.CW[1] @ uin[alpha - 1]
+        res.append(r)
+    return np.linalg.norm(res) / np.linalg.norm(F)
+
+
+@pytest.mark.parametrize("d,bie", [(1, 0), (1, 1), (2, 1)])
+def test_extinction_consistency(d, bie):
+    """Traces of a field regular inside the scatterer satisfy the discrete equation
+    up to a discretisation residual that shrinks under refinement."""
+    r1 = _extinction_residual(1, d, bie)
+    r2 = _extinction_residual(2, d, bie)
+    r3 = _extinction_residual(3, d, bie)
+    assert r2 < r1 and r3 < r2 and r3 < 0.5 and r2 / r3 > 1.5, (r1, r2, r3)
