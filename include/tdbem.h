@@ -1,0 +1,183 @@
+/*
+ * tdbem.h — C ABI of the MI355X time-domain boundary element library.
+ *
+ * The library solves the exterior initial-boundary value problem of the 3-D
+ * wave equation (paper: Section 2.1, eq. ibvp) on a closed surface of flat
+ * triangles with piecewise-constant densities in space and a uniform B-spline
+ * basis of order d in time (Section 2.3, eqs. u_bspline, decompose, w), by
+ * collocation at face centroids and times t_alpha = alpha*dt, alpha = 1..Nt-1.
+ * Either the ordinary BIE (eq. bie) or the Burton-Miller BIE (eq. bmbie, with
+ * the matrices of eq. U_W_BM) is marched in time (eq. linear).  The history
+ * part of the right-hand side is evaluated directly for near pairs (eq.
+ * linear, compact B-spline form) and, when enabled, by the interpolation-based
+ * space-time FMM for far pairs (Section 3, eqs. target, U_intp, m2l; Section 4,
+ * Formula 1 and Algorithm 1).
+ *
+ * Conventions
+ *  - Status: every int-returning call returns TDBEM_OK (0) or a negative
+ *    TDBEM_E_* code; tdbem_last_error() then holds a message for that context.
+ *  - Pointers named dev_* are HIP device pointers (e.g. torch.Tensor.data_ptr())
+ *    that must stay valid until the call returns; the library works on the
+ *    HIP stream given at creation and synchronises that stream before
+ *    returning from every call, so results are ready on return.
+ *  - Host pointers (mesh arrays, info structs) are read or written only during
+ *    the call.  The caller owns every buffer passed in; the library copies the
+ *    mesh at creation and owns all device tables and the density history
+ *    until tdbem_destroy().
+ *  - Mesh orientation: triangles counter-clockwise seen from OUTSIDE the
+ *    scatterer.  Internally the paper's normal n points into the scatterer
+ *    (this makes the free term part of the double layer, Section 2.4), so
+ *    q = du/dn is reported with that inward n.
+ *  - Array layouts are row-major; time-by-element arrays are [step][element].
+ *  - One context per host thread; distinct contexts are independent.
+ */
+#ifndef TDBEM_H
+#define TDBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TDBEM_OK = 0,
+  TDBEM_E_INVAL = -1,         /* bad argument or mesh */
+  TDBEM_E_NOMEM = -2,         /* device allocation failed */
+  TDBEM_E_DEVICE = -3,        /* HIP runtime error */
+  TDBEM_E_NOT_CONVERGED = -4, /* per-step GMRES did not reach its tolerance */
+  TDBEM_E_DIVERGED = -5,      /* non-finite or exploding solution */
+  TDBEM_E_STATE = -6          /* call out of order (e.g. step beyond nt_max) */
+};
+
+typedef enum { TDBEM_OBIE = 0, TDBEM_BMBIE = 1 } tdbem_bie;          /* eq. bie / eq. bmbie */
+typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1 } tdbem_bc;    /* u given (q unknown) / q given (u unknown) */
+typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1 } tdbem_m2l_prec;
+typedef enum { TDBEM_INC_GAUSS_MOD = 0, TDBEM_INC_RAISED_COS = 1 } tdbem_inc_kind;
+
+typedef struct {
+  int32_t nv, nt;        /* vertices, triangles */
+  const double *xyz;     /* host, nv x 3 */
+  const int32_t *tri;    /* host, nt x 3, CCW seen from outside */
+} tdbem_mesh;
+
+typedef struct {
+  int use_fmm;       /* 0: every pair evaluated directly (near-field kernel); 1: FMM for far pairs */
+  int depth;         /* octree depth: root level 0, leaves at level `depth` (FMM only, >= 2) */
+  int p_s, p_t;      /* Chebyshev nodes per axis in space and in time (FMM only) */
+  int mu;            /* near-future intervals (Section 4.2); 0 = smallest valid value */
+  int m2l_prec;      /* tdbem_m2l_prec */
+  double gmres_tol;  /* relative residual of the per-step solve (default 1e-12) */
+  int gmres_restart; /* default 30 */
+  int gmres_maxiter; /* default 300 */
+  int nt_max;        /* largest Nt the context will march (sizes the history), default 4096 */
+} tdbem_opts;
+
+typedef struct {
+  int kind;          /* tdbem_inc_kind */
+  double dir[3];     /* propagation direction (normalised by the library) */
+  double f0, sigma;  /* GAUSS_MOD: centre frequency and envelope width; RAISED_COS: sigma = pulse length */
+  double t0, rb;     /* GAUSS_MOD: delay; both: phase offset rb (arrival shift along dir) */
+} tdbem_incident;
+
+typedef struct {
+  int alpha;         /* collocation step just solved */
+  int iters;         /* GMRES iterations */
+  double resid;      /* final relative residual estimate */
+} tdbem_step_info;
+
+typedef struct {
+  int steps;            /* solves performed (nt-1) */
+  int total_iters;      /* GMRES iterations over the march */
+  int max_iters;        /* largest per-step iteration count */
+  double max_resid;     /* largest final relative residual */
+  double march_ms;      /* wall time of the march on the context stream (HIP events) */
+} tdbem_run_info;
+
+typedef struct {
+  int ns;               /* elements */
+  int d, bie, bc;
+  double c, dt;
+  int use_fmm, depth, p_s, p_t, mu, m_leaf;
+  int64_t near_pairs;   /* (i,j) pairs evaluated directly */
+  int64_t near_coefs;   /* compact coefficients per family in the near table */
+  int64_t a_nnz;        /* non-zeros of the per-step matrix */
+  int64_t il_pairs[16]; /* interaction-list pairs per level (FMM) */
+  int64_t m2l_matrix_bytes;
+  double setup_ms;
+} tdbem_info;
+
+/* Build a context: copies and validates the mesh (closed, consistently
+ * oriented, non-degenerate), precomputes the near-field compact coefficients
+ * C^{(g)}_ij = sum_kappa w^kappa X^{(g-kappa)}_ij (App. A, App. B) in FP64 on the
+ * device, the constant per-step matrix A (eq. linear), and with use_fmm the
+ * octree, space-time hierarchy and M2L operators (Section 3, Remark precomp).
+ * d in {1, 2}.  c > 0, dt > 0.  hip_stream: hipStream_t or NULL (null stream).
+ * opts NULL = defaults.  On success *out owns all device memory.
+ * Errors: TDBEM_E_INVAL (bad argument or mesh), TDBEM_E_NOMEM, TDBEM_E_DEVICE. */
+int tdbem_create(const tdbem_mesh *mesh, double c, double dt, int d, int bie, int bc,
+                 const tdbem_opts *opts, void *hip_stream, struct tdbem_ctx **out);
+
+/* Free every device buffer of the context.  NULL is ignored. */
+void tdbem_destroy(struct tdbem_ctx *ctx);
+
+/* Message of the last failing call on ctx (or of the last failed create when ctx is NULL). */
+const char *tdbem_last_error(const struct tdbem_ctx *ctx);
+
+/* Fill *info with sizes and derived parameters of the context. */
+int tdbem_get_info(const struct tdbem_ctx *ctx, tdbem_info *info);
+
+/* Return to the initial state (alpha = 1, zero history, zero FMM moments/locals). */
+int tdbem_reset(struct tdbem_ctx *ctx);
+
+/* Replace the stored history by nsteps coefficient rows beta = 0..nsteps-1
+ * (dev_u, dev_q: nsteps x Ns each; NULL = zeros) and position the march at
+ * alpha = nsteps + 1.  Moments and locals are rebuilt from the new history. */
+int tdbem_set_history(struct tdbem_ctx *ctx, int nsteps, const double *dev_u, const double *dev_q);
+
+/* History part of b^{alpha-1} (eq. linear) from the stored coefficients
+ * beta <= alpha-2:  sum_j sum_beta (C_U^{(alpha-beta)} q_j^beta - C_W^{(alpha-beta)} u_j^beta)
+ * (Burton-Miller matrices for the BMBIE), near pairs directly and far pairs by
+ * the FMM when enabled.  alpha must equal the current march position
+ * (1 <= alpha <= nsteps stored + 1).  dev_b_hist: Ns doubles, written. */
+int tdbem_fmm_eval(struct tdbem_ctx *ctx, int alpha, double *dev_b_hist);
+
+/* One step alpha -> alpha+1: b = forcing + history (near + far) + known
+ * current-step part, solve A x = b by GMRES (FP64), store x^{alpha-1} (u on
+ * Neumann faces, q on Dirichlet faces) and the prescribed coefficient, and
+ * advance the FMM (P2M, M2M, M2L by Algorithm 1, L2L).
+ * dev_forcing: Ns doubles f^alpha (u_in, or (d/dn - (1/c) d/dt) u_in for the
+ * BMBIE, with the inward normal), or NULL for zero.  dev_bc_values: Ns
+ * prescribed coefficients at beta = alpha-1 (u for Dirichlet, q for
+ * Neumann), NULL = homogeneous.  dev_x_out: Ns doubles or NULL.
+ * Errors: TDBEM_E_STATE past nt_max, TDBEM_E_NOT_CONVERGED, TDBEM_E_DIVERGED. */
+int tdbem_step(struct tdbem_ctx *ctx, const double *dev_forcing, const double *dev_bc_values,
+               double *dev_x_out, tdbem_step_info *info);
+
+/* March from the current position to alpha = nt-1 (normally from a fresh or
+ * reset context: nt-1 solves).  Forcing: dev_forcing ((nt-1) x Ns, row alpha-1)
+ * if not NULL, else the incident wave *inc evaluated on the device, else zero.
+ * dev_x_hist_out: (nt-1) x Ns solution coefficients, or NULL.  Homogeneous
+ * boundary condition.  info may be NULL. */
+int tdbem_run(struct tdbem_ctx *ctx, int nt, const double *dev_forcing, const tdbem_incident *inc,
+              double *dev_x_hist_out, tdbem_run_info *info);
+
+/* Copy the stored coefficients beta = 0..nsteps-1 to dev_u, dev_q (nsteps x Ns each; either may be NULL). */
+int tdbem_get_history(struct tdbem_ctx *ctx, int nsteps, double *dev_u, double *dev_q);
+
+/* Device evaluation of the incident forcing f^alpha for alpha = a0..a0+n-1 into
+ * dev_out (n x Ns): u_in (OBIE) or (d/dn - (1/c) d/dt) u_in (BMBIE) at the
+ * collocation points, inward normal. */
+int tdbem_incident_forcing(struct tdbem_ctx *ctx, const tdbem_incident *inc, int a0, int n, double *dev_out);
+
+/* Diagnostic access to the near-field compact coefficients of row i:
+ * writes up to cap entries (j, g, C_U^{(g)}_ij, C_W^{(g)}_ij) to host arrays;
+ * returns the number of entries of the row (>= 0) or an error code. */
+int tdbem_near_row(struct tdbem_ctx *ctx, int i, int cap, int32_t *j_out, int32_t *g_out,
+                   double *cu_out, double *cw_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDBEM_H */

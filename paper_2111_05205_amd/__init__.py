@@ -1,0 +1,162 @@
+"""MI355X time-domain boundary element method (Burton-Miller / ordinary BIE,
+B-spline time basis, interpolation-based space-time FMM) — Python binding.
+
+Every computation runs in the HIP library libtdbem.so behind the C ABI of
+include/tdbem.h; this module only marshals arguments.  Device arrays are
+torch float64 CUDA (HIP) tensors; the library works on the current torch
+stream of the tensors' device.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _native as N
+from ._native import (BMBIE, DIRICHLET, INC_GAUSS_MOD, INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
+
+__all__ = ["TDBEM", "TDBEMError", "incident", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
+           "INC_GAUSS_MOD", "INC_RAISED_COS"]
+
+
+class TDBEMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tdbem error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t, n=None, name="array"):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def incident(inc: dict):
+    """tdbem_incident from a dict with keys kind ('gauss_mod'|'raised_cos'), dir, f0, sigma, t0, rb."""
+    s = N.Incident()
+    s.kind = INC_GAUSS_MOD if inc["kind"] == "gauss_mod" else INC_RAISED_COS
+    for k in range(3):
+        s.dir[k] = float(inc["dir"][k])
+    s.f0, s.sigma, s.t0, s.rb = float(inc.get("f0", 1.0)), float(inc["sigma"]), float(inc.get("t0", 0.0)), \
+        float(inc.get("rb", 0.0))
+    return s
+
+
+class TDBEM:
+    """One scatterer: a context of the HIP library (tdbem_create ... tdbem_destroy)."""
+
+    def __init__(self, xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, *, use_fmm=0, depth=4, p_s=4, p_t=4, mu=0,
+                 m2l_prec=M2L_FP64, gmres_tol=1e-12, gmres_restart=30, gmres_maxiter=300, nt_max=4096,
+                 device=None):
+        torch = _torch()
+        self._L = N.lib()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        mesh = N.Mesh(xyz.shape[0], tri.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        o = N.Opts(int(use_fmm), int(depth), int(p_s), int(p_t), int(mu), int(m2l_prec), float(gmres_tol),
+                   int(gmres_restart), int(gmres_maxiter), int(nt_max))
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        rc = self._L.tdbem_create(ctypes.byref(mesh), float(c), float(dt), int(d), int(bie), int(bc),
+                                  ctypes.byref(o), ctypes.c_void_p(stream), ctypes.byref(h))
+        if rc != N.OK:
+            raise TDBEMError(rc, self._L.tdbem_last_error(None).decode())
+        self._h = h
+        inf = self.info()
+        self.ns = inf["ns"]
+        self.nt_max = int(nt_max)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tdbem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise TDBEMError(rc, self._L.tdbem_last_error(self._h).decode())
+        return rc
+
+    def _empty(self, *shape):
+        torch = _torch()
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def info(self):
+        i = N.Info()
+        self._check(self._L.tdbem_get_info(self._h, ctypes.byref(i)))
+        out = {k: getattr(i, k) for k, _ in N.Info._fields_}
+        out["il_pairs"] = list(i.il_pairs)
+        return out
+
+    def reset(self):
+        self._check(self._L.tdbem_reset(self._h))
+
+    def set_history(self, u=None, q=None):
+        nsteps = 0 if u is None and q is None else (u if u is not None else q).shape[0]
+        self._check(self._L.tdbem_set_history(self._h, nsteps, _dptr(u, nsteps * self.ns, "u"),
+                                              _dptr(q, nsteps * self.ns, "q")))
+
+    def get_history(self, nsteps):
+        u, q = self._empty(nsteps, self.ns), self._empty(nsteps, self.ns)
+        self._check(self._L.tdbem_get_history(self._h, nsteps, _dptr(u), _dptr(q)))
+        return u, q
+
+    def fmm_eval(self, alpha, out=None):
+        out = self._empty(self.ns) if out is None else out
+        self._check(self._L.tdbem_fmm_eval(self._h, int(alpha), _dptr(out, self.ns, "out")))
+        return out
+
+    def step(self, forcing=None, bc_values=None, out=None, check=True):
+        out = self._empty(self.ns) if out is None else out
+        si = N.StepInfo()
+        rc = self._L.tdbem_step(self._h, _dptr(forcing, self.ns, "forcing"), _dptr(bc_values, self.ns, "bc_values"),
+                                _dptr(out, self.ns, "out"), ctypes.byref(si))
+        if check:
+            self._check(rc)
+        return out, {"alpha": si.alpha, "iters": si.iters, "resid": si.resid, "rc": rc}
+
+    def run(self, nt, forcing=None, inc=None, out=None, check=True):
+        out = self._empty(nt - 1, self.ns) if out is None else out
+        ri = N.RunInfo()
+        incs = incident(inc) if isinstance(inc, dict) else inc
+        rc = self._L.tdbem_run(self._h, int(nt), _dptr(forcing, (nt - 1) * self.ns, "forcing"),
+                               ctypes.byref(incs) if incs is not None else None, _dptr(out, (nt - 1) * self.ns, "out"),
+                               ctypes.byref(ri))
+        if check:
+            self._check(rc)
+        return out, {k: getattr(ri, k) for k, _ in N.RunInfo._fields_} | {"rc": rc}
+
+    def incident_forcing(self, inc, a0, n):
+        out = self._empty(n, self.ns)
+        incs = incident(inc) if isinstance(inc, dict) else inc
+        self._check(self._L.tdbem_incident_forcing(self._h, ctypes.byref(incs), int(a0), int(n), _dptr(out)))
+        return out
+
+    def near_row(self, i):
+        n = self._check(self._L.tdbem_near_row(self._h, int(i), 0, None, None, None, None))
+        j = np.zeros(n, dtype=np.int32)
+        g = np.zeros(n, dtype=np.int32)
+        cu = np.zeros(n)
+        cw = np.zeros(n)
+        self._check(self._L.tdbem_near_row(self._h, int(i), n, j.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           cw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return j, g, cu, cw

@@ -1,0 +1,500 @@
+// C ABI of the library: context set-up and the marching-on-in-time driver.
+//
+// Step alpha (collocation time t_alpha, unknown coefficient beta = alpha-1),
+// eq. linear with the compact B-spline coefficients:
+//   b   = f^alpha + sum_{g>=2} (C_U^{(g)} q^{alpha-g} - C_W^{(g)} u^{alpha-g})   near pairs (direct)
+//       + far field at (x_i, t_alpha)                                        far pairs (FMM, L2P)
+//       + known current-step part (prescribed boundary coefficients)
+//   A x = b                                                                   GMRES, one workgroup
+//   store x (u on Neumann faces, q on Dirichlet faces) as row beta
+//   P2M of the new sample; interval-end M2M / M2L (Algorithm 1) / L2L           FMM
+// Everything runs on the context's stream; tdbem_run issues the whole march
+// without host synchronisation and reads the per-step statistics once.
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <utility>
+
+using namespace tdbem;
+
+static thread_local std::string g_create_err;
+
+template <class F>
+static int guarded(tdbem_ctx* ctx, F&& f) {
+  try {
+    f();
+    return TDBEM_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.msg; else g_create_err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what(); else g_create_err = e.what();
+    return TDBEM_E_INVAL;
+  }
+}
+
+static void fail(int code, const std::string& m) { throw Error(code, m); }
+
+// ---------------------------------------------------------------------------
+// Geometry and mesh validation (host).
+
+static Geometry build_geometry(const tdbem_mesh* mesh) {
+  if (!mesh || !mesh->xyz || !mesh->tri) fail(TDBEM_E_INVAL, "mesh arrays are NULL");
+  const int nv = mesh->nv, nt = mesh->nt;
+  if (nv < 4 || nt < 4) fail(TDBEM_E_INVAL, "mesh needs at least 4 vertices and 4 triangles");
+  if (nt > (1 << 27)) fail(TDBEM_E_INVAL, "too many triangles");
+  Geometry g;
+  g.ns = nt;
+  g.xc.resize(3 * (size_t)nt);
+  g.nrm.resize(3 * (size_t)nt);
+  g.tris.resize(9 * (size_t)nt);
+  g.area.resize(nt);
+  for (int k = 0; k < 3; ++k) { g.ext_lo[k] = 1e300; g.ext_hi[k] = -1e300; }
+  for (int v = 0; v < nv; ++v)
+    for (int k = 0; k < 3; ++k) {
+      const double c = mesh->xyz[3 * (size_t)v + k];
+      if (!std::isfinite(c)) fail(TDBEM_E_INVAL, "non-finite vertex coordinate");
+      g.ext_lo[k] = std::min(g.ext_lo[k], c);
+      g.ext_hi[k] = std::max(g.ext_hi[k], c);
+    }
+  std::map<std::pair<int, int>, int> edges;
+  double esum = 0.0;
+  long ecount = 0;
+  for (int t = 0; t < nt; ++t) {
+    int id[3];
+    for (int k = 0; k < 3; ++k) {
+      id[k] = mesh->tri[3 * (size_t)t + k];
+      if (id[k] < 0 || id[k] >= nv) fail(TDBEM_E_INVAL, "triangle index out of range");
+    }
+    if (id[0] == id[1] || id[1] == id[2] || id[0] == id[2]) fail(TDBEM_E_INVAL, "degenerate triangle");
+    const double* A = mesh->xyz + 3 * (size_t)id[0];
+    const double* B = mesh->xyz + 3 * (size_t)id[1];
+    const double* C = mesh->xyz + 3 * (size_t)id[2];
+    double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    double cr[3];
+    cross3(e1, e2, cr);
+    const double twoa = std::sqrt(dot3(cr, cr));
+    if (!(twoa > 0.0)) fail(TDBEM_E_INVAL, "zero-area triangle");
+    g.area[t] = 0.5 * twoa;
+    for (int k = 0; k < 3; ++k) {
+      g.nrm[3 * (size_t)t + k] = -cr[k] / twoa;  // paper normal: into the scatterer
+      g.xc[3 * (size_t)t + k] = (A[k] + B[k] + C[k]) / 3.0;
+      g.tris[9 * (size_t)t + k] = A[k];
+      g.tris[9 * (size_t)t + 3 + k] = B[k];
+      g.tris[9 * (size_t)t + 6 + k] = C[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      const int a = id[k], b = id[(k + 1) % 3];
+      if (++edges[{a, b}] > 1) fail(TDBEM_E_INVAL, "mesh is not consistently oriented (repeated directed edge)");
+      const double* P = mesh->xyz + 3 * (size_t)a;
+      const double* Q = mesh->xyz + 3 * (size_t)b;
+      double dv[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+      const double l = std::sqrt(dot3(dv, dv));
+      g.edge_max = std::max(g.edge_max, l);
+      if (a < b) { esum += l; ++ecount; }
+      double cv[3] = {P[0] - g.xc[3 * (size_t)t], P[1] - g.xc[3 * (size_t)t + 1], P[2] - g.xc[3 * (size_t)t + 2]};
+      g.e_max = std::max(g.e_max, std::sqrt(dot3(cv, cv)));
+    }
+  }
+  for (const auto& e : edges)
+    if (edges.find({e.first.second, e.first.first}) == edges.end())
+      fail(TDBEM_E_INVAL, "mesh is not closed (edge without an opposite edge)");
+  g.edge_mean = ecount ? esum / ecount : 0.0;
+  return g;
+}
+
+static BWeights bspline_weights(int d) {
+  BWeights b{};
+  b.d = d;
+  for (int k = 0; k <= d + 1; ++k) {
+    double p = 1.0;
+    for (int m = 0; m <= d + 1; ++m)
+      if (m != k) p *= (double)(m - k);
+    b.w[k] = (double)(d + 1) / p;
+  }
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels of the driver.
+
+__global__ void store_step_kernel(int ns, int beta, int bc, const double* __restrict__ x,
+                                  const double* __restrict__ bcv, double* __restrict__ hu, double* __restrict__ hq,
+                                  StepStat* __restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int64_t r = (int64_t)beta * ns + i;
+  const double xv = x[i], pv = bcv ? bcv[i] : 0.0;
+  if (bc == TDBEM_NEUMANN) { hu[r] = xv; hq[r] = pv; }
+  else { hq[r] = xv; hu[r] = pv; }
+  if (!isfinite(xv) || fabs(xv) > 1e100) atomicOr(&st->flags, 2);
+}
+
+__global__ void forcing_kernel(int ns, int a0, int n, int bie, double c, double dt, tdbem_incident inc,
+                               const double* __restrict__ xc, const double* __restrict__ nrm,
+                               double* __restrict__ out) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)n * ns) return;
+  const int i = (int)(id % ns);
+  const int a = a0 + (int)(id / ns);
+  const double t = a * dt;
+  const double kx = inc.dir[0] * xc[3 * i] + inc.dir[1] * xc[3 * i + 1] + inc.dir[2] * xc[3 * i + 2];
+  const double kn = inc.dir[0] * nrm[3 * i] + inc.dir[1] * nrm[3 * i + 1] + inc.dir[2] * nrm[3 * i + 2];
+  double val;
+  if (inc.kind == TDBEM_INC_GAUSS_MOD) {
+    // u = exp(-p^2 / 2 sigma^2) cos(2 pi f0 p), p = t - (k.x + rb)/c - t0
+    const double p = t - (kx + inc.rb) / c - inc.t0;
+    const double om = 2.0 * M_PI * inc.f0;
+    const double env = exp(-p * p / (2.0 * inc.sigma * inc.sigma));
+    const double cs = cos(om * p), sn = sin(om * p);
+    if (bie == TDBEM_OBIE) val = env * cs;
+    else {
+      const double du = env * (-p / (inc.sigma * inc.sigma) * cs - om * sn);  // du/dp
+      val = -du * (kn + 1.0) / c;  // grad u = -du k / c, du/dt = du
+    }
+  } else {
+    // u = (1 - cos a)/2 for 0 <= a <= 2 pi, else 0;  a = 2 pi (c t - k.x - rb) / lambda
+    const double lam = inc.sigma;
+    const double a2 = 2.0 * M_PI * (c * t - kx - inc.rb) / lam;
+    const bool in = a2 >= 0.0 && a2 <= 2.0 * M_PI;
+    if (bie == TDBEM_OBIE) val = in ? 0.5 * (1.0 - cos(a2)) : 0.0;
+    else val = in ? 0.5 * sin(a2) * (2.0 * M_PI / lam) * (-kn - 1.0) : 0.0;
+  }
+  out[id] = val;
+}
+
+namespace tdbem {
+void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc0, int a0, int n, double* out) {
+  tdbem_incident inc = inc0;
+  const double nd = std::sqrt(inc.dir[0] * inc.dir[0] + inc.dir[1] * inc.dir[1] + inc.dir[2] * inc.dir[2]);
+  if (!(nd > 0.0)) fail(TDBEM_E_INVAL, "incident direction is zero");
+  for (int k = 0; k < 3; ++k) inc.dir[k] /= nd;
+  if (inc.kind != TDBEM_INC_GAUSS_MOD && inc.kind != TDBEM_INC_RAISED_COS) fail(TDBEM_E_INVAL, "incident kind");
+  if (!(inc.sigma > 0.0)) fail(TDBEM_E_INVAL, "incident sigma must be > 0");
+  const int64_t tot = (int64_t)n * ctx->ns;
+  if (tot == 0) return;
+  forcing_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, ctx->stream>>>(ctx->ns, a0, n, ctx->bie, ctx->c, ctx->dt,
+                                                                         inc, ctx->d_xc.p, ctx->d_nrm.p, out);
+  TDBEM_HIP(hipGetLastError());
+}
+}  // namespace tdbem
+
+// ---------------------------------------------------------------------------
+
+static tdbem_opts default_opts() {
+  tdbem_opts o{};
+  o.use_fmm = 0;
+  o.depth = 4;
+  o.p_s = 4;
+  o.p_t = 4;
+  o.mu = 0;
+  o.m2l_prec = TDBEM_M2L_FP64;
+  o.gmres_tol = 1e-12;
+  o.gmres_restart = 30;
+  o.gmres_maxiter = 300;
+  o.nt_max = 4096;
+  return o;
+}
+
+static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, StepStat* stat) {
+  const int alpha = ctx->alpha, beta = alpha - 1;
+  if (alpha > ctx->nt_max - 1) fail(TDBEM_E_STATE, "step beyond nt_max");
+  launch_near_history(ctx, alpha, forcing, ctx->d_b.p);
+  if (ctx->fmm) fmm_far(ctx, alpha, ctx->d_b.p);
+  if (bcv) {
+    if (ctx->bc == TDBEM_DIRICHLET) launch_spmv_add(ctx, ctx->d_w1_val.p, -1.0, bcv, ctx->d_b.p);
+    else launch_spmv_add(ctx, ctx->d_u1_val.p, 1.0, bcv, ctx->d_b.p);
+  }
+  launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, stat);
+  store_step_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(ctx->ns, beta, ctx->bc, ctx->d_x.p, bcv,
+                                                                      ctx->d_hu.p, ctx->d_hq.p, stat);
+  TDBEM_HIP(hipGetLastError());
+  if (ctx->bc == TDBEM_NEUMANN) { ctx->hist_u = true; if (bcv) ctx->hist_q = true; }
+  else { ctx->hist_q = true; if (bcv) ctx->hist_u = true; }
+  if (ctx->fmm) fmm_advance(ctx, beta);
+  ctx->alpha = alpha + 1;
+}
+
+extern "C" {
+
+int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, int bc, const tdbem_opts* opts,
+                 void* hip_stream, tdbem_ctx** out) {
+  if (!out) { g_create_err = "out is NULL"; return TDBEM_E_INVAL; }
+  *out = nullptr;
+  tdbem_ctx* ctx = new tdbem_ctx();
+  int rc = guarded(nullptr, [&] {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!(c > 0.0) || !(dt > 0.0)) fail(TDBEM_E_INVAL, "c and dt must be > 0");
+    if (d < 1 || d > 2) fail(TDBEM_E_INVAL, "B-spline order d must be 1 or 2");
+    if (bie != TDBEM_OBIE && bie != TDBEM_BMBIE) fail(TDBEM_E_INVAL, "bie must be OBIE (0) or BMBIE (1)");
+    if (bc != TDBEM_DIRICHLET && bc != TDBEM_NEUMANN) fail(TDBEM_E_INVAL, "bc must be DIRICHLET (0) or NEUMANN (1)");
+    ctx->opts = opts ? *opts : default_opts();
+    tdbem_opts& o = ctx->opts;
+    if (!(o.gmres_tol > 0.0)) o.gmres_tol = 1e-12;
+    if (o.gmres_restart <= 0) o.gmres_restart = 30;
+    if (o.gmres_maxiter <= 0) o.gmres_maxiter = 300;
+    if (o.nt_max <= 1) o.nt_max = 4096;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->c = c;
+    ctx->dt = dt;
+    ctx->cdt = c * dt;
+    ctx->d = d;
+    ctx->bie = bie;
+    ctx->bc = bc;
+    ctx->bw = bspline_weights(d);
+    ctx->geo = build_geometry(mesh);
+    ctx->ns = ctx->geo.ns;
+    const int ns = ctx->ns;
+    upload_gl_rule();
+    ctx->d_xc.alloc(3 * (size_t)ns);
+    ctx->d_nrm.alloc(3 * (size_t)ns);
+    ctx->d_tris.alloc(9 * (size_t)ns);
+    TDBEM_HIP(hipMemcpyAsync(ctx->d_xc.p, ctx->geo.xc.data(), 3 * ns * sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+    TDBEM_HIP(hipMemcpyAsync(ctx->d_nrm.p, ctx->geo.nrm.data(), 3 * ns * sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+    TDBEM_HIP(hipMemcpyAsync(ctx->d_tris.p, ctx->geo.tris.data(), 9 * ns * sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> pair_j;
+    if (o.use_fmm) {
+      ctx->fmm = fmm_create(ctx);
+      fmm_near_pairs(ctx, row_ptr, pair_j);
+    } else {
+      if ((int64_t)ns * ns > (int64_t)2000000000) fail(TDBEM_E_INVAL, "direct mode limited to ~2e9 pairs");
+      row_ptr.resize(ns + 1);
+      pair_j.resize((size_t)ns * ns);
+      for (int i = 0; i <= ns; ++i) row_ptr[i] = (int64_t)i * ns;
+      for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ns; ++j) pair_j[(size_t)i * ns + j] = j;
+    }
+    build_near_table(ctx, row_ptr, pair_j);
+    build_step_matrix(ctx);
+    ctx->nt_max = o.nt_max;
+    ctx->d_hu.alloc((size_t)ctx->nt_max * ns);
+    ctx->d_hq.alloc((size_t)ctx->nt_max * ns);
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hu.p, 0, ctx->d_hu.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hq.p, 0, ctx->d_hq.n * sizeof(double), ctx->stream));
+    ctx->d_b.alloc(ns);
+    ctx->d_x.alloc(ns);
+    ctx->d_zero.alloc(ns);
+    ctx->d_V.alloc((size_t)(std::min(ctx->opts.gmres_restart, 32) + 1) * ns);
+    ctx->d_stat.alloc(ctx->nt_max);
+    TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ns * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_zero.p, 0, ns * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (rc != TDBEM_OK) {
+    tdbem_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return TDBEM_OK;
+}
+
+void tdbem_destroy(tdbem_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->fmm) fmm_destroy(ctx->fmm);
+  delete ctx;
+}
+
+const char* tdbem_last_error(const tdbem_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int tdbem_get_info(const tdbem_ctx* ctx, tdbem_info* info) {
+  if (!ctx || !info) return TDBEM_E_INVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->ns = ctx->ns;
+  info->d = ctx->d;
+  info->bie = ctx->bie;
+  info->bc = ctx->bc;
+  info->c = ctx->c;
+  info->dt = ctx->dt;
+  info->use_fmm = ctx->opts.use_fmm;
+  info->near_pairs = ctx->npairs;
+  info->near_coefs = ctx->ncoef;
+  info->a_nnz = ctx->a_nnz;
+  info->setup_ms = ctx->setup_ms;
+  if (ctx->fmm) fmm_info(ctx, info);
+  return TDBEM_OK;
+}
+
+int tdbem_reset(tdbem_ctx* ctx) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hu.p, 0, ctx->d_hu.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hq.p, 0, ctx->d_hq.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ctx->ns * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    ctx->alpha = 1;
+    ctx->hist_u = ctx->hist_q = false;
+    if (ctx->fmm) fmm_reset(ctx);
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tdbem_set_history(tdbem_ctx* ctx, int nsteps, const double* dev_u, const double* dev_q) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    if (nsteps < 0 || nsteps > ctx->nt_max - 1) fail(TDBEM_E_INVAL, "nsteps out of range");
+    const size_t bytes = (size_t)nsteps * ctx->ns * sizeof(double);
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hu.p, 0, ctx->d_hu.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hq.p, 0, ctx->d_hq.n * sizeof(double), ctx->stream));
+    if (dev_u && bytes) TDBEM_HIP(hipMemcpyAsync(ctx->d_hu.p, dev_u, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    if (dev_q && bytes) TDBEM_HIP(hipMemcpyAsync(ctx->d_hq.p, dev_q, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->hist_u = dev_u != nullptr;
+    ctx->hist_q = dev_q != nullptr;
+    ctx->alpha = nsteps + 1;
+    if (ctx->fmm) {
+      fmm_reset(ctx);
+      for (int beta = 0; beta < nsteps; ++beta) fmm_advance(ctx, beta);
+    }
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tdbem_fmm_eval(tdbem_ctx* ctx, int alpha, double* dev_b_hist) {
+  if (!ctx || !dev_b_hist) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    if (alpha < 1 || alpha > ctx->alpha || (ctx->fmm && alpha != ctx->alpha))
+      fail(TDBEM_E_STATE, "alpha must be the current march position");
+    launch_near_history(ctx, alpha, nullptr, dev_b_hist);
+    if (ctx->fmm) fmm_far(ctx, alpha, dev_b_hist);
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tdbem_step(tdbem_ctx* ctx, const double* dev_forcing, const double* dev_bc_values, double* dev_x_out,
+               tdbem_step_info* info) {
+  if (!ctx) return TDBEM_E_INVAL;
+  int rc = TDBEM_OK;
+  int r = guarded(ctx, [&] {
+    const int alpha = ctx->alpha;
+    StepStat* st = ctx->d_stat.p + (alpha - 1);
+    do_step(ctx, dev_forcing ? dev_forcing : ctx->d_zero.p, dev_bc_values, st);
+    if (dev_x_out)
+      TDBEM_HIP(hipMemcpyAsync(dev_x_out, ctx->d_x.p, ctx->ns * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    StepStat hs;
+    TDBEM_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, ctx->stream));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+    if (info) {
+      info->alpha = alpha;
+      info->iters = hs.iters;
+      info->resid = hs.resid;
+    }
+    if (hs.flags & 2) { ctx->err = "non-finite or exploding solution at step " + std::to_string(alpha); rc = TDBEM_E_DIVERGED; }
+    else if (hs.flags & 1) { ctx->err = "GMRES did not converge at step " + std::to_string(alpha); rc = TDBEM_E_NOT_CONVERGED; }
+  });
+  return r != TDBEM_OK ? r : rc;
+}
+
+int tdbem_run(tdbem_ctx* ctx, int nt, const double* dev_forcing, const tdbem_incident* inc, double* dev_x_hist_out,
+              tdbem_run_info* info) {
+  if (!ctx) return TDBEM_E_INVAL;
+  int rc = TDBEM_OK;
+  int r = guarded(ctx, [&] {
+    if (nt < 2 || nt > ctx->nt_max) fail(TDBEM_E_INVAL, "nt out of range [2, nt_max]");
+    const int a_first = ctx->alpha;
+    if (a_first > nt - 1) fail(TDBEM_E_STATE, "march already past nt-1; call tdbem_reset");
+    const int ns = ctx->ns;
+    const double* forc = dev_forcing;
+    if (!forc && inc) {
+      ctx->d_forc.alloc((size_t)(nt - 1) * ns);
+      launch_forcing(ctx, *inc, 1, nt - 1, ctx->d_forc.p);
+      forc = ctx->d_forc.p;
+    }
+    hipEvent_t e0, e1;
+    TDBEM_HIP(hipEventCreate(&e0));
+    TDBEM_HIP(hipEventCreate(&e1));
+    TDBEM_HIP(hipEventRecord(e0, ctx->stream));
+    for (int alpha = a_first; alpha <= nt - 1; ++alpha)
+      do_step(ctx, forc ? forc + (size_t)(alpha - 1) * ns : ctx->d_zero.p, nullptr, ctx->d_stat.p + (alpha - 1));
+    TDBEM_HIP(hipEventRecord(e1, ctx->stream));
+    if (dev_x_hist_out) {
+      const double* src = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
+      TDBEM_HIP(hipMemcpyAsync(dev_x_hist_out, src, (size_t)(nt - 1) * ns * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    std::vector<StepStat> st(nt - 1);
+    TDBEM_HIP(hipMemcpyAsync(st.data(), ctx->d_stat.p, (nt - 1) * sizeof(StepStat), hipMemcpyDeviceToHost,
+                             ctx->stream));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tdbem_run_info ri{};
+    ri.march_ms = ms;
+    for (int a = a_first; a <= nt - 1; ++a) {
+      const StepStat& s = st[a - 1];
+      ri.steps++;
+      ri.total_iters += s.iters;
+      ri.max_iters = std::max(ri.max_iters, s.iters);
+      ri.max_resid = std::max(ri.max_resid, s.resid);
+      if ((s.flags & 2) && rc == TDBEM_OK) { rc = TDBEM_E_DIVERGED; ctx->err = "non-finite or exploding solution at step " + std::to_string(a); }
+      else if ((s.flags & 1) && rc == TDBEM_OK) { rc = TDBEM_E_NOT_CONVERGED; ctx->err = "GMRES did not converge at step " + std::to_string(a); }
+    }
+    if (info) *info = ri;
+  });
+  return r != TDBEM_OK ? r : rc;
+}
+
+int tdbem_get_history(tdbem_ctx* ctx, int nsteps, double* dev_u, double* dev_q) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    if (nsteps < 0 || nsteps > ctx->nt_max) fail(TDBEM_E_INVAL, "nsteps out of range");
+    const size_t bytes = (size_t)nsteps * ctx->ns * sizeof(double);
+    if (dev_u && bytes) TDBEM_HIP(hipMemcpyAsync(dev_u, ctx->d_hu.p, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    if (dev_q && bytes) TDBEM_HIP(hipMemcpyAsync(dev_q, ctx->d_hq.p, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tdbem_incident_forcing(tdbem_ctx* ctx, const tdbem_incident* inc, int a0, int n, double* dev_out) {
+  if (!ctx || !inc || !dev_out || n < 0) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    launch_forcing(ctx, *inc, a0, n, dev_out);
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tdbem_near_row(tdbem_ctx* ctx, int i, int cap, int32_t* j_out, int32_t* g_out, double* cu_out, double* cw_out) {
+  if (!ctx) return TDBEM_E_INVAL;
+  int count = 0;
+  int r = guarded(ctx, [&] {
+    if (i < 0 || i >= ctx->ns) fail(TDBEM_E_INVAL, "row out of range");
+    int64_t rp[2];
+    TDBEM_HIP(hipMemcpy(rp, ctx->d_row_ptr.p + i, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
+    const int64_t np = rp[1] - rp[0];
+    std::vector<int32_t> pj(np), gw(np);
+    std::vector<int64_t> off(np);
+    TDBEM_HIP(hipMemcpy(pj.data(), ctx->d_pair_j.p + rp[0], np * sizeof(int32_t), hipMemcpyDeviceToHost));
+    TDBEM_HIP(hipMemcpy(gw.data(), ctx->d_pair_gw.p + rp[0], np * sizeof(int32_t), hipMemcpyDeviceToHost));
+    TDBEM_HIP(hipMemcpy(off.data(), ctx->d_pair_off.p + rp[0], np * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < np; ++p) {
+      const int glo = gw[p] >> 16, cnt = gw[p] & 0xffff;
+      std::vector<double> cu(cnt), cw(cnt);
+      TDBEM_HIP(hipMemcpy(cu.data(), ctx->d_cu.p + off[p], cnt * sizeof(double), hipMemcpyDeviceToHost));
+      TDBEM_HIP(hipMemcpy(cw.data(), ctx->d_cw.p + off[p], cnt * sizeof(double), hipMemcpyDeviceToHost));
+      for (int k = 0; k < cnt; ++k) {
+        if (count < cap) {
+          if (j_out) j_out[count] = pj[p];
+          if (g_out) g_out[count] = glo + k;
+          if (cu_out) cu_out[count] = cu[k];
+          if (cw_out) cw_out[count] = cw[k];
+        }
+        ++count;
+      }
+    }
+  });
+  return r != TDBEM_OK ? r : count;
+}
+
+}  // extern "C"

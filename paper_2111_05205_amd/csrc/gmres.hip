@@ -1,0 +1,208 @@
+// Per-step solve A x = b (eq. linear) by restarted GMRES in FP64.
+//
+// A is sparse (non-zero only for pairs within c*dt of each other) and
+// constant in time; its spectrum is tightly clustered, so GMRES converges in
+// about a dozen iterations.  The whole solve runs in ONE workgroup of 1024
+// threads (16 wavefronts) per step: the Krylov basis lives in global memory
+// (L2-resident for the sizes this kernel serves), the Hessenberg matrix,
+// Givens rotations and reduction scratch in LDS, and no host round trip is
+// needed.  Orthogonalisation is classical Gram-Schmidt applied twice (CGS2),
+// so each Arnoldi step needs two fused multi-dot reductions.
+#include "internal.h"
+
+namespace tdbem {
+
+constexpr int GM_THREADS = 1024;
+constexpr int GM_WAVES = GM_THREADS / 64;
+constexpr int GM_MAXM = 32;
+
+struct GmresShared {
+  double H[GM_MAXM + 1][GM_MAXM];
+  double cs[GM_MAXM], sn[GM_MAXM], g[GM_MAXM + 1], y[GM_MAXM];
+  double red[GM_WAVES][GM_MAXM + 1];
+  double hv[GM_MAXM + 1];
+  double scal[4];
+};
+
+__device__ inline double wave_sum(double v) {
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
+  return v;
+}
+
+// Sum of one value over the block, result broadcast to every thread.
+__device__ inline double block_sum(double v, GmresShared& sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh.red[wid][0] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < GM_WAVES; ++w) s += sh.red[w][0];
+  return s;
+}
+
+// hv[k] = <V_k, w> for k <= j, reduced over the block into sh.hv.
+__device__ inline void multi_dot(int ns, int j, const double* __restrict__ V, const double* __restrict__ w,
+                                 GmresShared& sh) {
+  double part[GM_MAXM];
+#pragma unroll
+  for (int k = 0; k < GM_MAXM; ++k) part[k] = 0.0;
+  for (int i = threadIdx.x; i < ns; i += GM_THREADS) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < GM_MAXM; ++k)
+      if (k <= j) part[k] += V[(size_t)k * ns + i] * wi;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < GM_MAXM; ++k) {
+    if (k <= j) {
+      const double v = wave_sum(part[k]);
+      if (lane == 0) sh.red[wid][k] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double s = 0.0;
+    for (int w2 = 0; w2 < GM_WAVES; ++w2) s += sh.red[w2][threadIdx.x];
+    sh.hv[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+__device__ inline void spmv(int ns, const int32_t* __restrict__ ap, const int32_t* __restrict__ ac,
+                            const double* __restrict__ av, const double* __restrict__ v, double* __restrict__ y) {
+  for (int i = threadIdx.x; i < ns; i += GM_THREADS) {
+    double s = 0.0;
+    for (int k = ap[i]; k < ap[i + 1]; ++k) s += av[k] * v[ac[k]];
+    y[i] = s;
+  }
+}
+
+__global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t* __restrict__ ap,
+                                                            const int32_t* __restrict__ ac,
+                                                            const double* __restrict__ av,
+                                                            const double* __restrict__ b, double* __restrict__ x,
+                                                            double* __restrict__ V, int m, int maxit, double tol,
+                                                            StepStat* __restrict__ stat) {
+  __shared__ GmresShared sh;
+  const int tid = threadIdx.x;
+  double bn2 = 0.0;
+  for (int i = tid; i < ns; i += GM_THREADS) bn2 += b[i] * b[i];
+  const double bnorm = sqrt(block_sum(bn2, sh));
+  int it = 0;
+  double rel = 0.0;
+  int flags = 0;
+  if (!(bnorm > 0.0)) {
+    for (int i = tid; i < ns; i += GM_THREADS) x[i] = 0.0;
+    if (!(bnorm == 0.0)) flags |= 2;
+  } else {
+    const double target = tol * bnorm;
+    for (;;) {
+      // r = b - A x  -> V_0
+      double* V0 = V;
+      spmv(ns, ap, ac, av, x, V0);
+      double rr = 0.0;
+      for (int i = tid; i < ns; i += GM_THREADS) {
+        const double r = b[i] - V0[i];
+        V0[i] = r;
+        rr += r * r;
+      }
+      const double beta = sqrt(block_sum(rr, sh));
+      rel = beta / bnorm;
+      if (!(beta > target) || it >= maxit) {
+        if (!(beta == beta)) flags |= 2;
+        break;
+      }
+      for (int i = tid; i < ns; i += GM_THREADS) V0[i] /= beta;
+      if (tid == 0) {
+        sh.g[0] = beta;
+        for (int k = 1; k <= m; ++k) sh.g[k] = 0.0;
+      }
+      __syncthreads();
+      int jlast = -1;
+      for (int j = 0; j < m; ++j) {
+        double* Vj = V + (size_t)j * ns;
+        double* W = V + (size_t)(j + 1) * ns;
+        spmv(ns, ap, ac, av, Vj, W);
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+          multi_dot(ns, j, V, W, sh);
+          if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
+          for (int i = tid; i < ns; i += GM_THREADS) {
+            double wi = W[i];
+            for (int k = 0; k <= j; ++k) wi -= sh.hv[k] * V[(size_t)k * ns + i];
+            W[i] = wi;
+          }
+          __syncthreads();
+        }
+        double ww = 0.0;
+        for (int i = tid; i < ns; i += GM_THREADS) ww += W[i] * W[i];
+        const double hn = sqrt(block_sum(ww, sh));
+        if (hn > 0.0)
+          for (int i = tid; i < ns; i += GM_THREADS) W[i] /= hn;
+        if (tid == 0) {
+          sh.H[j + 1][j] = hn;
+          for (int k = 0; k < j; ++k) {  // previous rotations
+            const double a = sh.H[k][j], c2 = sh.H[k + 1][j];
+            sh.H[k][j] = sh.cs[k] * a + sh.sn[k] * c2;
+            sh.H[k + 1][j] = -sh.sn[k] * a + sh.cs[k] * c2;
+          }
+          const double a = sh.H[j][j], c2 = sh.H[j + 1][j];
+          const double den = sqrt(a * a + c2 * c2);
+          const double cj = den > 0.0 ? a / den : 1.0, sj = den > 0.0 ? c2 / den : 0.0;
+          sh.cs[j] = cj;
+          sh.sn[j] = sj;
+          sh.H[j][j] = cj * a + sj * c2;
+          sh.H[j + 1][j] = 0.0;
+          sh.g[j + 1] = -sj * sh.g[j];
+          sh.g[j] = cj * sh.g[j];
+          sh.scal[0] = fabs(sh.g[j + 1]);
+          sh.scal[1] = hn;
+        }
+        __syncthreads();
+        ++it;
+        jlast = j;
+        rel = sh.scal[0] / bnorm;
+        if (!(sh.scal[0] > target) || it >= maxit || !(sh.scal[1] > 0.0)) break;
+      }
+      // x += V y with H y = g (upper triangular, size jlast+1)
+      if (tid == 0) {
+        for (int k = jlast; k >= 0; --k) {
+          double s = sh.g[k];
+          for (int l = k + 1; l <= jlast; ++l) s -= sh.H[k][l] * sh.y[l];
+          sh.y[k] = s / sh.H[k][k];
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < ns; i += GM_THREADS) {
+        double xi = x[i];
+        for (int k = 0; k <= jlast; ++k) xi += sh.y[k] * V[(size_t)k * ns + i];
+        x[i] = xi;
+      }
+      __syncthreads();
+      if (!(rel * bnorm > target) || it >= maxit) {
+        if (!(rel == rel)) flags |= 2;
+        break;
+      }
+    }
+    if (rel * bnorm > target) flags |= 1;
+  }
+  if (tid == 0 && stat) {
+    stat->iters = it;
+    stat->resid = rel;
+    stat->flags = flags;
+  }
+}
+
+void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat) {
+  int m = ctx->opts.gmres_restart;
+  if (m > GM_MAXM) m = GM_MAXM;
+  if (m < 1) m = 1;
+  gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, b, x,
+                                                   ctx->d_V.p, m, ctx->opts.gmres_maxiter, ctx->opts.gmres_tol, stat);
+  TDBEM_HIP(hipGetLastError());
+}
+
+}  // namespace tdbem

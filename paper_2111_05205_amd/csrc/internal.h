@@ -1,0 +1,144 @@
+// Internal declarations of the MI355X time-domain BEM library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tdbem.h"
+#include "elemint_gl.h"
+
+#define TDBEM_HIP(call)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      throw tdbem::Error(TDBEM_E_DEVICE, std::string(#call) + ": " +           \
+                                             hipGetErrorString(e_));           \
+    }                                                                          \
+  } while (0)
+
+namespace tdbem {
+
+struct Error {
+  int code;
+  std::string msg;
+  Error(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+// Device buffer owned by a context.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      n = 0;
+      throw Error(TDBEM_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+// Per-step record kept on the device during a march.
+struct StepStat {
+  int iters;
+  int flags;  // bit0: not converged, bit1: non-finite
+  double resid;
+};
+
+struct Fmm;  // space-time FMM state (fmm.hip)
+
+// B-spline weights w^{kappa,d} (eq. w), d <= 4.
+struct BWeights { double w[6]; int d; };
+
+struct Geometry {
+  int ns = 0;
+  std::vector<double> xc;    // ns x 3 collocation points (centroids)
+  std::vector<double> nrm;   // ns x 3 paper normals (into the scatterer)
+  std::vector<double> tris;  // ns x 9 vertex coordinates
+  std::vector<double> area;
+  double edge_max = 0.0, edge_mean = 0.0;
+  double ext_lo[3], ext_hi[3];  // vertex bounding box
+  double e_max = 0.0;           // largest centroid-to-vertex distance
+};
+
+}  // namespace tdbem
+
+struct tdbem_ctx {
+  std::string err;
+  hipStream_t stream = nullptr;
+  int ns = 0, d = 1, bie = 1, bc = 0;
+  double c = 1.0, dt = 1.0, cdt = 1.0;
+  tdbem_opts opts{};
+  tdbem::BWeights bw{};
+  tdbem::Geometry geo;
+  double setup_ms = 0.0;
+
+  // device geometry
+  tdbem::DevBuf<double> d_xc, d_nrm, d_tris;
+
+  // near-field table, CSR by collocation row i
+  int64_t npairs = 0, ncoef = 0;
+  tdbem::DevBuf<int64_t> d_row_ptr;    // ns+1
+  tdbem::DevBuf<int32_t> d_pair_j;     // npairs
+  tdbem::DevBuf<int32_t> d_pair_gw;    // npairs: (glo << 16) | cnt
+  tdbem::DevBuf<int64_t> d_pair_off;   // npairs: first coefficient
+  tdbem::DevBuf<double> d_cu, d_cw;    // ncoef each: compact C_U^{(g)}, C_W^{(g)}
+
+  // per-step matrix A and the g=1 blocks, CSR
+  int64_t a_nnz = 0;
+  tdbem::DevBuf<int32_t> d_a_ptr, d_a_col;
+  tdbem::DevBuf<double> d_a_val, d_u1_val, d_w1_val;
+
+  // history [beta][element], beta = 0..nt_max-2
+  int nt_max = 0;
+  tdbem::DevBuf<double> d_hu, d_hq;
+  int alpha = 1;        // next collocation step
+  bool hist_u = false;  // any non-zero u stored
+  bool hist_q = false;  // any non-zero q stored
+
+  // work
+  tdbem::DevBuf<double> d_b, d_x, d_V, d_forc, d_zero;
+  tdbem::DevBuf<tdbem::StepStat> d_stat;
+
+  tdbem::Fmm* fmm = nullptr;
+};
+
+namespace tdbem {
+
+// nearfield.hip
+void build_near_table(tdbem_ctx* ctx, const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& pair_j);
+void build_step_matrix(tdbem_ctx* ctx);
+void launch_near_history(tdbem_ctx* ctx, int alpha, const double* base, double* out);
+void launch_spmv_add(tdbem_ctx* ctx, const double* vals, double scale, const double* xin, double* y);
+void upload_gl_rule();
+
+// gmres.hip
+void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat);
+
+// api.hip
+void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc, int a0, int n, double* out);
+
+// fmm.hip
+Fmm* fmm_create(tdbem_ctx* ctx);
+void fmm_destroy(Fmm* f);
+void fmm_reset(tdbem_ctx* ctx);
+// add the far field at target step alpha to out (Ns)
+void fmm_far(tdbem_ctx* ctx, int alpha, double* out);
+// the coefficient row beta has been stored: update moments and run interval-end translations
+void fmm_advance(tdbem_ctx* ctx, int beta);
+void fmm_info(const tdbem_ctx* ctx, tdbem_info* info);
+void fmm_near_pairs(const tdbem_ctx* ctx, std::vector<int64_t>& row_ptr, std::vector<int32_t>& pair_j);
+
+}  // namespace tdbem

@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point declared in include/tdbem.h (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tdbem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdbem_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    from paper_2111_05205_amd import _native
+    L = _native.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_invalid_meshes_rejected_before_device_work():
+    import synth
+    from paper_2111_05205_amd import _native as N
+    L = N.lib()
+    xyz, tri = synth.icosphere(1)
+
+    def create(v, f, c=1.0, dt=0.1, d=1):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        f = np.ascontiguousarray(f, dtype=np.int32)
+        m = N.Mesh(v.shape[0], f.shape[0], v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        h = ctypes.c_void_p()
+        rc = L.tdbem_create(ctypes.byref(m), c, dt, d, 1, 0, None, None, ctypes.byref(h))
+        return rc, L.tdbem_last_error(None).decode()
+
+    assert create(xyz, tri[:-1])[0] == N.E_INVAL                      # open surface
+    bad = tri.copy(); bad[0] = bad[0][[0, 2, 1]]
+    assert create(xyz, bad)[0] == N.E_INVAL                           # inconsistent orientation
+    bad = tri.copy(); bad[3, 1] = 10 ** 6
+    assert create(xyz, bad)[0] == N.E_INVAL                           # index out of range
+    assert create(xyz, tri, c=-1.0)[0] == N.E_INVAL
+    assert create(xyz, tri, d=3)[0] == N.E_INVAL
+    assert create(xyz, tri, dt=0.0)[0] == N.E_INVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import importlib
+    from paper_2111_05205_amd import _native
+    monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    try:
+        _native.lib()
+    except RuntimeError as e:
+        assert "missing" in str(e)
+    else:
+        raise AssertionError("expected a RuntimeError")
