@@ -1,16 +1,913 @@
-// Interpolation-based space-time FMM (Section 3, Section 4).
+// Interpolation-based space-time FMM for the far part of the history sum
+// (paper Section 3: eqs. target, U_intp, Uabmn, target_m2l, m2l and the
+// Burton-Miller evaluation of the local field; Section 4: near-future M2L,
+// eq. m2l_near, derivative products, eq. L_l,k, and the O(Nt) recurrence of
+// Formula 1 / Algorithm 1).
+//
+// Space: octree over the vertex bounding box (root half side rounded up to a
+// power of two), faces assigned to leaves by centroid, near field = the 27
+// leaves around a face's leaf, interaction lists on levels 2..depth with 316
+// possible relative offsets.  Time: M_leaf steps per leaf interval (the
+// largest value for which same-interval interaction-list pairs vanish by
+// causality), doubling per level; a source sample tau^{beta} belongs to
+// interval floor((beta+1)/M) (grouped by t_{beta+1} as in eq. target), a
+// target t_alpha to floor(alpha/M); intervals are centred on the times they
+// hold.  Interpolation: tensor Lagrange on Chebyshev points (first kind) in
+// each of the eight variables; P = p_s^3 p_t coefficients per cell.
+//
+// Per sample beta (after the solve of step beta+1):
+//   P2M        leaf moments of the current source interval       (HBM-bound, small)
+//   at the end of a level's source interval k:
+//     M2L      offset-batched dense products: for every interaction pair,
+//              [U_{k+1,k}; ...; U_{k+mu+1,k}; U^{(1)}; ...; U^{(d)}] M_k(S)
+//              written to a per-pair staging buffer                   (dense contraction)
+//     reduce   per target cell: near-future locals L_{k+l} += ..., then the
+//              recurrence of Algorithm 1 (eqs. m2l_expand_rec1, m2l_rec,
+//              m2l_expand_rec2) fused in the same pass                  (HBM-bound)
+//     M2M      child -> parent re-interpolation (parent-centric, no atomics)
+//   L2L        at the start of a parent's target interval, parent -> child
+//   L2P        at each target step: field or Burton-Miller operator of it
 #include "internal.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
 
 namespace tdbem {
 
-struct Fmm {};
+constexpr int MAXP = 8;  // nodes per axis
 
-Fmm* fmm_create(tdbem_ctx*) { throw Error(TDBEM_E_INVAL, "FMM mode is not available in this build"); }
+struct FmmLevel {
+  int ncell = 0;
+  std::vector<std::array<int, 3>> key;      // integer cell coordinates
+  std::vector<int> parent;                  // index in level-1
+  std::vector<int> octant;                  // bit q set: upper half along axis q
+  // interaction pairs sorted by target cell
+  int64_t npair = 0;
+  std::vector<int> il_ptr;                  // ncell+1
+  std::vector<int> il_src, il_slot;         // npair
+  std::vector<std::array<int, 3>> slot_off; // offset vector of each matrix slot present at this level
+  // device
+  DevBuf<int32_t> d_il_ptr, d_il_src, d_parent, d_octant, d_child_ptr, d_child;
+  DevBuf<int32_t> d_tiles;                  // GEMM column tiles: (slot, first, count) triples
+  DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
+  int ntiles = 0;
+  DevBuf<double> d_U;                       // [slot][G*P][P]
+  DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_stage;
+};
+
+struct Fmm {
+  int D = 0, ps = 0, pt = 0, Ps = 0, P = 0, G = 0, mu = 0, R = 0, m_leaf = 1;
+  double H = 0, center[3] = {0, 0, 0}, e_max = 0;
+  double om_s[MAXP], om_t[MAXP];
+  std::vector<FmmLevel> lev;               // 0..D
+  std::vector<int> leaf_of;                // element -> leaf cell
+  std::vector<int> leaf_ptr, leaf_elems;   // leaf -> elements (CSR)
+  DevBuf<int32_t> d_leaf_of, d_leaf_ptr, d_leaf_elems;
+  DevBuf<double> d_A, d_B, d_E0, d_E1;     // P2M / L2P tables, ns x Ps
+  DevBuf<double> d_tau, d_sig;
+  DevBuf<double> d_S, d_T;                 // 1-D re-interpolation matrices [side][parent][child]
+  double Cd = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Host helpers
+
+static void cheb(int p, double* om) {
+  for (int a = 0; a < p; ++a) om[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * p));
+}
+
+static double lag(const double* om, int p, int a, double x) {
+  double v = 1.0;
+  for (int b = 0; b < p; ++b)
+    if (b != a) v *= (x - om[b]) / (om[a] - om[b]);
+  return v;
+}
+
+static double dlag(const double* om, int p, int a, double x) {
+  double s = 0.0;
+  for (int c = 0; c < p; ++c) {
+    if (c == a) continue;
+    double t = 1.0 / (om[a] - om[c]);
+    for (int b = 0; b < p; ++b)
+      if (b != a && b != c) t *= (x - om[b]) / (om[a] - om[b]);
+    s += t;
+  }
+  return s;
+}
+
+static uint64_t morton(int x, int y, int z) {
+  uint64_t m = 0;
+  for (int b = 0; b < 21; ++b) {
+    m |= (uint64_t)((x >> b) & 1) << (3 * b);
+    m |= (uint64_t)((y >> b) & 1) << (3 * b + 1);
+    m |= (uint64_t)((z >> b) & 1) << (3 * b + 2);
+  }
+  return m;
+}
+
+static int64_t key64(int x, int y, int z) { return ((int64_t)x << 42) | ((int64_t)y << 21) | (int64_t)z; }
+
+static double hs_of(const Fmm* f, int l) { return f->H / (double)(1 << l); }
+
+// ---------------------------------------------------------------------------
+// Device kernels
+
+struct NodeSet { double s[MAXP], t[MAXP]; };
+
+// U[slot][g*P + row][col] for one level.  row = a1 + ps(a2 + ps(a3 + ps m)), col likewise (b, n).
+__global__ void m2l_matrix_kernel(int ps, int pt, int P, int G, int mu, int d, double c, double hs, double ht,
+                                  double dt, int Ml, NodeSet nodes, const int32_t* __restrict__ slot_off,
+                                  double* __restrict__ U) {
+  const int slot = blockIdx.z;
+  const int g = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)P * P) return;
+  const int row = (int)(idx / P), col = (int)(idx % P);
+  const int Ps = ps * ps * ps;
+  const int a = row % Ps, m = row / Ps, b = col % Ps, n = col / Ps;
+  const int a1 = a % ps, a2 = (a / ps) % ps, a3 = a / (ps * ps);
+  const int b1 = b % ps, b2 = (b / ps) % ps, b3 = b / (ps * ps);
+  const int ox = slot_off[3 * slot], oy = slot_off[3 * slot + 1], oz = slot_off[3 * slot + 2];
+  // y - x between source node b of cell O+o and target node a of cell O
+  const double dx = 2.0 * hs * ox + hs * (nodes.s[b1] - nodes.s[a1]);
+  const double dy = 2.0 * hs * oy + hs * (nodes.s[b2] - nodes.s[a2]);
+  const double dz = 2.0 * hs * oz + hs * (nodes.s[b3] - nodes.s[a3]);
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double val;
+  if (g <= mu) {  // near future, target interval k + (g+1)
+    const double tds = ((g + 1) * (double)Ml + 1.0) * dt + ht * (nodes.t[m] - nodes.t[n]);
+    double arg = c * tds - r;
+    if (arg < 0.0) arg = 0.0;
+    val = ipow(arg, d) / r;
+  } else {        // derivative p of eq. U_expand at the expansion interval k + mu + 1
+    const int p = g - mu;
+    const double tds = ((mu + 1) * (double)Ml + 1.0) * dt + ht * (nodes.t[m] - nodes.t[n]);
+    const double arg = c * tds - r;
+    double bin = 1.0;
+    for (int q = 0; q < p; ++q) bin = bin * (d - q) / (q + 1);
+    val = bin * ipow(arg, d - p) / r;
+  }
+  U[((int64_t)slot * G + g) * P * P + idx] = val;
+}
+
+// P2M / L2P element tables on the device.  Triangle quadrature: collapsed
+// (Duffy) tensor Gauss-Legendre with nq points per direction, exact for the
+// polynomial degree 3(p_s-1) of the tensor basis.
+struct QuadRule { double x[16]; double w[16]; int n; };
+
+__global__ void elem_tables_kernel(int ns, int ps, double hs, NodeSet nodes, QuadRule q,
+                                   const double* __restrict__ tris, const double* __restrict__ nrm,
+                                   const double* __restrict__ xc, const double* __restrict__ cell_center,
+                                   const int32_t* __restrict__ leaf_of, double* __restrict__ A,
+                                   double* __restrict__ B, double* __restrict__ E0, double* __restrict__ E1) {
+  const int e = blockIdx.x;
+  const int Ps = ps * ps * ps;
+  const int b = threadIdx.x;
+  if (b >= Ps) return;
+  const int b1 = b % ps, b2 = (b / ps) % ps, b3 = b / (ps * ps);
+  const double* V = tris + 9 * (int64_t)e;
+  const double* cc = cell_center + 3 * (int64_t)leaf_of[e];
+  const double* n = nrm + 3 * (int64_t)e;
+  double e1[3] = {V[3] - V[0], V[4] - V[1], V[5] - V[2]};
+  double e2[3] = {V[6] - V[3], V[7] - V[4], V[8] - V[5]};
+  double cr[3];
+  cross3(e1, e2, cr);
+  const double area2 = sqrt(dot3(cr, cr));
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < q.n; ++i) {
+    const double u = q.x[i];
+    for (int j = 0; j < q.n; ++j) {
+      const double v = q.x[j];
+      const double w = q.w[i] * q.w[j] * u * area2;
+      double xi[3];
+      for (int k = 0; k < 3; ++k) xi[k] = (V[k] + u * e1[k] + u * v * e2[k] - cc[k]) / hs;
+      double l[3], dl[3];
+      const int bb[3] = {b1, b2, b3};
+      for (int k = 0; k < 3; ++k) {
+        double val = 1.0, der = 0.0;
+        for (int o = 0; o < ps; ++o) {
+          if (o == bb[k]) continue;
+          const double f = 1.0 / (nodes.s[bb[k]] - nodes.s[o]);
+          der = der * (xi[k] - nodes.s[o]) * f + val * f;
+          val *= (xi[k] - nodes.s[o]) * f;
+        }
+        l[k] = val;
+        dl[k] = der;
+      }
+      sa += w * l[0] * l[1] * l[2];
+      sb += w * (n[0] * dl[0] * l[1] * l[2] + n[1] * l[0] * dl[1] * l[2] + n[2] * l[0] * l[1] * dl[2]);
+    }
+  }
+  A[(int64_t)e * Ps + b] = sa;
+  B[(int64_t)e * Ps + b] = sb / hs;
+  // L2P: basis and its normal derivative at the collocation point
+  double xi[3], l[3], dl[3];
+  const int bb[3] = {b1, b2, b3};
+  for (int k = 0; k < 3; ++k) {
+    xi[k] = (xc[3 * (int64_t)e + k] - cc[k]) / hs;
+    double val = 1.0, der = 0.0;
+    for (int o = 0; o < ps; ++o) {
+      if (o == bb[k]) continue;
+      const double f = 1.0 / (nodes.s[bb[k]] - nodes.s[o]);
+      der = der * (xi[k] - nodes.s[o]) * f + val * f;
+      val *= (xi[k] - nodes.s[o]) * f;
+    }
+    l[k] = val;
+    dl[k] = der;
+  }
+  E0[(int64_t)e * Ps + b] = l[0] * l[1] * l[2];
+  E1[(int64_t)e * Ps + b] = (n[0] * dl[0] * l[1] * l[2] + n[1] * l[0] * dl[1] * l[2] + n[2] * l[0] * l[1] * dl[2]) / hs;
+}
+
+// tau^beta and sigma^beta (eqs. tau, sigma, full kappa sum).
+__global__ void densities_kernel(int ns, int beta, int d, BWeights bw, const double* __restrict__ hu,
+                                 const double* __restrict__ hq, int use_u, int use_q, double* __restrict__ tau,
+                                 double* __restrict__ sig) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  double t = 0.0, s = 0.0;
+  const int kmax = min(d + 1, beta);
+  for (int k = 0; k <= kmax; ++k) {
+    const int64_t r = (int64_t)(beta - k) * ns + i;
+    if (use_q) t += bw.w[k] * hq[r];
+    if (use_u) s += bw.w[k] * hu[r];
+  }
+  tau[i] = t;
+  sig[i] = s;
+}
+
+struct TimeWeights { double w[MAXP]; double dw[MAXP]; };
+
+// P2M of one sample into the leaf moments: one block per leaf, thread per spatial node.
+__global__ void p2m_kernel(int Ps, int pt, double Cd, TimeWeights tw, const int32_t* __restrict__ leaf_ptr,
+                           const int32_t* __restrict__ leaf_elems, const double* __restrict__ A,
+                           const double* __restrict__ B, const double* __restrict__ tau,
+                           const double* __restrict__ sig, double* __restrict__ mom) {
+  const int S = blockIdx.x;
+  const int P = Ps * pt;
+  for (int b = threadIdx.x; b < Ps; b += blockDim.x) {
+    double acc = 0.0;
+    for (int k = leaf_ptr[S]; k < leaf_ptr[S + 1]; ++k) {
+      const int e = leaf_elems[k];
+      acc += A[(int64_t)e * Ps + b] * tau[e] - B[(int64_t)e * Ps + b] * sig[e];
+    }
+    acc *= Cd;
+    for (int n = 0; n < pt; ++n) mom[(int64_t)S * P + b + Ps * n] += acc * tw.w[n];
+  }
+}
+
+// Apply the separable re-interpolation to one P-vector held in LDS:
+// along axis 0 (x), 1 (y), 2 (z) with ps x ps matrices and along time with pt x pt.
+// Mx[q][i][j]: output index i, input index j.  Works in place between buf0/buf1; returns the buffer holding the result.
+__device__ double* apply_sep(double* buf0, double* buf1, int ps, int pt, const double* Mx, const double* My,
+                             const double* Mz, const double* Mt) {
+  const int Ps = ps * ps * ps, P = Ps * pt;
+  double* in = buf0;
+  double* out = buf1;
+  for (int ax = 0; ax < 4; ++ax) {
+    const double* Mm = ax == 0 ? Mx : ax == 1 ? My : ax == 2 ? Mz : Mt;
+    const int len = ax < 3 ? ps : pt;
+    const int stride = ax == 0 ? 1 : ax == 1 ? ps : ax == 2 ? ps * ps : Ps;
+    for (int idx = threadIdx.x; idx < P; idx += blockDim.x) {
+      const int i = (idx / stride) % len;
+      const int base = idx - i * stride;
+      double s = 0.0;
+      for (int j = 0; j < len; ++j) s += Mm[i * len + j] * in[base + j * stride];
+      out[idx] = s;
+    }
+    __syncthreads();
+    double* t = in; in = out; out = t;
+  }
+  return in;
+}
+
+// M2M: one block per parent cell; sums its children's re-interpolated moments.
+// S[side][parent a][child b] (side 0: lower half, 1: upper), T likewise for time.
+__global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__ child_ptr,
+                           const int32_t* __restrict__ child, const int32_t* __restrict__ octant,
+                           const double* __restrict__ S, const double* __restrict__ T,
+                           const double* __restrict__ mom_c, double* __restrict__ mom_p) {
+  extern __shared__ double sm[];
+  const int Ps = ps * ps * ps, P = Ps * pt;
+  double* b0 = sm;
+  double* b1 = sm + P;
+  const int p = blockIdx.x;
+  double acc[4] = {0, 0, 0, 0};
+  const int per = (P + blockDim.x - 1) / blockDim.x;
+  for (int k = child_ptr[p]; k < child_ptr[p + 1]; ++k) {
+    const int cidx = child[k];
+    const int oc = octant[cidx];
+    for (int idx = threadIdx.x; idx < P; idx += blockDim.x) b0[idx] = mom_c[(int64_t)cidx * P + idx];
+    __syncthreads();
+    const double* Mx = S + (oc & 1) * ps * ps;
+    const double* My = S + ((oc >> 1) & 1) * ps * ps;
+    const double* Mz = S + ((oc >> 2) & 1) * ps * ps;
+    const double* Mt = T + half * pt * pt;
+    double* res = apply_sep(b0, b1, ps, pt, Mx, My, Mz, Mt);
+    for (int q = 0; q < per; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < P) acc[q] += res[idx];
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < per; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < P) mom_p[(int64_t)p * P + idx] += acc[q];
+  }
+}
+
+// L2L: one block per child cell; adds the parent's local of interval kp into the
+// child's intervals 2kp and 2kp+1.  St/Tt: transposed matrices [side][child a][parent a'].
+__global__ void l2l_kernel(int ps, int pt, int R, int kp, const int32_t* __restrict__ parent,
+                           const int32_t* __restrict__ octant, const double* __restrict__ St,
+                           const double* __restrict__ Tt, const double* __restrict__ ring_p, int ncell_p,
+                           double* __restrict__ ring_c, int ncell_c) {
+  extern __shared__ double sm[];
+  const int Ps = ps * ps * ps, P = Ps * pt;
+  double* b0 = sm;
+  double* b1 = sm + P;
+  const int c = blockIdx.x;
+  const int oc = octant[c];
+  const double* src = ring_p + ((int64_t)(kp % R) * ncell_p + parent[c]) * P;
+  for (int half = 0; half < 2; ++half) {
+    for (int idx = threadIdx.x; idx < P; idx += blockDim.x) b0[idx] = src[idx];
+    __syncthreads();
+    const double* Mx = St + (oc & 1) * ps * ps;
+    const double* My = St + ((oc >> 1) & 1) * ps * ps;
+    const double* Mz = St + ((oc >> 2) & 1) * ps * ps;
+    const double* Mt = Tt + half * pt * pt;
+    double* res = apply_sep(b0, b1, ps, pt, Mx, My, Mz, Mt);
+    const int kc = 2 * kp + half;
+    double* dst = ring_c + ((int64_t)(kc % R) * ncell_c + c) * P;
+    for (int idx = threadIdx.x; idx < P; idx += blockDim.x) dst[idx] += res[idx];
+    __syncthreads();
+  }
+}
+
+// M2L products, plain LDS-tiled FP64 GEMM: for each tile (slot, first pair, count)
+// stage[pair][row] = sum_col U[slot][row][col] * mom[src(pair)][col], rows = G*P.
+constexpr int GB_M = 64, GB_N = 32, GB_K = 16;
+
+__global__ __launch_bounds__(256) void m2l_gemm_kernel(int P, int GP, const int32_t* __restrict__ tiles,
+                                                       const int32_t* __restrict__ pairs_by_slot,
+                                                       const int32_t* __restrict__ il_src,
+                                                       const double* __restrict__ U, const double* __restrict__ mom,
+                                                       double* __restrict__ stage) {
+  __shared__ double As[GB_K][GB_M + 1];
+  __shared__ double Bs[GB_K][GB_N + 1];
+  __shared__ int src[GB_N], pid[GB_N];
+  const int slot = tiles[3 * blockIdx.x], first = tiles[3 * blockIdx.x + 1], cnt = tiles[3 * blockIdx.x + 2];
+  const int row0 = blockIdx.y * GB_M;
+  const int tid = threadIdx.x;
+  if (tid < GB_N) {
+    const int p = tid < cnt ? pairs_by_slot[first + tid] : -1;
+    pid[tid] = p;
+    src[tid] = p >= 0 ? il_src[p] : -1;
+  }
+  __syncthreads();
+  const double* Us = U + (int64_t)slot * GP * P;
+  const int tr = tid / 8, tc = tid % 8;  // 32 x 8 threads: rows tr*2.., cols tc*4..
+  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int k0 = 0; k0 < P; k0 += GB_K) {
+    for (int e = tid; e < GB_M * GB_K; e += 256) {
+      const int r = e / GB_K, kk = e % GB_K;
+      const int row = row0 + r, col = k0 + kk;
+      As[kk][r] = (row < GP && col < P) ? Us[(int64_t)row * P + col] : 0.0;
+    }
+    for (int e = tid; e < GB_N * GB_K; e += 256) {
+      const int cc = e / GB_K, kk = e % GB_K;
+      const int col = k0 + kk;
+      Bs[kk][cc] = (src[cc] >= 0 && col < P) ? mom[(int64_t)src[cc] * P + col] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < GB_K; ++kk) {
+      const double a0 = As[kk][tr * 2], a1 = As[kk][tr * 2 + 1];
+      for (int j = 0; j < 4; ++j) {
+        const double bv = Bs[kk][tc * 4 + j];
+        acc[0][j] += a0 * bv;
+        acc[1][j] += a1 * bv;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i) {
+    const int row = row0 + tr * 2 + i;
+    if (row >= GP) continue;
+    for (int j = 0; j < 4; ++j) {
+      const int cc = tc * 4 + j;
+      if (pid[cc] >= 0) stage[(int64_t)pid[cc] * GP + row] = acc[i][j];
+    }
+  }
+}
+
+// Reduce the staged products per target cell and run the recurrence of Algorithm 1.
+// grid: (ncell, ceil(P/256)); thread per coefficient index a of the cell.
+__global__ void m2l_reduce_kernel(int P, int G, int mu, int d, int R, int k, double T,
+                                  const int32_t* __restrict__ il_ptr, const double* __restrict__ stage,
+                                  int ncell, double* __restrict__ ring, double* __restrict__ lp,
+                                  double* __restrict__ aux) {
+  const int O = blockIdx.x;
+  const int a = blockIdx.y * blockDim.x + threadIdx.x;
+  if (a >= P) return;
+  const int GP = G * P;
+  const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
+  // near future: L_{k+l} += sum over the cell's pairs
+  for (int l = 1; l <= mu + 1; ++l) {
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) s += stage[(int64_t)p * GP + (l - 1) * P + a];
+    ring[((int64_t)((k + l) % R) * ncell + O) * P + a] += s;
+  }
+  double Dp[4] = {0, 0, 0, 0};
+  for (int q = 1; q <= d; ++q) {
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) s += stage[(int64_t)p * GP + (mu + q) * P + a];
+    Dp[q] = s;
+  }
+  // eq. m2l_expand_rec1 (uses auxiliaries of k-1), eq. m2l_rec, eq. m2l_expand_rec2
+  const int64_t cell = (int64_t)O * P + a;
+  const int64_t stride = (int64_t)ncell * P;
+  double Lnew[4] = {0, 0, 0, 0};
+  for (int q = 1; q <= d; ++q) {
+    double v = lp[(q - 1) * stride + cell] + Dp[q];
+    if (q == 2) v += 2.0 * aux[cell];  // c_0^2(k) = 2
+    Lnew[q] = v;
+    lp[(q - 1) * stride + cell] = v;
+  }
+  double next = ring[((int64_t)((k + mu + 1) % R) * ncell + O) * P + a];
+  double Tp = 1.0;
+  for (int q = 1; q <= d; ++q) { Tp *= T; next += Lnew[q] * Tp; }
+  ring[((int64_t)((k + mu + 2) % R) * ncell + O) * P + a] = next;
+  if (d >= 2) aux[cell] += Dp[2];  // m = 0: k^0 = 1
+}
+
+// L2P: far field at (x_i, t_alpha) from the leaf local of the current interval.
+__global__ void l2p_kernel(int ns, int Ps, int pt, int bie, double inv_c, TimeWeights tw,
+                           const int32_t* __restrict__ leaf_of, const double* __restrict__ E0,
+                           const double* __restrict__ E1, const double* __restrict__ L, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int P = Ps * pt;
+  const double* Lc = L + (int64_t)leaf_of[i] * P;
+  double s = 0.0;
+  for (int a = 0; a < Ps; ++a) {
+    double lw = 0.0, ldw = 0.0;
+    for (int m = 0; m < pt; ++m) {
+      const double v = Lc[a + Ps * m];
+      lw += v * tw.w[m];
+      ldw += v * tw.dw[m];
+    }
+    if (bie) s += E1[(int64_t)i * Ps + a] * lw - inv_c * E0[(int64_t)i * Ps + a] * ldw;
+    else s += E0[(int64_t)i * Ps + a] * lw;
+  }
+  out[i] += s;
+}
+
+// ---------------------------------------------------------------------------
+// Set-up
+
+static void build_tree(tdbem_ctx* ctx, Fmm* f) {
+  const Geometry& g = ctx->geo;
+  const int ns = g.ns, D = f->D;
+  double ext = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    f->center[k] = 0.5 * (g.ext_lo[k] + g.ext_hi[k]);
+    ext = std::max(ext, 0.5 * (g.ext_hi[k] - g.ext_lo[k]));
+  }
+  if (!(ext > 0.0)) throw Error(TDBEM_E_INVAL, "degenerate mesh extent");
+  f->H = std::pow(2.0, std::ceil(std::log2(ext)));
+  f->e_max = g.e_max;
+  const int n = 1 << D;
+  std::vector<std::array<int, 3>> li(ns);
+  for (int e = 0; e < ns; ++e)
+    for (int k = 0; k < 3; ++k) {
+      int v = (int)std::floor((g.xc[3 * e + k] - (f->center[k] - f->H)) / (2.0 * f->H) * n);
+      li[e][k] = std::min(std::max(v, 0), n - 1);
+    }
+  f->lev.assign(D + 1, FmmLevel());
+  std::vector<std::vector<int>> cell_of(D + 1, std::vector<int>(ns));
+  for (int l = 0; l <= D; ++l) {
+    FmmLevel& L = f->lev[l];
+    std::vector<std::pair<uint64_t, std::array<int, 3>>> ks;
+    ks.reserve(ns);
+    for (int e = 0; e < ns; ++e) {
+      std::array<int, 3> k3 = {li[e][0] >> (D - l), li[e][1] >> (D - l), li[e][2] >> (D - l)};
+      ks.push_back({morton(k3[0], k3[1], k3[2]), k3});
+    }
+    std::sort(ks.begin(), ks.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    ks.erase(std::unique(ks.begin(), ks.end(), [](const auto& a, const auto& b) { return a.first == b.first; }),
+             ks.end());
+    L.ncell = (int)ks.size();
+    std::unordered_map<int64_t, int> pos;
+    for (int i = 0; i < L.ncell; ++i) {
+      L.key.push_back(ks[i].second);
+      pos[key64(ks[i].second[0], ks[i].second[1], ks[i].second[2])] = i;
+    }
+    for (int e = 0; e < ns; ++e)
+      cell_of[l][e] = pos[key64(li[e][0] >> (D - l), li[e][1] >> (D - l), li[e][2] >> (D - l))];
+    if (l >= 1) {
+      std::unordered_map<int64_t, int> ppos;
+      const FmmLevel& Pl = f->lev[l - 1];
+      for (int i = 0; i < Pl.ncell; ++i) ppos[key64(Pl.key[i][0], Pl.key[i][1], Pl.key[i][2])] = i;
+      L.parent.resize(L.ncell);
+      L.octant.resize(L.ncell);
+      for (int i = 0; i < L.ncell; ++i) {
+        const auto& k = L.key[i];
+        L.parent[i] = ppos[key64(k[0] >> 1, k[1] >> 1, k[2] >> 1)];
+        L.octant[i] = (k[0] & 1) | ((k[1] & 1) << 1) | ((k[2] & 1) << 2);
+      }
+    }
+    // interaction lists
+    if (l >= 2) {
+      std::unordered_map<int64_t, int> slot_of;
+      L.il_ptr.assign(L.ncell + 1, 0);
+      for (int O = 0; O < L.ncell; ++O) {
+        const auto& k = L.key[O];
+        const int px = k[0] >> 1, py = k[1] >> 1, pz = k[2] >> 1;
+        for (int dx = -1; dx <= 1; ++dx)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int cx = 0; cx < 2; ++cx)
+                for (int cy = 0; cy < 2; ++cy)
+                  for (int cz = 0; cz < 2; ++cz) {
+                    const int sx = 2 * (px + dx) + cx, sy = 2 * (py + dy) + cy, sz = 2 * (pz + dz) + cz;
+                    const int ox = sx - k[0], oy = sy - k[1], oz = sz - k[2];
+                    if (std::max({std::abs(ox), std::abs(oy), std::abs(oz)}) <= 1) continue;
+                    auto it = pos.find(key64(sx, sy, sz));
+                    if (sx < 0 || sy < 0 || sz < 0 || it == pos.end()) continue;
+                    const int64_t ok = key64(ox + 8, oy + 8, oz + 8);
+                    auto st = slot_of.find(ok);
+                    int slot;
+                    if (st == slot_of.end()) {
+                      slot = (int)L.slot_off.size();
+                      slot_of[ok] = slot;
+                      L.slot_off.push_back({ox, oy, oz});
+                    } else {
+                      slot = st->second;
+                    }
+                    L.il_src.push_back(it->second);
+                    L.il_slot.push_back(slot);
+                  }
+        L.il_ptr[O + 1] = (int)L.il_src.size();
+      }
+      L.npair = (int64_t)L.il_src.size();
+    }
+  }
+  // leaf membership
+  f->leaf_of = cell_of[D];
+  const int nl = f->lev[D].ncell;
+  f->leaf_ptr.assign(nl + 1, 0);
+  for (int e = 0; e < ns; ++e) f->leaf_ptr[f->leaf_of[e] + 1]++;
+  for (int i = 0; i < nl; ++i) f->leaf_ptr[i + 1] += f->leaf_ptr[i];
+  f->leaf_elems.resize(ns);
+  std::vector<int> fill(f->leaf_ptr.begin(), f->leaf_ptr.end() - 1);
+  for (int e = 0; e < ns; ++e) f->leaf_elems[fill[f->leaf_of[e]]++] = e;
+}
+
+static void build_hierarchy(tdbem_ctx* ctx, Fmm* f) {
+  const double cdt = ctx->cdt;
+  const int m_leaf = (int)std::floor((2.0 * hs_of(f, f->D) - f->e_max) / cdt);
+  if (m_leaf < 1)
+    throw Error(TDBEM_E_INVAL, "octree too deep for this time step: leaves must be wider than c*dt plus the "
+                               "largest centroid-to-vertex distance");
+  f->m_leaf = m_leaf;
+  // smallest mu with c (t - s) - r > 0 for every node pair of interval k+mu+1, every level and offset
+  int need = 1;
+  for (int l = 2; l <= f->D; ++l) {
+    const double hs = hs_of(f, l), Ml = (double)m_leaf * (1 << (f->D - l)), ht = Ml * ctx->dt / 2.0;
+    double smin = 1e300, smax = -1e300, tmin = 1e300;
+    for (int a = 0; a < f->ps; ++a) { smin = std::min(smin, f->om_s[a]); smax = std::max(smax, f->om_s[a]); }
+    for (int m = 0; m < f->pt; ++m)
+      for (int n = 0; n < f->pt; ++n) tmin = std::min(tmin, f->om_t[m] - f->om_t[n]);
+    // largest node distance over all 316 offsets: offset 3 per axis, node spread (smax - smin)
+    const double ax = 6.0 * hs + hs * (smax - smin);
+    const double rmax = std::sqrt(3.0) * ax;
+    int m = 1;
+    while (ctx->c * (((m + 1) * Ml + 1.0) * ctx->dt + ht * tmin) - rmax <= 0.0) ++m;
+    need = std::max(need, m);
+  }
+  if (ctx->opts.mu > 0 && ctx->opts.mu < need)
+    throw Error(TDBEM_E_INVAL, "mu too small for this hierarchy (need " + std::to_string(need) + ")");
+  f->mu = ctx->opts.mu > 0 ? ctx->opts.mu : need;
+  f->G = f->mu + 1 + ctx->d;
+  f->R = f->mu + 3;
+}
+
+static QuadRule gauss_legendre01(int n) {
+  QuadRule q;
+  q.n = n;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    q.x[i] = 0.5 * (x + 1.0);
+    q.w[i] = 0.5 * 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return q;
+}
+
+template <class T>
+static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
+  buf.alloc(v.size());
+  if (!v.empty()) TDBEM_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+Fmm* fmm_create(tdbem_ctx* ctx) {
+  const tdbem_opts& o = ctx->opts;
+  if (o.depth < 2 || o.depth > 12) throw Error(TDBEM_E_INVAL, "depth must be in [2, 12]");
+  if (o.p_s < 2 || o.p_s > MAXP || o.p_t < 2 || o.p_t > MAXP)
+    throw Error(TDBEM_E_INVAL, "p_s and p_t must be in [2, 8]");
+  if (o.p_t <= ctx->d) throw Error(TDBEM_E_INVAL, "p_t must exceed the B-spline order d");
+  if (o.m2l_prec != TDBEM_M2L_FP64) throw Error(TDBEM_E_INVAL, "only FP64 M2L is available in this build");
+  Fmm* f = new Fmm();
+  try {
+    f->D = o.depth;
+    f->ps = o.p_s;
+    f->pt = o.p_t;
+    f->Ps = f->ps * f->ps * f->ps;
+    f->P = f->Ps * f->pt;
+    cheb(f->ps, f->om_s);
+    cheb(f->pt, f->om_t);
+    f->Cd = 1.0 / (4.0 * M_PI * std::pow(ctx->cdt, ctx->d));
+    build_tree(ctx, f);
+    build_hierarchy(ctx, f);
+    hipStream_t st = ctx->stream;
+    const int ns = ctx->ns, P = f->P, G = f->G;
+    NodeSet nodes{};
+    for (int a = 0; a < f->ps; ++a) nodes.s[a] = f->om_s[a];
+    for (int a = 0; a < f->pt; ++a) nodes.t[a] = f->om_t[a];
+    // element tables
+    const FmmLevel& LL = f->lev[f->D];
+    std::vector<double> cc(3 * (size_t)LL.ncell);
+    const double hsl = hs_of(f, f->D);
+    for (int i = 0; i < LL.ncell; ++i)
+      for (int k = 0; k < 3; ++k) cc[3 * i + k] = f->center[k] - f->H + (LL.key[i][k] + 0.5) * 2.0 * hsl;
+    DevBuf<double> d_cc;
+    upload(d_cc, cc, st);
+    std::vector<int32_t> leaf_of(f->leaf_of.begin(), f->leaf_of.end());
+    std::vector<int32_t> leaf_ptr(f->leaf_ptr.begin(), f->leaf_ptr.end());
+    std::vector<int32_t> leaf_elems(f->leaf_elems.begin(), f->leaf_elems.end());
+    upload(f->d_leaf_of, leaf_of, st);
+    upload(f->d_leaf_ptr, leaf_ptr, st);
+    upload(f->d_leaf_elems, leaf_elems, st);
+    f->d_A.alloc((size_t)ns * f->Ps);
+    f->d_B.alloc((size_t)ns * f->Ps);
+    f->d_E0.alloc((size_t)ns * f->Ps);
+    f->d_E1.alloc((size_t)ns * f->Ps);
+    const int nq = std::max(4, (3 * (f->ps - 1) + 3) / 2);
+    QuadRule q = gauss_legendre01(nq);
+    elem_tables_kernel<<<ns, ((f->Ps + 63) / 64) * 64, 0, st>>>(ns, f->ps, hsl, nodes, q, ctx->d_tris.p,
+                                                                  ctx->d_nrm.p, ctx->d_xc.p, d_cc.p, f->d_leaf_of.p,
+                                                                  f->d_A.p, f->d_B.p, f->d_E0.p, f->d_E1.p);
+    TDBEM_HIP(hipGetLastError());
+    f->d_tau.alloc(ns);
+    f->d_sig.alloc(ns);
+    // re-interpolation matrices: S[side][parent a][child b] = l_a(side/2 + om_b/2), side 0 -> -1
+    std::vector<double> S(2 * f->ps * f->ps), T(2 * f->pt * f->pt), St(S.size()), Tt(T.size());
+    for (int sd = 0; sd < 2; ++sd) {
+      const double sgn = sd ? 1.0 : -1.0;
+      for (int a = 0; a < f->ps; ++a)
+        for (int b = 0; b < f->ps; ++b) {
+          const double v = lag(f->om_s, f->ps, a, 0.5 * sgn + 0.5 * f->om_s[b]);
+          S[sd * f->ps * f->ps + a * f->ps + b] = v;
+          St[sd * f->ps * f->ps + b * f->ps + a] = v;
+        }
+      for (int a = 0; a < f->pt; ++a)
+        for (int b = 0; b < f->pt; ++b) {
+          const double v = lag(f->om_t, f->pt, a, 0.5 * sgn + 0.5 * f->om_t[b]);
+          T[sd * f->pt * f->pt + a * f->pt + b] = v;
+          Tt[sd * f->pt * f->pt + b * f->pt + a] = v;
+        }
+    }
+    std::vector<double> ST(S);
+    ST.insert(ST.end(), T.begin(), T.end());
+    ST.insert(ST.end(), St.begin(), St.end());
+    ST.insert(ST.end(), Tt.begin(), Tt.end());
+    upload(f->d_S, ST, st);
+    // per-level device data
+    for (int l = 1; l <= f->D; ++l) {
+      FmmLevel& L = f->lev[l];
+      std::vector<int32_t> par(L.parent.begin(), L.parent.end()), oc(L.octant.begin(), L.octant.end());
+      upload(L.d_parent, par, st);
+      upload(L.d_octant, oc, st);
+    }
+    for (int l = 1; l < f->D; ++l) {  // children CSR of level l cells (from level l+1)
+      FmmLevel& L = f->lev[l];
+      const FmmLevel& C = f->lev[l + 1];
+      std::vector<int32_t> ptr(L.ncell + 1, 0), ch(C.ncell);
+      for (int c = 0; c < C.ncell; ++c) ptr[C.parent[c] + 1]++;
+      for (int i = 0; i < L.ncell; ++i) ptr[i + 1] += ptr[i];
+      std::vector<int32_t> fl(ptr.begin(), ptr.end() - 1);
+      for (int c = 0; c < C.ncell; ++c) ch[fl[C.parent[c]]++] = c;
+      upload(L.d_child_ptr, ptr, st);
+      upload(L.d_child, ch, st);
+    }
+    for (int l = 2; l <= f->D; ++l) {
+      FmmLevel& L = f->lev[l];
+      std::vector<int32_t> ilp(L.il_ptr.begin(), L.il_ptr.end()), ils(L.il_src.begin(), L.il_src.end());
+      upload(L.d_il_ptr, ilp, st);
+      upload(L.d_il_src, ils, st);
+      const int nslot = (int)L.slot_off.size();
+      std::vector<std::vector<int32_t>> by(nslot);
+      for (int64_t p = 0; p < L.npair; ++p) by[L.il_slot[p]].push_back((int32_t)p);
+      std::vector<int32_t> flat, tiles;
+      for (int sl = 0; sl < nslot; ++sl) {
+        const int first = (int)flat.size();
+        flat.insert(flat.end(), by[sl].begin(), by[sl].end());
+        for (int s0 = 0; s0 < (int)by[sl].size(); s0 += GB_N) {
+          tiles.push_back(sl);
+          tiles.push_back(first + s0);
+          tiles.push_back(std::min(GB_N, (int)by[sl].size() - s0));
+        }
+      }
+      L.ntiles = (int)tiles.size() / 3;
+      upload(L.d_pairs_by_slot, flat, st);
+      upload(L.d_tiles, tiles, st);
+      std::vector<int32_t> so;
+      for (auto& v : L.slot_off) { so.push_back(v[0]); so.push_back(v[1]); so.push_back(v[2]); }
+      DevBuf<int32_t> d_so;
+      upload(d_so, so, st);
+      L.d_U.alloc((size_t)std::max(nslot, 1) * G * P * P);
+      if (nslot > 0) {
+        const double Ml = (double)f->m_leaf * (1 << (f->D - l));
+        dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, nslot);
+        m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, ctx->c, hs_of(f, l),
+                                                Ml * ctx->dt / 2.0, ctx->dt, (int)Ml, nodes, d_so.p, L.d_U.p);
+        TDBEM_HIP(hipGetLastError());
+      }
+      L.d_mom.alloc((size_t)L.ncell * P);
+      L.d_ring.alloc((size_t)f->R * L.ncell * P);
+      L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
+      L.d_aux.alloc((size_t)std::max(1, ctx->d - 1) * L.ncell * P);
+      L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+      for (DevBuf<double>* b : {&L.d_mom, &L.d_ring, &L.d_lp, &L.d_aux})
+        TDBEM_HIP(hipMemsetAsync(b->p, 0, b->n * sizeof(double), st));
+      TDBEM_HIP(hipStreamSynchronize(st));  // temporaries (d_so) are released at scope end
+    }
+    TDBEM_HIP(hipStreamSynchronize(st));
+    return f;
+  } catch (...) {
+    delete f;
+    throw;
+  }
+}
+
 void fmm_destroy(Fmm* f) { delete f; }
-void fmm_reset(tdbem_ctx*) {}
-void fmm_far(tdbem_ctx*, int, double*) {}
-void fmm_advance(tdbem_ctx*, int) {}
-void fmm_info(const tdbem_ctx*, tdbem_info*) {}
-void fmm_near_pairs(const tdbem_ctx*, std::vector<int64_t>&, std::vector<int32_t>&) {}
+
+void fmm_reset(tdbem_ctx* ctx) {
+  Fmm* f = ctx->fmm;
+  for (int l = 2; l <= f->D; ++l) {
+    FmmLevel& L = f->lev[l];
+    TDBEM_HIP(hipMemsetAsync(L.d_mom.p, 0, L.d_mom.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(L.d_ring.p, 0, L.d_ring.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(L.d_lp.p, 0, L.d_lp.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(L.d_aux.p, 0, L.d_aux.n * sizeof(double), ctx->stream));
+  }
+}
+
+static TimeWeights time_weights(const Fmm* f, double xi, double ht) {
+  TimeWeights tw{};
+  for (int m = 0; m < f->pt; ++m) {
+    tw.w[m] = lag(f->om_t, f->pt, m, xi);
+    tw.dw[m] = dlag(f->om_t, f->pt, m, xi) / ht;
+  }
+  return tw;
+}
+
+void fmm_far(tdbem_ctx* ctx, int alpha, double* out) {
+  Fmm* f = ctx->fmm;
+  const int D = f->D;
+  const FmmLevel& L = f->lev[D];
+  const int Ml = f->m_leaf;
+  const int k = alpha / Ml;
+  const double ht = Ml * ctx->dt / 2.0;
+  const double center = (k * (double)Ml + (Ml - 1) / 2.0) * ctx->dt;
+  TimeWeights tw = time_weights(f, (alpha * ctx->dt - center) / ht, ht);
+  const double* Lk = L.d_ring.p + (int64_t)(k % f->R) * L.ncell * f->P;
+  l2p_kernel<<<(ctx->ns + 127) / 128, 128, 0, ctx->stream>>>(ctx->ns, f->Ps, f->pt, ctx->bie, 1.0 / ctx->c, tw,
+                                                             f->d_leaf_of.p, f->d_E0.p, f->d_E1.p, Lk, out);
+  TDBEM_HIP(hipGetLastError());
+}
+
+static int sep_threads(int P) { return std::min(1024, ((P + 63) / 64) * 64); }
+
+void fmm_advance(tdbem_ctx* ctx, int beta) {
+  Fmm* f = ctx->fmm;
+  hipStream_t st = ctx->stream;
+  const int D = f->D, P = f->P, G = f->G;
+  // densities of the new sample and P2M into the leaf source interval
+  densities_kernel<<<(ctx->ns + 255) / 256, 256, 0, st>>>(ctx->ns, beta, ctx->d, ctx->bw, ctx->d_hu.p, ctx->d_hq.p,
+                                                           ctx->hist_u ? 1 : 0, ctx->hist_q ? 1 : 0, f->d_tau.p,
+                                                           f->d_sig.p);
+  TDBEM_HIP(hipGetLastError());
+  {
+    const int Ml = f->m_leaf;
+    const int k = (beta + 1) / Ml;
+    const double ht = Ml * ctx->dt / 2.0;
+    const double center = (k * (double)Ml - 1.0 + (Ml - 1) / 2.0) * ctx->dt;
+    TimeWeights tw = time_weights(f, (beta * ctx->dt - center) / ht, ht);
+    FmmLevel& L = f->lev[D];
+    p2m_kernel<<<L.ncell, ((f->Ps + 63) / 64) * 64, 0, st>>>(f->Ps, f->pt, f->Cd, tw, f->d_leaf_ptr.p,
+                                                              f->d_leaf_elems.p, f->d_A.p, f->d_B.p, f->d_tau.p,
+                                                              f->d_sig.p, L.d_mom.p);
+    TDBEM_HIP(hipGetLastError());
+  }
+  const double* S = f->d_S.p;
+  const double* T = S + 2 * f->ps * f->ps;
+  const double* St = T + 2 * f->pt * f->pt;
+  const double* Tt = St + 2 * f->ps * f->ps;
+  const size_t shm = 2 * (size_t)P * sizeof(double);
+  for (int l = D; l >= 2; --l) {
+    const int Ml = f->m_leaf * (1 << (D - l));
+    if ((beta + 2) % Ml != 0) break;
+    const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
+    FmmLevel& L = f->lev[l];
+    if (L.npair > 0) {
+      dim3 g1(L.ntiles, (G * P + GB_M - 1) / GB_M);
+      m2l_gemm_kernel<<<g1, 256, 0, st>>>(P, G * P, L.d_tiles.p, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_U.p,
+                                           L.d_mom.p, L.d_stage.p);
+      TDBEM_HIP(hipGetLastError());
+      dim3 g2(L.ncell, (P + 255) / 256);
+      m2l_reduce_kernel<<<g2, 256, 0, st>>>(P, G, f->mu, ctx->d, f->R, k, ctx->c * Ml * ctx->dt, L.d_il_ptr.p,
+                                            L.d_stage.p, L.ncell, L.d_ring.p, L.d_lp.p, L.d_aux.p);
+      TDBEM_HIP(hipGetLastError());
+    }
+    if (l > 2) {
+      FmmLevel& Pl = f->lev[l - 1];
+      m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
+                                                         L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p);
+      TDBEM_HIP(hipGetLastError());
+    }
+    TDBEM_HIP(hipMemsetAsync(L.d_mom.p, 0, L.d_mom.n * sizeof(double), st));
+  }
+  // L2L for the target intervals that start at the next step, top-down
+  const int anext = beta + 2;
+  for (int l = 2; l < D; ++l) {
+    const int Ml = f->m_leaf * (1 << (D - l));
+    if (anext % Ml != 0) continue;
+    FmmLevel& Pl = f->lev[l];
+    FmmLevel& C = f->lev[l + 1];
+    l2l_kernel<<<C.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, f->R, anext / Ml, C.d_parent.p, C.d_octant.p, St,
+                                                      Tt, Pl.d_ring.p, Pl.ncell, C.d_ring.p, C.ncell);
+    TDBEM_HIP(hipGetLastError());
+  }
+}
+
+void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
+  const Fmm* f = ctx->fmm;
+  info->depth = f->D;
+  info->p_s = f->ps;
+  info->p_t = f->pt;
+  info->mu = f->mu;
+  info->m_leaf = f->m_leaf;
+  int64_t bytes = 0;
+  for (int l = 2; l <= f->D && l < 16; ++l) {
+    info->il_pairs[l] = f->lev[l].npair;
+    bytes += (int64_t)f->lev[l].d_U.n * sizeof(double);
+  }
+  info->m2l_matrix_bytes = bytes;
+}
+
+void fmm_near_pairs(const tdbem_ctx* ctx, std::vector<int64_t>& row_ptr, std::vector<int32_t>& pair_j) {
+  const Fmm* f = ctx->fmm;
+  const FmmLevel& L = f->lev[f->D];
+  std::unordered_map<int64_t, int> pos;
+  for (int i = 0; i < L.ncell; ++i) pos[key64(L.key[i][0], L.key[i][1], L.key[i][2])] = i;
+  const int ns = ctx->ns;
+  row_ptr.assign(ns + 1, 0);
+  pair_j.clear();
+  for (int i = 0; i < ns; ++i) {
+    const auto& k = L.key[f->leaf_of[i]];
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          auto it = pos.find(key64(k[0] + dx, k[1] + dy, k[2] + dz));
+          if (k[0] + dx < 0 || k[1] + dy < 0 || k[2] + dz < 0 || it == pos.end()) continue;
+          const int c = it->second;
+          for (int q = f->leaf_ptr[c]; q < f->leaf_ptr[c + 1]; ++q) pair_j.push_back(f->leaf_elems[q]);
+        }
+    row_ptr[i + 1] = (int64_t)pair_j.size();
+  }
+}
 
 }  // namespace tdbem
