@@ -1,0 +1,185 @@
+"""Benchmark: Ns*Nt per second of the time-domain BEM march on one MI355X.
+
+One "step" is one complete march of the named workload (Nt-1 collocation
+steps, each with near-field history sum, FMM far field (L2P), GMRES solve,
+history update, P2M, and at interval ends M2L (Algorithm 1), M2M and L2L),
+starting from a reset context; inputs (mesh tables, M2L operators) are
+resident in HBM before the timed region.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload sphere5k] [--mode fmm|direct]
+                  [--m2l fp64|fp32] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Ns·Nt/sec FMM-TDBEM at rel err ≤1e-4 vs direct; speedup vs FP64 plain form"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6        # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_TFLOPS = 157.3       # MI355X dense FP32
+
+WORKLOAD_TEXT = {
+    "sphere5k": "unit icosphere level 4 (Ns=5120), Nt=256, c dt = mean edge, Burton-Miller BIE, B-spline d=2, "
+                "homogeneous Neumann, Gaussian-modulated plane wave (f0=1, sigma=0.5, seeded direction); "
+                "FMM depth 4, 4 Chebyshev nodes per axis in space and time",
+    "small": "unit icosphere level 2 (Ns=320), Nt=64, Burton-Miller BIE, d=1, homogeneous Dirichlet, direct",
+    "sphere20k": "unit icosphere level 5 (Ns=20480), Nt=1024, Burton-Miller d=2 Neumann, FMM depth 5, p=4",
+}
+
+
+def m2l_flops_per_march(info, nt, m_leaf, depth, G, P):
+    """Algorithmic M2L flops of one march: 2 G P^2 per interaction pair per completed
+    source interval (G = mu+1+d operator blocks of P x P)."""
+    tot = 0
+    for lev in range(2, depth + 1):
+        Ml = m_leaf * 2 ** (depth - lev)
+        events = sum(1 for beta in range(0, nt - 1) if (beta + 2) % Ml == 0)
+        tot += events * 2 * G * P * P * info["il_pairs"][lev]
+    return tot
+
+
+def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0):
+    """The FP64 oracle (direct marching-on-in-time, plain definition) on a bounded sample:
+    compact coefficients of `rows_sample` seeded collocation rows against all elements,
+    then the Nt-1 history sums of those rows over a synthetic history (chunks of rows)."""
+    import synth
+    from oracle import elemint
+    g = elemint.Geometry(w["xyz"], w["tri"])
+    ns, nt, d = g.ns, w["nt"], w["d"]
+    rows = np.sort(np.random.default_rng(seed).choice(ns, size=min(rows_sample, ns), replace=False))
+    hist = synth.random_history(ns, nt, seed=seed + 1)
+    fam = (3 if w["bc"] == 1 else 2) if w["bie"] else (1 if w["bc"] == 1 else 0)
+    t0 = time.perf_counter()
+    acc = 0.0
+    for c0 in range(0, len(rows), chunk):
+        gmax, C = elemint.compact_rows(g, d, w["c"] * w["dt"], rows[c0:c0 + chunk])
+        Cf = np.ascontiguousarray(C[fam])
+        del C
+        for alpha in range(1, nt):
+            b = np.zeros(Cf.shape[0])
+            for gg in range(2, min(gmax, alpha) + 1):
+                b += Cf[:, gg, :] @ hist[alpha - gg]
+            acc += float(b[0])
+    sec = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(len(rows) * (nt - 1) / sec, 1), "unit": "Ns*Nt/s", "cores": cores, "kind": "oracle",
+            "sample": f"direct FP64 oracle: compact coefficients of {len(rows)} seeded rows x {ns} elements plus "
+                      f"their {nt - 1} history sums ({sec:.1f} s); rate = rows*(Nt-1)/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sphere5k")
+    ap.add_argument("--mode", default="fmm", choices=["fmm", "direct"])
+    ap.add_argument("--m2l", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 5}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(value is the single-GPU throughput); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2111_05205_amd as P
+
+    torch.cuda.set_device(0)
+    w = synth.workload(args.workload)
+    use_fmm = int(args.mode == "fmm" and w["use_fmm"])
+    prec = P.M2L_FP32 if args.m2l == "fp32" else P.M2L_FP64
+    s = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=use_fmm,
+                depth=w["depth"] or 4, p_s=w["p_s"] or 4, p_t=w["p_t"] or 4, m2l_prec=prec, nt_max=w["nt"])
+    info = s.info()
+    ns, nt = info["ns"], w["nt"]
+    for _ in range(args.warmup):
+        s.reset()
+        x, _ = s.run(nt, inc=w["inc"])
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(args.steps):
+        s.reset()
+        x, ri = s.run(nt, inc=w["inc"])
+        iters += ri["total_iters"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    sec = (t1 - t0) / args.steps
+    value = ns * nt / sec
+
+    # roofline of the dominant kernel
+    if use_fmm:
+        Pn = info["p_s"] ** 3 * info["p_t"]
+        G = info["mu"] + 1 + info["d"]
+        flops = m2l_flops_per_march(info, nt, info["m_leaf"], info["depth"], G, Pn) * args.steps
+        ms, n = prof["m2l_gemm"]
+        peak = PEAK_FP32_TFLOPS if args.m2l == "fp32" else PEAK_FP64_TFLOPS
+        achieved = flops / (ms * 1e-3) / 1e12
+        roof = {"kernel": "m2l_gemm", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
+    else:
+        ms, n = prof["near_history"]
+        byts = (info["near_coefs"] * 8 + info["near_pairs"] * 16 + ns * 8) * n
+        achieved = byts / (ms * 1e-3) / 1e9
+        roof = {"kernel": "near_history", "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
+    print("kernel time per march (ms): " + ", ".join(f"{k} {v[0] / args.steps:.2f} ({v[1] // args.steps})"
+                                                     for k, v in prof.items()), file=sys.stderr)
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "Ns*Nt/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if args.m2l == "fp64" else "f64 (M2L products f32)",
+           "data": "synthetic",
+           "config": {"workload": args.workload + ": " + WORKLOAD_TEXT.get(args.workload, ""),
+                      "mode": "fmm" if use_fmm else "direct", "ns": ns, "nt": nt, "d": info["d"],
+                      "mu": info["mu"], "m_leaf": info["m_leaf"], "near_pairs": info["near_pairs"],
+                      "il_pairs": info["il_pairs"][: (info["depth"] or 0) + 1],
+                      "gmres_iters_per_march": iters // args.steps, "setup_ms": round(info["setup_ms"], 1)},
+           "roofline": roof}
+
+    if not args.no_accuracy and use_fmm:
+        d = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0, nt_max=nt)
+        xd, _ = d.run(nt, inc=w["inc"])
+        err = float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))
+        out["accuracy"] = {"rel_l2_vs_direct": err, "direct_ms_per_march": None}
+        d.reset()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        d.run(nt, inc=w["inc"])
+        torch.cuda.synchronize()
+        out["accuracy"]["direct_ms_per_march"] = round((time.perf_counter() - t2) * 1e3, 3)
+        del d
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

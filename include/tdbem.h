@@ -177,6 +177,17 @@ int tdbem_incident_forcing(struct tdbem_ctx *ctx, const tdbem_incident *inc, int
 int tdbem_near_row(struct tdbem_ctx *ctx, int i, int cap, int32_t *j_out, int32_t *g_out,
                    double *cu_out, double *cw_out);
 
+/* Kernel timing.  While enabled, every kernel launch of the context is
+ * bracketed by HIP events on the context stream and attributed to a category:
+ * 0 near-field history sum, 1 GMRES solve, 2 L2P, 3 P2M (with densities),
+ * 4 M2L products, 5 M2L reduction + recurrence, 6 M2M, 7 L2L, 8 other.
+ * tdbem_profile(ctx, 1) clears the accumulators; tdbem_profile_read() waits
+ * for the stream and writes per-category total milliseconds and launch counts
+ * (arrays of n <= 16 entries). */
+#define TDBEM_PROF_KINDS 9
+int tdbem_profile(struct tdbem_ctx *ctx, int enable);
+int tdbem_profile_read(struct tdbem_ctx *ctx, double *ms, int64_t *launches, int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -237,36 +237,45 @@ static void window_of(double rmin, double rmax, int d, double cdt, int *glo, int
   *glo = lo; *ghi = hi;
 }
 
-/* Pass 1 over all pairs: window start and length per (i, j), row-major i*ns+j.
+/* Pass 1: window start and length per (row, j), row-major r*ns+j, for the
+ * collocation rows rows[0..nrows-1] (rows == NULL: all ns rows).
  * xc: collocation points (ns x 3), tris: vertex coordinates (ns x 9). */
-void oracle_windows(int ns, const double *xc, const double *tris, int d, double cdt,
-                    int *glo, int *cnt) {
+void oracle_windows_rows(int ns, int nrows, const int *rows, const double *xc, const double *tris, int d,
+                         double cdt, int *glo, int *cnt) {
 #pragma omp parallel for schedule(dynamic, 8)
-  for (int i = 0; i < ns; ++i)
+  for (int r = 0; r < nrows; ++r) {
+    int i = rows ? rows[r] : r;
     for (int j = 0; j < ns; ++j) {
       double rmin, rmax;
       if (i == j) { double a; oracle_dist_range(xc + 3*i, tris + 9*j, &a, &rmax); rmin = 0.0; }
       else oracle_dist_range(xc + 3*i, tris + 9*j, &rmin, &rmax);
       int lo, hi; window_of(rmin, rmax, d, cdt, &lo, &hi);
-      glo[(long)i*ns + j] = lo; cnt[(long)i*ns + j] = hi - lo + 1;
+      glo[(long)r*ns + j] = lo; cnt[(long)r*ns + j] = hi - lo + 1;
     }
+  }
 }
 
-/* Pass 2: compact coefficients for every pair and g in its window.
- * out has 4 families interleaved per slot: out[4*(off[i*ns+j] + k) + f],
+void oracle_windows(int ns, const double *xc, const double *tris, int d, double cdt, int *glo, int *cnt) {
+  oracle_windows_rows(ns, ns, 0, xc, tris, d, cdt, glo, cnt);
+}
+
+/* Pass 2: compact coefficients for every (row, j) and g in its window.
+ * out has 4 families interleaved per slot: out[4*(off[r*ns+j] + k) + f],
  * f = 0 U, 1 W, 2 Ubar, 3 Wbar;  g = glo + k.  nrm: paper normals (ns x 3). */
-void oracle_fill(int ns, const double *xc, const double *nrm, const double *tris, int d, double cdt,
-                 const int *glo, const int *cnt, const long *off, double *out) {
+void oracle_fill_rows(int ns, int nrows, const int *rows, const double *xc, const double *nrm, const double *tris,
+                      int d, double cdt, const int *glo, const int *cnt, const long *off, double *out) {
   double w[8];
   for (int k = 0; k <= d + 1; ++k) w[k] = bspline_w(k, d);
 #pragma omp parallel for schedule(dynamic, 8)
-  for (int i = 0; i < ns; ++i)
+  for (int r = 0; r < nrows; ++r) {
+    int i = rows ? rows[r] : r;
     for (int j = 0; j < ns; ++j) {
-      long p = (long)i*ns + j;
+      long p = (long)r*ns + j;
       int lo = glo[p], n = cnt[p];
       double X[64][4];
       int gmin = lo - d - 1; if (gmin < 1) gmin = 1;
       int gmax = lo + n - 1;
+      if (gmax - gmin + 1 > 64) continue; /* caller rejects such windows */
       for (int g = gmin; g <= gmax; ++g)
         oracle_elem(xc + 3*i, nrm + 3*i, tris + 9*j, nrm + 3*j, i == j, g * cdt, d, cdt, X[g - gmin]);
       for (int k = 0; k < n; ++k) {
@@ -280,4 +289,10 @@ void oracle_fill(int ns, const double *xc, const double *nrm, const double *tris
         for (int f = 0; f < 4; ++f) out[4*(off[p] + k) + f] = acc[f];
       }
     }
+  }
+}
+
+void oracle_fill(int ns, const double *xc, const double *nrm, const double *tris, int d, double cdt,
+                 const int *glo, const int *cnt, const long *off, double *out) {
+  oracle_fill_rows(ns, ns, 0, xc, nrm, tris, d, cdt, glo, cnt, off, out);
 }

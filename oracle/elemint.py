@@ -30,6 +30,10 @@ def lib():
         L.oracle_dist_range.argtypes = [dp, dp, dp, dp]
         L.oracle_windows.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip]
         L.oracle_fill.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip, lp, dp]
+        L.oracle_windows_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double,
+                                          ip, ip]
+        L.oracle_fill_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                                       ip, ip, lp, dp]
         _lib = L
     return _lib
 
@@ -111,3 +115,29 @@ def compact_coefficients(geom: Geometry, d: int, cdt: float):
             mats[gg] = sp.csr_matrix((vals[m, f], (rows[m], cols[m])), shape=(ns, ns))
         fams[name] = mats
     return gmax, fams
+
+
+def compact_rows(geom: Geometry, d: int, cdt: float, rows):
+    """Compact coefficients of the given collocation rows against every element:
+    returns (gmax, dense array C[f, r, g, j]) with f in (U, W, Ubar, Wbar), g = 0..gmax (g=0 unused)."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    ns, nr = geom.ns, len(rows)
+    glo = np.zeros(nr * ns, dtype=np.int32)
+    cnt = np.zeros(nr * ns, dtype=np.int32)
+    lib().oracle_windows_rows(ns, nr, _p(rows, ctypes.c_int), _p(geom.x), _p(geom.tris), d, cdt,
+                              _p(glo, ctypes.c_int), _p(cnt, ctypes.c_int))
+    if cnt.max() + d + 1 > 64:
+        raise ValueError("time window too long for the oracle's fixed buffer")
+    off = np.zeros(nr * ns, dtype=np.int64)
+    off[1:] = np.cumsum(cnt[:-1], dtype=np.int64)
+    vals = np.zeros((int(cnt.sum()), 4))
+    lib().oracle_fill_rows(ns, nr, _p(rows, ctypes.c_int), _p(geom.x), _p(geom.n), _p(geom.tris), d, cdt,
+                           _p(glo, ctypes.c_int), _p(cnt, ctypes.c_int), _p(off, ctypes.c_long), _p(vals))
+    g = np.repeat(glo, cnt) + (np.arange(vals.shape[0]) - np.repeat(off, cnt))
+    gmax = int(g.max())
+    r = np.repeat(np.repeat(np.arange(nr), ns), cnt)
+    j = np.repeat(np.tile(np.arange(ns), nr), cnt)
+    C = np.zeros((4, nr, gmax + 1, ns))
+    for f in range(4):
+        C[f, r, g, j] = vals[:, f]
+    return gmax, C

@@ -149,6 +149,18 @@ class TDBEM:
         self._check(self._L.tdbem_incident_forcing(self._h, ctypes.byref(incs), int(a0), int(n), _dptr(out)))
         return out
 
+    def profile(self, enable=True):
+        """Start (clear) or stop per-kernel timing of this context."""
+        self._check(self._L.tdbem_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{category: (total ms, launches)} accumulated since profile(True)."""
+        n = len(N.PROF_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self._check(self._L.tdbem_profile_read(self._h, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(N.PROF_KINDS)}
+
     def near_row(self, i):
         n = self._check(self._L.tdbem_near_row(self._h, int(i), 0, None, None, None, None))
         j = np.zeros(n, dtype=np.int32)

@@ -44,6 +44,8 @@ class Info(ctypes.Structure):
                 ("il_pairs", ctypes.c_int64 * 16), ("m2l_matrix_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double)]
 
 
+PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other"]
+
 _lib = None
 
 
@@ -72,5 +74,7 @@ def lib():
         L.tdbem_incident_forcing.argtypes = [vp, ctypes.POINTER(Incident), ip, ip, vp]
         L.tdbem_near_row.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                      dp, dp]
+        L.tdbem_profile.argtypes = [vp, ip]
+        L.tdbem_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ip]
         _lib = L
     return _lib

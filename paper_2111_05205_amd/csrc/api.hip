@@ -135,6 +135,19 @@ __global__ void store_step_kernel(int ns, int beta, int bc, const double* __rest
   if (!isfinite(xv) || fabs(xv) > 1e100) atomicOr(&st->flags, 2);
 }
 
+// Initial guess of the per-step solve: quadratic extrapolation of the last
+// three solved coefficient rows (previous row, or zero, early in the march).
+__global__ void guess_kernel(int ns, int beta, const double* __restrict__ h, double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  double v = 0.0;
+  if (beta >= 3)
+    v = 3.0 * h[(int64_t)(beta - 1) * ns + i] - 3.0 * h[(int64_t)(beta - 2) * ns + i] + h[(int64_t)(beta - 3) * ns + i];
+  else if (beta >= 1)
+    v = h[(int64_t)(beta - 1) * ns + i];
+  x[i] = v;
+}
+
 __global__ void forcing_kernel(int ns, int a0, int n, int bie, double c, double dt, tdbem_incident inc,
                                const double* __restrict__ xc, const double* __restrict__ nrm,
                                double* __restrict__ out) {
@@ -210,9 +223,17 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
     if (ctx->bc == TDBEM_DIRICHLET) launch_spmv_add(ctx, ctx->d_w1_val.p, -1.0, bcv, ctx->d_b.p);
     else launch_spmv_add(ctx, ctx->d_u1_val.p, 1.0, bcv, ctx->d_b.p);
   }
+  {
+    ProfScope pg(ctx, K_OTHER);
+    guess_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
+        ctx->ns, beta, ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p, ctx->d_x.p);
+    TDBEM_HIP(hipGetLastError());
+  }
   launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, stat);
+  ProfScope* ps = new ProfScope(ctx, K_OTHER);
   store_step_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(ctx->ns, beta, ctx->bc, ctx->d_x.p, bcv,
                                                                       ctx->d_hu.p, ctx->d_hq.p, stat);
+  delete ps;
   TDBEM_HIP(hipGetLastError());
   if (ctx->bc == TDBEM_NEUMANN) { ctx->hist_u = true; if (bcv) ctx->hist_q = true; }
   else { ctx->hist_q = true; if (bcv) ctx->hist_u = true; }
@@ -299,8 +320,43 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
   return TDBEM_OK;
 }
 
+static void prof_collect(tdbem_ctx* ctx) {
+  if (!ctx->prof_ev.empty()) TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  for (auto& e : ctx->prof_ev) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.second.first, e.second.second) == hipSuccess) {
+      ctx->prof_ms[e.first] += ms;
+      ctx->prof_cnt[e.first] += 1;
+    }
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  ctx->prof_ev.clear();
+}
+
+int tdbem_profile(tdbem_ctx* ctx, int enable) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    prof_collect(ctx);
+    for (int k = 0; k < 16; ++k) { ctx->prof_ms[k] = 0.0; ctx->prof_cnt[k] = 0; }
+    ctx->prof = enable != 0;
+  });
+}
+
+int tdbem_profile_read(tdbem_ctx* ctx, double* ms, int64_t* launches, int n) {
+  if (!ctx || n < 0 || n > 16) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    prof_collect(ctx);
+    for (int k = 0; k < n; ++k) {
+      if (ms) ms[k] = ctx->prof_ms[k];
+      if (launches) launches[k] = ctx->prof_cnt[k];
+    }
+  });
+}
+
 void tdbem_destroy(tdbem_ctx* ctx) {
   if (!ctx) return;
+  for (auto& e : ctx->prof_ev) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
   if (ctx->fmm) fmm_destroy(ctx->fmm);
   delete ctx;
 }

@@ -55,12 +55,15 @@ struct FmmLevel {
   DevBuf<int32_t> d_tiles;                  // GEMM column tiles: (slot, first, count) triples
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
   int ntiles = 0;
-  DevBuf<double> d_U;                       // [slot][G*P][P]
-  DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_stage;
+  DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
+  DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
+  DevBuf<float> d_U32, d_stage32;           // FP32 operators and staging (mixed-precision M2L)
+  DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_stage, d_dp;
 };
 
 struct Fmm {
   int D = 0, ps = 0, pt = 0, Ps = 0, P = 0, G = 0, mu = 0, R = 0, m_leaf = 1;
+  bool f32 = false;
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
   double om_s[MAXP], om_t[MAXP];
   std::vector<FmmLevel> lev;               // 0..D
@@ -348,100 +351,188 @@ __global__ void l2l_kernel(int ps, int pt, int R, int kp, const int32_t* __restr
   }
 }
 
-// M2L products, plain LDS-tiled FP64 GEMM: for each tile (slot, first pair, count)
-// stage[pair][row] = sum_col U[slot][row][col] * mom[src(pair)][col], rows = G*P.
-constexpr int GB_M = 64, GB_N = 32, GB_K = 16;
+// M2L products on the matrix cores.  For each column tile (offset slot, first
+// pair, count <= 128) and each block of 128 operator rows:
+//   stage[pair][row] = sum_col U[slot][row][col] * mom[src(pair)][col],   rows = G*P.
+// The moments of the tile's source cells are gathered into LDS, so each block
+// of U is read once per column tile (most offsets fit one tile).  Four waves
+// each own 32 rows x 128 columns as 2 x 8 blocks of 16 x 16 MFMA accumulators;
+// K advances in steps of 16.  FP64 uses
+// v_mfma_f64_16x16x4 (D row = 4 r + lane/16), FP32 v_mfma_f32_16x16x4
+// (D row = 4 (lane/16) + r); in both, A[i][k] sits in lane i + 16 k and
+// B[k][j] in lane j + 16 k.  The operators are stored in that fragment order,
+// so each wave streams its A fragments from memory with fully coalesced
+// 64-lane loads (one K step ahead); the gathered moments go through LDS.
+constexpr int MB_M = 128, MB_N = 128, MB_K = 16;
+constexpr int BS_LD = MB_N + 4;  // LDS row stride of the moment tile
 
-__global__ __launch_bounds__(256) void m2l_gemm_kernel(int P, int GP, const int32_t* __restrict__ tiles,
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef dbl4_t acc_t;
+  static __device__ inline acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef flt4_t acc_t;
+  static __device__ inline acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// Operators in MFMA fragment order: Uf[slot][rb][kb][lane] = U[16 rb + lane%16][4 kb + lane/16],
+// rows padded to RB = ceil(GP/16) blocks and columns to KB = ceil(P/4) blocks (zeros), so one
+// A fragment is 64 consecutive values.
+template <class T>
+__global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double* __restrict__ U,
+                                    T* __restrict__ Uf) {
+  const int slot = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)RB * KB * 64;
+  if (idx >= per) return;
+  const int lane = (int)(idx & 63);
+  const int64_t blk = idx >> 6;
+  const int kb = (int)(blk % KB), rb = (int)(blk / KB);
+  const int row = rb * 16 + (lane & 15), col = kb * 4 + (lane >> 4);
+  const double v = (row < GP && col < P) ? U[((int64_t)slot * GP + row) * P + col] : 0.0;
+  Uf[(int64_t)slot * per + idx] = (T)v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, int KB, const int32_t* __restrict__ tiles,
                                                        const int32_t* __restrict__ pairs_by_slot,
-                                                       const int32_t* __restrict__ il_src,
-                                                       const double* __restrict__ U, const double* __restrict__ mom,
-                                                       double* __restrict__ stage) {
-  __shared__ double As[GB_K][GB_M + 1];
-  __shared__ double Bs[GB_K][GB_N + 1];
-  __shared__ int src[GB_N], pid[GB_N];
+                                                       const int32_t* __restrict__ il_src, const T* __restrict__ Uf,
+                                                       const double* __restrict__ mom, T* __restrict__ stage) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T Bs[MB_K][BS_LD];
+  __shared__ int src[MB_N], pid[MB_N];
   const int slot = tiles[3 * blockIdx.x], first = tiles[3 * blockIdx.x + 1], cnt = tiles[3 * blockIdx.x + 2];
-  const int row0 = blockIdx.y * GB_M;
-  const int tid = threadIdx.x;
-  if (tid < GB_N) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb0 = blockIdx.y * (MB_M / 16) + wave * 2;   // this wave: row blocks rb0, rb0+1 (32 rows)
+  if (tid < MB_N) {
     const int p = tid < cnt ? pairs_by_slot[first + tid] : -1;
     pid[tid] = p;
     src[tid] = p >= 0 ? il_src[p] : -1;
   }
   __syncthreads();
-  const double* Us = U + (int64_t)slot * GP * P;
-  const int tr = tid / 8, tc = tid % 8;  // 32 x 8 threads: rows tr*2.., cols tc*4..
-  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int k0 = 0; k0 < P; k0 += GB_K) {
-    for (int e = tid; e < GB_M * GB_K; e += 256) {
-      const int r = e / GB_K, kk = e % GB_K;
-      const int row = row0 + r, col = k0 + kk;
-      As[kk][r] = (row < GP && col < P) ? Us[(int64_t)row * P + col] : 0.0;
+  const int64_t per = (int64_t)RB * KB * 64;
+  const T* A0 = Uf + (int64_t)slot * per + ((int64_t)rb0 * KB) * 64 + lane;   // row block rb0
+  const T* A1 = A0 + (int64_t)KB * 64;                                         // row block rb0+1
+  const bool rlive0 = rb0 < RB, rlive1 = rb0 + 1 < RB;
+  const int ncb = (cnt + 15) >> 4;                                             // live column blocks
+  acc_t acc[2][8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  const int bc = tid >> 1, bk = (tid & 1) * 8;
+  const int bsrc = src[bc];
+  const double* mrow = mom + (int64_t)(bsrc >= 0 ? bsrc : 0) * P;
+  // prefetch of the A fragments of one K step (4 k-blocks x 2 row blocks)
+  T fa[2][4];
+  auto loadA = [&](int kb0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kb = kb0 + q;
+      fa[0][q] = (rlive0 && kb < KB) ? A0[(int64_t)kb * 64] : T(0);
+      fa[1][q] = (rlive1 && kb < KB) ? A1[(int64_t)kb * 64] : T(0);
     }
-    for (int e = tid; e < GB_N * GB_K; e += 256) {
-      const int cc = e / GB_K, kk = e % GB_K;
-      const int col = k0 + kk;
-      Bs[kk][cc] = (src[cc] >= 0 && col < P) ? mom[(int64_t)src[cc] * P + col] : 0.0;
+  };
+  loadA(0);
+  for (int k0 = 0; k0 < P; k0 += MB_K) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + bk + i;
+      Bs[bk + i][bc] = (bsrc >= 0 && k < P) ? (T)mrow[k] : T(0);
     }
     __syncthreads();
-    for (int kk = 0; kk < GB_K; ++kk) {
-      const double a0 = As[kk][tr * 2], a1 = As[kk][tr * 2 + 1];
-      for (int j = 0; j < 4; ++j) {
-        const double bv = Bs[kk][tc * 4 + j];
-        acc[0][j] += a0 * bv;
-        acc[1][j] += a1 * bv;
+    T ca[2][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { ca[0][q] = fa[0][q]; ca[1][q] = fa[1][q]; }
+    if (k0 + MB_K < P) loadA((k0 + MB_K) >> 2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        if (cb < ncb) {
+          const T bf = Bs[4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
+          acc[0][cb] = Mfma<T>::op(ca[0][q], bf, acc[0][cb]);
+          acc[1][cb] = Mfma<T>::op(ca[1][q], bf, acc[1][cb]);
+        }
       }
     }
     __syncthreads();
   }
-  for (int i = 0; i < 2; ++i) {
-    const int row = row0 + tr * 2 + i;
-    if (row >= GP) continue;
-    for (int j = 0; j < 4; ++j) {
-      const int cc = tc * 4 + j;
-      if (pid[cc] >= 0) stage[(int64_t)pid[cc] * GP + row] = acc[i][j];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) {
+      if (cb >= ncb) continue;
+      const int p = pid[cb * 16 + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (rb0 + h) * 16 + Mfma<T>::row(lane, r);
+        if (p >= 0 && row < GP) stage[(int64_t)p * GP + row] = acc[h][cb][r];
+      }
     }
-  }
 }
 
-// Reduce the staged products per target cell and run the recurrence of Algorithm 1.
-// grid: (ncell, ceil(P/256)); thread per coefficient index a of the cell.
-__global__ void m2l_reduce_kernel(int P, int G, int mu, int d, int R, int k, double T,
-                                  const int32_t* __restrict__ il_ptr, const double* __restrict__ stage,
-                                  int ncell, double* __restrict__ ring, double* __restrict__ lp,
-                                  double* __restrict__ aux) {
-  const int O = blockIdx.x;
-  const int a = blockIdx.y * blockDim.x + threadIdx.x;
+// Reduce the staged products per target cell: grid (ncell, G, ceil(P/256)).
+// Block g < mu+1 adds its sum into the near-future local L_{k+g+1}; block
+// g = mu+p writes L^{(p)}_{k+mu+1,k} to dp[p-1].  Each thread sums one
+// coefficient over the cell's interaction pairs (independent loads).
+template <class ST>
+__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int G, int mu, int R, int k,
+                                                         const int32_t* __restrict__ il_ptr,
+                                                         const ST* __restrict__ stage, int ncell,
+                                                         double* __restrict__ ring, double* __restrict__ dp) {
+  const int O = blockIdx.x, g = blockIdx.y;
+  const int a = blockIdx.z * blockDim.x + threadIdx.x;
   if (a >= P) return;
-  const int GP = G * P;
+  const int64_t GP = (int64_t)G * P;
   const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
-  // near future: L_{k+l} += sum over the cell's pairs
-  for (int l = 1; l <= mu + 1; ++l) {
-    double s = 0.0;
-    for (int p = p0; p < p1; ++p) s += stage[(int64_t)p * GP + (l - 1) * P + a];
-    ring[((int64_t)((k + l) % R) * ncell + O) * P + a] += s;
+  const ST* sp = stage + (int64_t)g * P + a;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int p = p0;
+  for (; p + 3 < p1; p += 4) {
+    s0 += (double)sp[(int64_t)p * GP];
+    s1 += (double)sp[(int64_t)(p + 1) * GP];
+    s2 += (double)sp[(int64_t)(p + 2) * GP];
+    s3 += (double)sp[(int64_t)(p + 3) * GP];
   }
-  double Dp[4] = {0, 0, 0, 0};
+  for (; p < p1; ++p) s0 += (double)sp[(int64_t)p * GP];
+  const double s = (s0 + s1) + (s2 + s3);
+  if (g <= mu) ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s;
+  else dp[((int64_t)(g - mu - 1) * ncell + O) * P + a] = s;
+}
+
+// Recurrence of Algorithm 1 for source interval k, per (cell, coefficient):
+// eq. m2l_expand_rec1 (derivatives, using the auxiliaries of k-1), eq. m2l_rec
+// (local of interval k+mu+2), eq. m2l_expand_rec2 (auxiliaries).  d <= 2, so
+// the only coefficient is c_0^2(k) = 2 and the only auxiliary L^{(2,0)}.
+__global__ void m2l_recurrence_kernel(int P, int mu, int d, int R, int k, double T, int ncell,
+                                      const double* __restrict__ dp, double* __restrict__ ring,
+                                      double* __restrict__ lp, double* __restrict__ aux) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)ncell * P;
+  if (idx >= n) return;
+  double Lnew[3] = {0, 0, 0};
   for (int q = 1; q <= d; ++q) {
-    double s = 0.0;
-    for (int p = p0; p < p1; ++p) s += stage[(int64_t)p * GP + (mu + q) * P + a];
-    Dp[q] = s;
-  }
-  // eq. m2l_expand_rec1 (uses auxiliaries of k-1), eq. m2l_rec, eq. m2l_expand_rec2
-  const int64_t cell = (int64_t)O * P + a;
-  const int64_t stride = (int64_t)ncell * P;
-  double Lnew[4] = {0, 0, 0, 0};
-  for (int q = 1; q <= d; ++q) {
-    double v = lp[(q - 1) * stride + cell] + Dp[q];
-    if (q == 2) v += 2.0 * aux[cell];  // c_0^2(k) = 2
+    double v = lp[(q - 1) * n + idx] + dp[(q - 1) * n + idx];
+    if (q == 2) v += 2.0 * aux[idx];
     Lnew[q] = v;
-    lp[(q - 1) * stride + cell] = v;
+    lp[(q - 1) * n + idx] = v;
   }
-  double next = ring[((int64_t)((k + mu + 1) % R) * ncell + O) * P + a];
+  double next = ring[(int64_t)((k + mu + 1) % R) * n + idx];
   double Tp = 1.0;
   for (int q = 1; q <= d; ++q) { Tp *= T; next += Lnew[q] * Tp; }
-  ring[((int64_t)((k + mu + 2) % R) * ncell + O) * P + a] = next;
-  if (d >= 2) aux[cell] += Dp[2];  // m = 0: k^0 = 1
+  ring[(int64_t)((k + mu + 2) % R) * n + idx] = next;
+  if (d >= 2) aux[idx] += dp[n + idx];
 }
 
 // L2P: far field at (x_i, t_alpha) from the leaf local of the current interval.
@@ -638,10 +729,12 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
   if (o.p_s < 2 || o.p_s > MAXP || o.p_t < 2 || o.p_t > MAXP)
     throw Error(TDBEM_E_INVAL, "p_s and p_t must be in [2, 8]");
   if (o.p_t <= ctx->d) throw Error(TDBEM_E_INVAL, "p_t must exceed the B-spline order d");
-  if (o.m2l_prec != TDBEM_M2L_FP64) throw Error(TDBEM_E_INVAL, "only FP64 M2L is available in this build");
+  if (o.m2l_prec != TDBEM_M2L_FP64 && o.m2l_prec != TDBEM_M2L_FP32)
+    throw Error(TDBEM_E_INVAL, "m2l_prec must be FP64 (0) or FP32 (1)");
   Fmm* f = new Fmm();
   try {
     f->D = o.depth;
+    f->f32 = o.m2l_prec == TDBEM_M2L_FP32;
     f->ps = o.p_s;
     f->pt = o.p_t;
     f->Ps = f->ps * f->ps * f->ps;
@@ -734,10 +827,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       for (int sl = 0; sl < nslot; ++sl) {
         const int first = (int)flat.size();
         flat.insert(flat.end(), by[sl].begin(), by[sl].end());
-        for (int s0 = 0; s0 < (int)by[sl].size(); s0 += GB_N) {
+        for (int s0 = 0; s0 < (int)by[sl].size(); s0 += MB_N) {
           tiles.push_back(sl);
           tiles.push_back(first + s0);
-          tiles.push_back(std::min(GB_N, (int)by[sl].size() - s0));
+          tiles.push_back(std::min(MB_N, (int)by[sl].size() - s0));
         }
       }
       L.ntiles = (int)tiles.size() / 3;
@@ -759,7 +852,24 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_ring.alloc((size_t)f->R * L.ncell * P);
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d - 1) * L.ncell * P);
-      L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+      L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
+      {
+        const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
+        const int64_t per = (int64_t)RB * KB * 64;
+        dim3 gf((unsigned)((per + 255) / 256), std::max(nslot, 1));
+        if (f->f32) {
+          L.d_U32.alloc((size_t)std::max(nslot, 1) * per);
+          if (nslot > 0) to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, RB, KB, L.d_U.p, L.d_U32.p);
+          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+        } else {
+          L.d_Uf.alloc((size_t)std::max(nslot, 1) * per);
+          if (nslot > 0) to_fragments_kernel<double><<<gf, 256, 0, st>>>(P, G * P, RB, KB, L.d_U.p, L.d_Uf.p);
+          L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+        }
+        TDBEM_HIP(hipGetLastError());
+        TDBEM_HIP(hipStreamSynchronize(st));
+        L.d_U.release();  // row-major master no longer needed
+      }
       for (DevBuf<double>* b : {&L.d_mom, &L.d_ring, &L.d_lp, &L.d_aux})
         TDBEM_HIP(hipMemsetAsync(b->p, 0, b->n * sizeof(double), st));
       TDBEM_HIP(hipStreamSynchronize(st));  // temporaries (d_so) are released at scope end
@@ -804,6 +914,7 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out) {
   const double center = (k * (double)Ml + (Ml - 1) / 2.0) * ctx->dt;
   TimeWeights tw = time_weights(f, (alpha * ctx->dt - center) / ht, ht);
   const double* Lk = L.d_ring.p + (int64_t)(k % f->R) * L.ncell * f->P;
+  ProfScope ps(ctx, K_L2P);
   l2p_kernel<<<(ctx->ns + 127) / 128, 128, 0, ctx->stream>>>(ctx->ns, f->Ps, f->pt, ctx->bie, 1.0 / ctx->c, tw,
                                                              f->d_leaf_of.p, f->d_E0.p, f->d_E1.p, Lk, out);
   TDBEM_HIP(hipGetLastError());
@@ -816,6 +927,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
   hipStream_t st = ctx->stream;
   const int D = f->D, P = f->P, G = f->G;
   // densities of the new sample and P2M into the leaf source interval
+  ProfScope* p2m_scope = new ProfScope(ctx, K_P2M);
   densities_kernel<<<(ctx->ns + 255) / 256, 256, 0, st>>>(ctx->ns, beta, ctx->d, ctx->bw, ctx->d_hu.p, ctx->d_hq.p,
                                                            ctx->hist_u ? 1 : 0, ctx->hist_q ? 1 : 0, f->d_tau.p,
                                                            f->d_sig.p);
@@ -832,6 +944,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
                                                               f->d_sig.p, L.d_mom.p);
     TDBEM_HIP(hipGetLastError());
   }
+  delete p2m_scope;
   const double* S = f->d_S.p;
   const double* T = S + 2 * f->ps * f->ps;
   const double* St = T + 2 * f->pt * f->pt;
@@ -843,17 +956,38 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
     FmmLevel& L = f->lev[l];
     if (L.npair > 0) {
-      dim3 g1(L.ntiles, (G * P + GB_M - 1) / GB_M);
-      m2l_gemm_kernel<<<g1, 256, 0, st>>>(P, G * P, L.d_tiles.p, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_U.p,
-                                           L.d_mom.p, L.d_stage.p);
+      {
+        ProfScope ps(ctx, K_M2L_GEMM);
+        dim3 g1(L.ntiles, (G * P + MB_M - 1) / MB_M);
+        const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
+        if (f->f32)
+          m2l_mfma_kernel<float><<<g1, 256, 0, st>>>(P, G * P, RB, KB, L.d_tiles.p, L.d_pairs_by_slot.p,
+                                                      L.d_il_src.p, L.d_U32.p, L.d_mom.p, L.d_stage32.p);
+        else
+          m2l_mfma_kernel<double><<<g1, 256, 0, st>>>(P, G * P, RB, KB, L.d_tiles.p, L.d_pairs_by_slot.p,
+                                                       L.d_il_src.p, L.d_Uf.p, L.d_mom.p, L.d_stage.p);
+        TDBEM_HIP(hipGetLastError());
+      }
+      ProfScope ps(ctx, K_M2L_RED);
+      dim3 g2(L.ncell, G, (P + 255) / 256);
+      const int bs = std::min(256, ((P + 63) / 64) * 64);
+      if (f->f32)
+        m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
+                                                     L.d_ring.p, L.d_dp.p);
+      else
+        m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage.p, L.ncell,
+                                                      L.d_ring.p, L.d_dp.p);
       TDBEM_HIP(hipGetLastError());
-      dim3 g2(L.ncell, (P + 255) / 256);
-      m2l_reduce_kernel<<<g2, 256, 0, st>>>(P, G, f->mu, ctx->d, f->R, k, ctx->c * Ml * ctx->dt, L.d_il_ptr.p,
-                                            L.d_stage.p, L.ncell, L.d_ring.p, L.d_lp.p, L.d_aux.p);
+      const int64_t nrec = (int64_t)L.ncell * P;
+      m2l_recurrence_kernel<<<(unsigned)((nrec + 255) / 256), 256, 0, st>>>(P, f->mu, ctx->d, f->R, k,
+                                                                             ctx->c * Ml * ctx->dt, L.ncell,
+                                                                             L.d_dp.p, L.d_ring.p, L.d_lp.p,
+                                                                             L.d_aux.p);
       TDBEM_HIP(hipGetLastError());
     }
     if (l > 2) {
       FmmLevel& Pl = f->lev[l - 1];
+      ProfScope ps(ctx, K_M2M);
       m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
                                                          L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p);
       TDBEM_HIP(hipGetLastError());
@@ -867,6 +1001,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     if (anext % Ml != 0) continue;
     FmmLevel& Pl = f->lev[l];
     FmmLevel& C = f->lev[l + 1];
+    ProfScope ps(ctx, K_L2L);
     l2l_kernel<<<C.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, f->R, anext / Ml, C.d_parent.p, C.d_octant.p, St,
                                                       Tt, Pl.d_ring.p, Pl.ncell, C.d_ring.p, C.ncell);
     TDBEM_HIP(hipGetLastError());
@@ -883,7 +1018,7 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   int64_t bytes = 0;
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
-    bytes += (int64_t)f->lev[l].d_U.n * sizeof(double);
+    bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
   }
   info->m2l_matrix_bytes = bytes;
 }

@@ -197,6 +197,7 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
 }
 
 void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat) {
+  ProfScope ps(ctx, K_GMRES);
   int m = ctx->opts.gmres_restart;
   if (m > GM_MAXM) m = GM_MAXM;
   if (m < 1) m = 1;

@@ -113,9 +113,35 @@ struct tdbem_ctx {
   tdbem::DevBuf<tdbem::StepStat> d_stat;
 
   tdbem::Fmm* fmm = nullptr;
+
+  // kernel timing (tdbem_profile)
+  bool prof = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
+  double prof_ms[16] = {0};
+  int64_t prof_cnt[16] = {0};
 };
 
 namespace tdbem {
+
+enum ProfKind { K_NEAR = 0, K_GMRES = 1, K_L2P = 2, K_P2M = 3, K_M2L_GEMM = 4, K_M2L_RED = 5, K_M2M = 6, K_L2L = 7,
+                K_OTHER = 8 };
+
+// Brackets the launches in its scope with events when profiling is enabled.
+struct ProfScope {
+  tdbem_ctx* c;
+  int kind;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(tdbem_ctx* ctx, int k) : c(ctx), kind(k) {
+    if (c->prof && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+      (void)hipEventRecord(e0, c->stream);
+  }
+  ~ProfScope() {
+    if (c->prof && e0 && e1) {
+      (void)hipEventRecord(e1, c->stream);
+      c->prof_ev.push_back({kind, {e0, e1}});
+    }
+  }
+};
 
 // nearfield.hip
 void build_near_table(tdbem_ctx* ctx, const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& pair_j);

@@ -242,6 +242,7 @@ __global__ __launch_bounds__(256) void near_history_kernel(
 }
 
 void launch_near_history(tdbem_ctx* ctx, int alpha, const double* base, double* out) {
+  ProfScope ps(ctx, K_NEAR);
   const int rows_per_block = 4;
   near_history_kernel<<<(ctx->ns + rows_per_block - 1) / rows_per_block, 64 * rows_per_block, 0, ctx->stream>>>(
       ctx->ns, alpha, ctx->d_row_ptr.p, ctx->d_pair_j.p, ctx->d_pair_gw.p, ctx->d_pair_off.p, ctx->d_cu.p,
@@ -261,6 +262,7 @@ __global__ void spmv_add_kernel(int ns, const int32_t* __restrict__ ptr, const i
 }
 
 void launch_spmv_add(tdbem_ctx* ctx, const double* vals, double scale, const double* xin, double* y) {
+  ProfScope ps(ctx, K_OTHER);
   spmv_add_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, vals,
                                                                     scale, xin, y);
   TDBEM_HIP(hipGetLastError());

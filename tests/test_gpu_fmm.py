@@ -80,3 +80,19 @@ def test_fmm_rejects_bad_options(s3):
         args.update(kw)
         with pytest.raises(P.TDBEMError):
             P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, nt_max=8, **args)
+
+
+def test_fmm_fp32_m2l_products(s3):
+    """Mixed precision: M2L operators and products in FP32 (FP32 accumulation), everything else
+    FP64.  The history sum stays within FP32 rounding of the FP64 oracle FMM."""
+    P = _P()
+    xyz, tri, dt = s3
+    g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=3, p_s=3, p_t=3, m2l_prec=P.M2L_FP32, nt_max=64)
+    R = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 3, 3, 3)
+    u = synth.random_history(g.ns, 30, seed=13)
+    dev = torch.device("cuda")
+    g.set_history(torch.tensor(u[:25], device=dev), None)
+    got = g.fmm_eval(26).cpu().numpy()
+    want = R.history_rhs(26, u, np.zeros_like(u))
+    e = _rel(got, want)
+    assert 1e-12 < e < 1e-4, e
