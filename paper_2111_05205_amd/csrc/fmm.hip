@@ -411,9 +411,18 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T Bs[MB_K][BS_LD];
   __shared__ int src[MB_N], pid[MB_N];
-  const int slot = tiles[3 * blockIdx.x], first = tiles[3 * blockIdx.x + 1], cnt = tiles[3 * blockIdx.x + 2];
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
+  // give each XCD a contiguous range of (row block, column tile) items with the
+  // tiles of one offset adjacent; the second tile of an offset then finds that
+  // row block of U in the XCD's L2.
+  const int total = gridDim.x * gridDim.y;
+  const int w = blockIdx.x + blockIdx.y * gridDim.x;
+  const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
+  const int item = x8 * q8 + min(x8, r8) + w / 8;
+  const int tile = item % gridDim.x, rowblk = item / gridDim.x;
+  const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rb0 = blockIdx.y * (MB_M / 16) + wave * 2;   // this wave: row blocks rb0, rb0+1 (32 rows)
+  const int rb0 = rowblk * (MB_M / 16) + wave * 2;       // this wave: row blocks rb0, rb0+1 (32 rows)
   if (tid < MB_N) {
     const int p = tid < cnt ? pairs_by_slot[first + tid] : -1;
     pid[tid] = p;

@@ -8,7 +8,18 @@
 // Givens rotations and reduction scratch in LDS, and no host round trip is
 // needed.  Orthogonalisation is classical Gram-Schmidt applied twice (CGS2),
 // so each Arnoldi step needs two fused multi-dot reductions.
+//
+// Larger systems use the cooperative variant: NW workgroups of 256 threads,
+// guaranteed co-resident by a cooperative launch, each owning a contiguous
+// slice of rows.  Every reduction goes through per-workgroup partial sums in
+// global memory and a grid barrier; every workgroup then sums the partials in
+// the same order, so the Hessenberg matrix, Givens rotations and stopping
+// decision are bitwise identical in all workgroups (4 barriers per step).
 #include "internal.h"
+
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
 
 namespace tdbem {
 
@@ -196,14 +207,211 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
   }
 }
 
+constexpr int GC_THREADS = 256;
+
+struct CoopShared {
+  double H[GM_MAXM + 1][GM_MAXM];
+  double cs[GM_MAXM], sn[GM_MAXM], g[GM_MAXM + 1], y[GM_MAXM];
+  double red[GC_THREADS / 64][GM_MAXM + 1];
+  double hv[GM_MAXM + 1];
+};
+
+// Sum over the grid of per-thread values part[0..n-1] (n <= GM_MAXM+1): wave and
+// block reduction, per-workgroup partials to gpart[wg][*], grid barrier, then an
+// ordered sum over workgroups into sh.hv (identical in every workgroup).
+__device__ inline void grid_multi_sum(int n, const double* part, double* __restrict__ gpart, CoopShared& sh,
+                                      cooperative_groups::grid_group& grid) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < GM_MAXM + 1; ++k) {
+    if (k < n) {
+      const double v = wave_sum(part[k]);
+      if (lane == 0) sh.red[wid][k] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < n) {
+    double s = 0.0;
+    for (int w = 0; w < GC_THREADS / 64; ++w) s += sh.red[w][threadIdx.x];
+    gpart[blockIdx.x * (GM_MAXM + 1) + threadIdx.x] = s;
+  }
+  __threadfence();
+  grid.sync();
+  if (threadIdx.x < n) {
+    double s = 0.0;
+    for (int w = 0; w < (int)gridDim.x; ++w) s += gpart[w * (GM_MAXM + 1) + threadIdx.x];
+    sh.hv[threadIdx.x] = s;
+  }
+  __syncthreads();
+  grid.sync();  // partials may be overwritten by the next reduction only after everyone has read them
+}
+
+__global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
+    int ns, const int32_t* __restrict__ ap, const int32_t* __restrict__ ac, const double* __restrict__ av,
+    const double* __restrict__ b, double* __restrict__ x, double* __restrict__ V, int m, int maxit, double tol,
+    StepStat* __restrict__ stat, double* __restrict__ gpart) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ CoopShared sh;
+  const int tid = threadIdx.x;
+  const int per = (ns + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(ns, r0 + per);
+  double part[GM_MAXM + 1];
+  part[0] = 0.0;
+  for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += b[i] * b[i];
+  grid_multi_sum(1, part, gpart, sh, grid);
+  const double bnorm = sqrt(sh.hv[0]);
+  int it = 0, flags = 0;
+  double rel = 0.0;
+  if (!(bnorm > 0.0)) {
+    for (int i = r0 + tid; i < r1; i += GC_THREADS) x[i] = 0.0;
+    if (!(bnorm == 0.0)) flags |= 2;
+  } else {
+    const double target = tol * bnorm;
+    for (;;) {
+      double* V0 = V;
+      part[0] = 0.0;
+      for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+        double s = 0.0;
+        for (int k = ap[i]; k < ap[i + 1]; ++k) s += av[k] * x[ac[k]];
+        const double r = b[i] - s;
+        V0[i] = r;
+        part[0] += r * r;
+      }
+      grid_multi_sum(1, part, gpart, sh, grid);
+      const double beta = sqrt(sh.hv[0]);
+      rel = beta / bnorm;
+      if (!(beta > target) || it >= maxit) {
+        if (!(beta == beta)) flags |= 2;
+        break;
+      }
+      for (int i = r0 + tid; i < r1; i += GC_THREADS) V0[i] /= beta;
+      if (tid == 0) {
+        sh.g[0] = beta;
+        for (int k = 1; k <= m; ++k) sh.g[k] = 0.0;
+      }
+      __threadfence();
+      grid.sync();
+      int jlast = -1;
+      for (int j = 0; j < m; ++j) {
+        const double* Vj = V + (size_t)j * ns;
+        double* W = V + (size_t)(j + 1) * ns;
+        for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+          double s = 0.0;
+          for (int k = ap[i]; k < ap[i + 1]; ++k) s += av[k] * Vj[ac[k]];
+          W[i] = s;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+          for (int k = 0; k < GM_MAXM + 1; ++k) part[k] = 0.0;
+          for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+            const double wi = W[i];
+#pragma unroll
+            for (int k = 0; k < GM_MAXM; ++k)
+              if (k <= j) part[k] += V[(size_t)k * ns + i] * wi;
+          }
+          grid_multi_sum(j + 1, part, gpart, sh, grid);
+          if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
+          for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+            double wi = W[i];
+            for (int k = 0; k <= j; ++k) wi -= sh.hv[k] * V[(size_t)k * ns + i];
+            W[i] = wi;
+          }
+        }
+        part[0] = 0.0;
+        for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += W[i] * W[i];
+        grid_multi_sum(1, part, gpart, sh, grid);
+        const double hn = sqrt(sh.hv[0]);
+        if (hn > 0.0)
+          for (int i = r0 + tid; i < r1; i += GC_THREADS) W[i] /= hn;
+        if (tid == 0) {
+          sh.H[j + 1][j] = hn;
+          for (int k = 0; k < j; ++k) {
+            const double a = sh.H[k][j], c2 = sh.H[k + 1][j];
+            sh.H[k][j] = sh.cs[k] * a + sh.sn[k] * c2;
+            sh.H[k + 1][j] = -sh.sn[k] * a + sh.cs[k] * c2;
+          }
+          const double a = sh.H[j][j], c2 = sh.H[j + 1][j];
+          const double den = sqrt(a * a + c2 * c2);
+          const double cj = den > 0.0 ? a / den : 1.0, sj = den > 0.0 ? c2 / den : 0.0;
+          sh.cs[j] = cj;
+          sh.sn[j] = sj;
+          sh.H[j][j] = cj * a + sj * c2;
+          sh.H[j + 1][j] = 0.0;
+          sh.g[j + 1] = -sj * sh.g[j];
+          sh.g[j] = cj * sh.g[j];
+        }
+        __threadfence();
+        grid.sync();  // W normalised everywhere; every workgroup's Givens state updated
+        ++it;
+        jlast = j;
+        rel = fabs(sh.g[j + 1]) / bnorm;
+        if (!(fabs(sh.g[j + 1]) > target) || it >= maxit || !(hn > 0.0)) break;
+      }
+      if (tid == 0) {
+        for (int k = jlast; k >= 0; --k) {
+          double s2 = sh.g[k];
+          for (int l = k + 1; l <= jlast; ++l) s2 -= sh.H[k][l] * sh.y[l];
+          sh.y[k] = s2 / sh.H[k][k];
+        }
+      }
+      __syncthreads();
+      for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+        double xi = x[i];
+        for (int k = 0; k <= jlast; ++k) xi += sh.y[k] * V[(size_t)k * ns + i];
+        x[i] = xi;
+      }
+      __threadfence();
+      grid.sync();
+      if (!(rel * bnorm > target) || it >= maxit) {
+        if (!(rel == rel)) flags |= 2;
+        break;
+      }
+    }
+    if (rel * bnorm > target) flags |= 1;
+  }
+  if (blockIdx.x == 0 && tid == 0 && stat) {
+    stat->iters = it;
+    stat->resid = rel;
+    stat->flags = flags;
+  }
+}
+
 void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat) {
   ProfScope ps(ctx, K_GMRES);
   int m = ctx->opts.gmres_restart;
   if (m > GM_MAXM) m = GM_MAXM;
   if (m < 1) m = 1;
-  gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, b, x,
-                                                   ctx->d_V.p, m, ctx->opts.gmres_maxiter, ctx->opts.gmres_tol, stat);
-  TDBEM_HIP(hipGetLastError());
+  const int nwg = ctx->gmres_wg;
+  if (nwg <= 1) {
+    gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, b, x,
+                                                     ctx->d_V.p, m, ctx->opts.gmres_maxiter, ctx->opts.gmres_tol,
+                                                     stat);
+    TDBEM_HIP(hipGetLastError());
+    return;
+  }
+  int ns = ctx->ns, maxit = ctx->opts.gmres_maxiter;
+  double tol = ctx->opts.gmres_tol;
+  const int32_t* ap = ctx->d_a_ptr.p;
+  const int32_t* ac = ctx->d_a_col.p;
+  const double* av = ctx->d_a_val.p;
+  double* V = ctx->d_V.p;
+  double* gp = ctx->d_gpart.p;
+  void* args[] = {&ns, &ap, &ac, &av, &b, &x, &V, &m, &maxit, &tol, &stat, &gp};
+  TDBEM_HIP(hipLaunchCooperativeKernel((const void*)gmres_coop_kernel, dim3(nwg), dim3(GC_THREADS), args, 0,
+                                       ctx->stream));
+}
+
+int gmres_workgroups(int ns) {
+  // one workgroup per 512 rows, capped by what is guaranteed co-resident
+  int want = (ns + 511) / 512;
+  if (ns <= 2048) return 1;
+  int dev = 0, ncu = 0, per = 0;
+  TDBEM_HIP(hipGetDevice(&dev));
+  TDBEM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  TDBEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)gmres_coop_kernel, GC_THREADS, 0));
+  const int cap = std::max(1, std::min(ncu * std::max(per, 1), ncu));
+  return std::max(1, std::min(want, cap));
 }
 
 }  // namespace tdbem

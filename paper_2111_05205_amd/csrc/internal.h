@@ -109,7 +109,8 @@ struct tdbem_ctx {
   bool hist_q = false;  // any non-zero q stored
 
   // work
-  tdbem::DevBuf<double> d_b, d_x, d_V, d_forc, d_zero;
+  tdbem::DevBuf<double> d_b, d_x, d_V, d_forc, d_zero, d_gpart;
+  int gmres_wg = 1;  // workgroups of the per-step solve (1: single-workgroup kernel)
   tdbem::DevBuf<tdbem::StepStat> d_stat;
 
   tdbem::Fmm* fmm = nullptr;
@@ -152,6 +153,7 @@ void upload_gl_rule();
 
 // gmres.hip
 void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat);
+int gmres_workgroups(int ns);
 
 // api.hip
 void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc, int a0, int n, double* out);

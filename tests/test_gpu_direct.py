@@ -149,3 +149,18 @@ def test_error_paths_forced_from_host(sphere2):
     assert e.value.code == P._native.E_STATE
     with pytest.raises(P.TDBEMError):
         s2.fmm_eval(7)
+
+
+def test_march_multi_workgroup_solver_matches_oracle():
+    """Ns > 2048 selects the cooperative multi-workgroup GMRES; same parity bar."""
+    P = _P()
+    xyz, tri = synth.geodesic_sphere(11)             # 2420 faces
+    dt = synth.mean_edge_length(xyz, tri)
+    nt = 20
+    inc = synth.incident_params(xyz, seed=2)
+    s = P.TDBEM(xyz, tri, 1.0, dt, 2, P.BMBIE, P.NEUMANN, nt_max=nt)
+    x, info = s.run(nt, inc=inc)
+    ref = mot.DirectMOT(xyz, tri, 1.0, dt, 2, mot.BMBIE, mot.NEUMANN)
+    u, q = ref.run(nt, mot.incident(ref.geom, inc, 1.0, dt, nt, mot.BMBIE))
+    assert info["max_resid"] < 1e-11
+    assert _rel(x.cpu().numpy(), u) < 1e-10
