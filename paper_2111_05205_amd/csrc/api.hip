@@ -307,7 +307,7 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     ctx->d_V.alloc((size_t)(std::min(ctx->opts.gmres_restart, 32) + 1) * ns);
     ctx->d_stat.alloc(ctx->nt_max);
     ctx->gmres_wg = gmres_workgroups(ns);
-    ctx->d_gpart.alloc((size_t)std::max(ctx->gmres_wg, 1) * 33);
+    ctx->d_gpart.alloc((size_t)2 * std::max(ctx->gmres_wg, 1) * 33);
     TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_zero.p, 0, ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));

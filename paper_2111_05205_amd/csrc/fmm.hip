@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
                                                        const int32_t* __restrict__ il_src, const T* __restrict__ Uf,
                                                        const double* __restrict__ mom, T* __restrict__ stage) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T Bs[MB_K][BS_LD];
+  __shared__ T Bs[2][MB_K][BS_LD];
   __shared__ int src[MB_N], pid[MB_N];
   // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
   // give each XCD a contiguous range of (row block, column tile) items with the
@@ -442,40 +442,45 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   const int bc = tid >> 1, bk = (tid & 1) * 8;
   const int bsrc = src[bc];
   const double* mrow = mom + (int64_t)(bsrc >= 0 ? bsrc : 0) * P;
-  // prefetch of the A fragments of one K step (4 k-blocks x 2 row blocks)
-  T fa[2][4];
-  auto loadA = [&](int kb0) {
+  // one K step ahead in registers: A fragments (4 k-blocks x 2 row blocks) and
+  // this thread's 8 moment values of the B tile
+  T fa[2][4], fb[8];
+  auto load = [&](int k0) {
+    const int kb0 = k0 >> 2;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kb = kb0 + q;
       fa[0][q] = (rlive0 && kb < KB) ? A0[(int64_t)kb * 64] : T(0);
       fa[1][q] = (rlive1 && kb < KB) ? A1[(int64_t)kb * 64] : T(0);
     }
-  };
-  loadA(0);
-  for (int k0 = 0; k0 < P; k0 += MB_K) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + bk + i;
-      Bs[bk + i][bc] = (bsrc >= 0 && k < P) ? (T)mrow[k] : T(0);
+      fb[i] = (bsrc >= 0 && k < P) ? (T)mrow[k] : T(0);
     }
-    __syncthreads();
+  };
+  load(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < P; k0 += MB_K) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Bs[buf][bk + i][bc] = fb[i];
+    __syncthreads();   // tile k0 complete; every wave is done with the buffer written two steps ago
     T ca[2][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) { ca[0][q] = fa[0][q]; ca[1][q] = fa[1][q]; }
-    if (k0 + MB_K < P) loadA((k0 + MB_K) >> 2);
+    if (k0 + MB_K < P) load(k0 + MB_K);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) {
         if (cb < ncb) {
-          const T bf = Bs[4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
+          const T bf = Bs[buf][4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
           acc[0][cb] = Mfma<T>::op(ca[0][q], bf, acc[0][cb]);
           acc[1][cb] = Mfma<T>::op(ca[1][q], bf, acc[1][cb]);
         }
       }
     }
-    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h)

@@ -219,8 +219,12 @@ struct CoopShared {
 // Sum over the grid of per-thread values part[0..n-1] (n <= GM_MAXM+1): wave and
 // block reduction, per-workgroup partials to gpart[wg][*], grid barrier, then an
 // ordered sum over workgroups into sh.hv (identical in every workgroup).
-__device__ inline void grid_multi_sum(int n, const double* part, double* __restrict__ gpart, CoopShared& sh,
-                                      cooperative_groups::grid_group& grid) {
+__device__ inline void grid_multi_sum(int n, const double* part, double* __restrict__ gpart_all, int& flip,
+                                      CoopShared& sh, cooperative_groups::grid_group& grid) {
+  // two partial buffers used alternately: a buffer is rewritten only two
+  // reductions later, after every workgroup has passed the barrier in between
+  double* __restrict__ gpart = gpart_all + (size_t)flip * gridDim.x * (GM_MAXM + 1);
+  flip ^= 1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
 #pragma unroll
@@ -244,7 +248,6 @@ __device__ inline void grid_multi_sum(int n, const double* part, double* __restr
     sh.hv[threadIdx.x] = s;
   }
   __syncthreads();
-  grid.sync();  // partials may be overwritten by the next reduction only after everyone has read them
 }
 
 __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
@@ -257,9 +260,10 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
   const int per = (ns + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(ns, r0 + per);
   double part[GM_MAXM + 1];
+  int flip = 0;
   part[0] = 0.0;
   for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += b[i] * b[i];
-  grid_multi_sum(1, part, gpart, sh, grid);
+  grid_multi_sum(1, part, gpart, flip, sh, grid);
   const double bnorm = sqrt(sh.hv[0]);
   int it = 0, flags = 0;
   double rel = 0.0;
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
         V0[i] = r;
         part[0] += r * r;
       }
-      grid_multi_sum(1, part, gpart, sh, grid);
+      grid_multi_sum(1, part, gpart, flip, sh, grid);
       const double beta = sqrt(sh.hv[0]);
       rel = beta / bnorm;
       if (!(beta > target) || it >= maxit) {
@@ -310,7 +314,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
             for (int k = 0; k < GM_MAXM; ++k)
               if (k <= j) part[k] += V[(size_t)k * ns + i] * wi;
           }
-          grid_multi_sum(j + 1, part, gpart, sh, grid);
+          grid_multi_sum(j + 1, part, gpart, flip, sh, grid);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
           for (int i = r0 + tid; i < r1; i += GC_THREADS) {
             double wi = W[i];
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
         }
         part[0] = 0.0;
         for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += W[i] * W[i];
-        grid_multi_sum(1, part, gpart, sh, grid);
+        grid_multi_sum(1, part, gpart, flip, sh, grid);
         const double hn = sqrt(sh.hv[0]);
         if (hn > 0.0)
           for (int i = r0 + tid; i < r1; i += GC_THREADS) W[i] /= hn;
