@@ -161,6 +161,7 @@ def main():
                       "mode": "fmm" if use_fmm else "direct", "ns": ns, "nt": nt, "d": info["d"],
                       "mu": info["mu"], "m_leaf": info["m_leaf"], "near_pairs": info["near_pairs"],
                       "il_pairs": info["il_pairs"][: (info["depth"] or 0) + 1],
+                      "m2l_tile_variant": info["m2l_variant"][: (info["depth"] or 0) + 1],
                       "gmres_iters_per_march": iters // args.steps, "setup_ms": round(info["setup_ms"], 1)},
            "roofline": roof}
 

@@ -103,6 +103,7 @@ class TDBEM:
         self._check(self._L.tdbem_get_info(self._h, ctypes.byref(i)))
         out = {k: getattr(i, k) for k, _ in N.Info._fields_}
         out["il_pairs"] = list(i.il_pairs)
+        out["m2l_variant"] = list(i.m2l_variant)
         return out
 
     def reset(self):

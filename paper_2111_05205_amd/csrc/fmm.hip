@@ -52,9 +52,10 @@ struct FmmLevel {
   std::vector<std::array<int, 3>> slot_off; // offset vector of each matrix slot present at this level
   // device
   DevBuf<int32_t> d_il_ptr, d_il_src, d_parent, d_octant, d_child_ptr, d_child;
-  DevBuf<int32_t> d_tiles;                  // GEMM column tiles: (slot, first, count) triples
+  DevBuf<int32_t> d_tiles128, d_tiles64;    // GEMM column tiles (slot, first, count), widths 128 / 64
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
-  int ntiles = 0;
+  int ntiles128 = 0, ntiles64 = 0;
+  int variant = 0;                          // chosen M2L tile variant (autotuned)
   DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
   DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
   DevBuf<float> d_U32, d_stage32;           // FP32 operators and staging (mixed-precision M2L)
@@ -363,8 +364,8 @@ __global__ void l2l_kernel(int ps, int pt, int R, int kp, const int32_t* __restr
 // B[k][j] in lane j + 16 k.  The operators are stored in that fragment order,
 // so each wave streams its A fragments from memory with fully coalesced
 // 64-lane loads (one K step ahead); the gathered moments go through LDS.
-constexpr int MB_M = 128, MB_N = 128, MB_K = 16;
-constexpr int BS_LD = MB_N + 4;  // LDS row stride of the moment tile
+constexpr int MB_M = 128;        // operator rows per workgroup (4 waves x 32)
+constexpr int MB_NMAX = 128;     // widest column tile
 
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
@@ -403,14 +404,19 @@ __global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double*
   Uf[(int64_t)slot * per + idx] = (T)v;
 }
 
-template <class T>
+template <class T, int NCB, int KS>
 __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, int KB, const int32_t* __restrict__ tiles,
                                                        const int32_t* __restrict__ pairs_by_slot,
                                                        const int32_t* __restrict__ il_src, const T* __restrict__ Uf,
                                                        const double* __restrict__ mom, T* __restrict__ stage) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T Bs[2][MB_K][BS_LD];
-  __shared__ int src[MB_N], pid[MB_N];
+  constexpr int BN = NCB * 16;              // columns (interaction pairs) per tile
+  constexpr int LD = BN + 4;                // LDS row stride of the moment tile
+  constexpr int BPT = KS * BN / 256;        // moment values loaded per thread per K step
+  constexpr int TPC = 256 / BN;             // threads per column
+  constexpr int QS = KS / 4;                // MFMA k-substeps per K step
+  __shared__ T Bs[2][KS][LD];
+  __shared__ int src[BN], pid[BN];
   // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
   // give each XCD a contiguous range of (row block, column tile) items with the
   // tiles of one offset adjacent; the second tile of an offset then finds that
@@ -423,7 +429,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rb0 = rowblk * (MB_M / 16) + wave * 2;       // this wave: row blocks rb0, rb0+1 (32 rows)
-  if (tid < MB_N) {
+  if (tid < BN) {
     const int p = tid < cnt ? pairs_by_slot[first + tid] : -1;
     pid[tid] = p;
     src[tid] = p >= 0 ? il_src[p] : -1;
@@ -434,45 +440,45 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   const T* A1 = A0 + (int64_t)KB * 64;                                         // row block rb0+1
   const bool rlive0 = rb0 < RB, rlive1 = rb0 + 1 < RB;
   const int ncb = (cnt + 15) >> 4;                                             // live column blocks
-  acc_t acc[2][8];
+  acc_t acc[2][NCB];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-  const int bc = tid >> 1, bk = (tid & 1) * 8;
+    for (int j = 0; j < NCB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  const int bc = tid / TPC, bk = (tid % TPC) * BPT;
   const int bsrc = src[bc];
   const double* mrow = mom + (int64_t)(bsrc >= 0 ? bsrc : 0) * P;
-  // one K step ahead in registers: A fragments (4 k-blocks x 2 row blocks) and
-  // this thread's 8 moment values of the B tile
-  T fa[2][4], fb[8];
+  // one K step ahead in registers: A fragments (QS k-blocks x 2 row blocks) and
+  // this thread's BPT moment values of the B tile
+  T fa[2][QS], fb[BPT];
   auto load = [&](int k0) {
     const int kb0 = k0 >> 2;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QS; ++q) {
       const int kb = kb0 + q;
       fa[0][q] = (rlive0 && kb < KB) ? A0[(int64_t)kb * 64] : T(0);
       fa[1][q] = (rlive1 && kb < KB) ? A1[(int64_t)kb * 64] : T(0);
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < BPT; ++i) {
       const int k = k0 + bk + i;
       fb[i] = (bsrc >= 0 && k < P) ? (T)mrow[k] : T(0);
     }
   };
   load(0);
   int buf = 0;
-  for (int k0 = 0; k0 < P; k0 += MB_K) {
+  for (int k0 = 0; k0 < P; k0 += KS) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Bs[buf][bk + i][bc] = fb[i];
+    for (int i = 0; i < BPT; ++i) Bs[buf][bk + i][bc] = fb[i];
     __syncthreads();   // tile k0 complete; every wave is done with the buffer written two steps ago
-    T ca[2][4];
+    T ca[2][QS];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) { ca[0][q] = fa[0][q]; ca[1][q] = fa[1][q]; }
-    if (k0 + MB_K < P) load(k0 + MB_K);
+    for (int q = 0; q < QS; ++q) { ca[0][q] = fa[0][q]; ca[1][q] = fa[1][q]; }
+    if (k0 + KS < P) load(k0 + KS);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QS; ++q) {
 #pragma unroll
-      for (int cb = 0; cb < 8; ++cb) {
+      for (int cb = 0; cb < NCB; ++cb) {
         if (cb < ncb) {
           const T bf = Bs[buf][4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
           acc[0][cb] = Mfma<T>::op(ca[0][q], bf, acc[0][cb]);
@@ -485,7 +491,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int cb = 0; cb < 8; ++cb) {
+    for (int cb = 0; cb < NCB; ++cb) {
       if (cb >= ncb) continue;
       const int p = pid[cb * 16 + (lane & 15)];
 #pragma unroll
@@ -494,6 +500,26 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
         if (p >= 0 && row < GP) stage[(int64_t)p * GP + row] = acc[h][cb][r];
       }
     }
+}
+
+// Tile variants of the M2L products: (columns per tile, K step).  The choice per
+// level is made once per context by timing every variant (autotuning).
+constexpr int M2L_VARIANTS = 4;
+static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64};
+static const int kVariantKs[M2L_VARIANTS] = {16, 32, 16, 32};
+
+template <class T>
+static void launch_m2l_variant(int v, dim3 grid, hipStream_t st, int P, int GP, int RB, int KB, const int32_t* tiles,
+                               const int32_t* pbs, const int32_t* il_src, const T* Uf, const double* mom, T* stage) {
+  switch (v) {
+    case 0: m2l_mfma_kernel<T, 8, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    case 1:  // the FP64 tile would need 68 KB of LDS: FP64 uses the K=16 kernel here
+      if (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage);
+      else m2l_mfma_kernel<T, 8, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage);
+      break;
+    case 2: m2l_mfma_kernel<T, 4, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    default: m2l_mfma_kernel<T, 4, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+  }
 }
 
 // Reduce the staged products per target cell: grid (ncell, G, ceil(P/256)).
@@ -737,6 +763,47 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
   if (!v.empty()) TDBEM_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+static void launch_m2l_level(const Fmm* f, const FmmLevel& L, int P, int G, hipStream_t st, int variant = -1) {
+  const int v = variant >= 0 ? variant : L.variant;
+  const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
+  const bool wide = kVariantCols[v] == 128;
+  dim3 grid(wide ? L.ntiles128 : L.ntiles64, (G * P + MB_M - 1) / MB_M);
+  const int32_t* tl = wide ? L.d_tiles128.p : L.d_tiles64.p;
+  if (f->f32)
+    launch_m2l_variant<float>(v, grid, st, P, G * P, RB, KB, tl, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_U32.p,
+                              L.d_mom.p, L.d_stage32.p);
+  else
+    launch_m2l_variant<double>(v, grid, st, P, G * P, RB, KB, tl, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_Uf.p,
+                               L.d_mom.p, L.d_stage.p);
+  TDBEM_HIP(hipGetLastError());
+}
+
+// Pick the fastest tile variant per level: each variant runs a few times on the
+// level's real interaction lists (moments are zero at this point; the work does
+// not depend on their values) and is timed with HIP events.
+static void autotune_m2l(Fmm* f, int P, int G, hipStream_t st) {
+  hipEvent_t e0, e1;
+  TDBEM_HIP(hipEventCreate(&e0));
+  TDBEM_HIP(hipEventCreate(&e1));
+  for (int l = 2; l <= f->D; ++l) {
+    FmmLevel& L = f->lev[l];
+    if (L.npair == 0) continue;
+    float best = 1e30f;
+    for (int v = 0; v < M2L_VARIANTS; ++v) {
+      launch_m2l_level(f, L, P, G, st, v);  // warm-up
+      TDBEM_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) launch_m2l_level(f, L, P, G, st, v);
+      TDBEM_HIP(hipEventRecord(e1, st));
+      TDBEM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; L.variant = v; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 Fmm* fmm_create(tdbem_ctx* ctx) {
   const tdbem_opts& o = ctx->opts;
   if (o.depth < 2 || o.depth > 12) throw Error(TDBEM_E_INVAL, "depth must be in [2, 12]");
@@ -837,19 +904,24 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       const int nslot = (int)L.slot_off.size();
       std::vector<std::vector<int32_t>> by(nslot);
       for (int64_t p = 0; p < L.npair; ++p) by[L.il_slot[p]].push_back((int32_t)p);
-      std::vector<int32_t> flat, tiles;
+      std::vector<int32_t> flat, tiles128, tiles64;
       for (int sl = 0; sl < nslot; ++sl) {
         const int first = (int)flat.size();
         flat.insert(flat.end(), by[sl].begin(), by[sl].end());
-        for (int s0 = 0; s0 < (int)by[sl].size(); s0 += MB_N) {
-          tiles.push_back(sl);
-          tiles.push_back(first + s0);
-          tiles.push_back(std::min(MB_N, (int)by[sl].size() - s0));
+        for (int width : {128, 64}) {
+          std::vector<int32_t>& tl = width == 128 ? tiles128 : tiles64;
+          for (int s0 = 0; s0 < (int)by[sl].size(); s0 += width) {
+            tl.push_back(sl);
+            tl.push_back(first + s0);
+            tl.push_back(std::min(width, (int)by[sl].size() - s0));
+          }
         }
       }
-      L.ntiles = (int)tiles.size() / 3;
+      L.ntiles128 = (int)tiles128.size() / 3;
+      L.ntiles64 = (int)tiles64.size() / 3;
+      upload(L.d_tiles128, tiles128, st);
+      upload(L.d_tiles64, tiles64, st);
       upload(L.d_pairs_by_slot, flat, st);
-      upload(L.d_tiles, tiles, st);
       std::vector<int32_t> so;
       for (auto& v : L.slot_off) { so.push_back(v[0]); so.push_back(v[1]); so.push_back(v[2]); }
       DevBuf<int32_t> d_so;
@@ -889,6 +961,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       TDBEM_HIP(hipStreamSynchronize(st));  // temporaries (d_so) are released at scope end
     }
     TDBEM_HIP(hipStreamSynchronize(st));
+    autotune_m2l(f, P, G, st);
     return f;
   } catch (...) {
     delete f;
@@ -972,15 +1045,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     if (L.npair > 0) {
       {
         ProfScope ps(ctx, K_M2L_GEMM);
-        dim3 g1(L.ntiles, (G * P + MB_M - 1) / MB_M);
-        const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
-        if (f->f32)
-          m2l_mfma_kernel<float><<<g1, 256, 0, st>>>(P, G * P, RB, KB, L.d_tiles.p, L.d_pairs_by_slot.p,
-                                                      L.d_il_src.p, L.d_U32.p, L.d_mom.p, L.d_stage32.p);
-        else
-          m2l_mfma_kernel<double><<<g1, 256, 0, st>>>(P, G * P, RB, KB, L.d_tiles.p, L.d_pairs_by_slot.p,
-                                                       L.d_il_src.p, L.d_Uf.p, L.d_mom.p, L.d_stage.p);
-        TDBEM_HIP(hipGetLastError());
+        launch_m2l_level(f, L, P, G, st);
       }
       ProfScope ps(ctx, K_M2L_RED);
       dim3 g2(L.ncell, G, (P + 255) / 256);
@@ -1032,6 +1097,7 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   int64_t bytes = 0;
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
+    info->m2l_variant[l] = f->lev[l].variant;
     bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
   }
   info->m2l_matrix_bytes = bytes;
