@@ -52,9 +52,9 @@ struct FmmLevel {
   std::vector<std::array<int, 3>> slot_off; // offset vector of each matrix slot present at this level
   // device
   DevBuf<int32_t> d_il_ptr, d_il_src, d_parent, d_octant, d_child_ptr, d_child;
-  DevBuf<int32_t> d_tiles128, d_tiles64;    // GEMM column tiles (slot, first, count), widths 128 / 64
+  DevBuf<int32_t> d_tiles128, d_tiles64, d_tiles32;  // GEMM column tiles (slot, first, count) by width
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
-  int ntiles128 = 0, ntiles64 = 0;
+  int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
   int variant = 0;                          // chosen M2L tile variant (autotuned)
   DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
   DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
@@ -504,9 +504,9 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
 
 // Tile variants of the M2L products: (columns per tile, K step).  The choice per
 // level is made once per context by timing every variant (autotuning).
-constexpr int M2L_VARIANTS = 4;
-static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64};
-static const int kVariantKs[M2L_VARIANTS] = {16, 32, 16, 32};
+constexpr int M2L_VARIANTS = 6;
+static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64, 32, 32};
+static const int kVariantKs[M2L_VARIANTS] = {16, 32, 16, 32, 16, 32};
 
 template <class T>
 static void launch_m2l_variant(int v, dim3 grid, hipStream_t st, int P, int GP, int RB, int KB, const int32_t* tiles,
@@ -518,7 +518,9 @@ static void launch_m2l_variant(int v, dim3 grid, hipStream_t st, int P, int GP, 
       else m2l_mfma_kernel<T, 8, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage);
       break;
     case 2: m2l_mfma_kernel<T, 4, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
-    default: m2l_mfma_kernel<T, 4, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    case 3: m2l_mfma_kernel<T, 4, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    case 4: m2l_mfma_kernel<T, 2, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    default: m2l_mfma_kernel<T, 2, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
   }
 }
 
@@ -766,9 +768,9 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
 static void launch_m2l_level(const Fmm* f, const FmmLevel& L, int P, int G, hipStream_t st, int variant = -1) {
   const int v = variant >= 0 ? variant : L.variant;
   const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
-  const bool wide = kVariantCols[v] == 128;
-  dim3 grid(wide ? L.ntiles128 : L.ntiles64, (G * P + MB_M - 1) / MB_M);
-  const int32_t* tl = wide ? L.d_tiles128.p : L.d_tiles64.p;
+  const int cols = kVariantCols[v];
+  dim3 grid(cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32, (G * P + MB_M - 1) / MB_M);
+  const int32_t* tl = cols == 128 ? L.d_tiles128.p : cols == 64 ? L.d_tiles64.p : L.d_tiles32.p;
   if (f->f32)
     launch_m2l_variant<float>(v, grid, st, P, G * P, RB, KB, tl, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_U32.p,
                               L.d_mom.p, L.d_stage32.p);
@@ -904,12 +906,12 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       const int nslot = (int)L.slot_off.size();
       std::vector<std::vector<int32_t>> by(nslot);
       for (int64_t p = 0; p < L.npair; ++p) by[L.il_slot[p]].push_back((int32_t)p);
-      std::vector<int32_t> flat, tiles128, tiles64;
+      std::vector<int32_t> flat, tiles128, tiles64, tiles32;
       for (int sl = 0; sl < nslot; ++sl) {
         const int first = (int)flat.size();
         flat.insert(flat.end(), by[sl].begin(), by[sl].end());
-        for (int width : {128, 64}) {
-          std::vector<int32_t>& tl = width == 128 ? tiles128 : tiles64;
+        for (int width : {128, 64, 32}) {
+          std::vector<int32_t>& tl = width == 128 ? tiles128 : width == 64 ? tiles64 : tiles32;
           for (int s0 = 0; s0 < (int)by[sl].size(); s0 += width) {
             tl.push_back(sl);
             tl.push_back(first + s0);
@@ -919,8 +921,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       }
       L.ntiles128 = (int)tiles128.size() / 3;
       L.ntiles64 = (int)tiles64.size() / 3;
+      L.ntiles32 = (int)tiles32.size() / 3;
       upload(L.d_tiles128, tiles128, st);
       upload(L.d_tiles64, tiles64, st);
+      upload(L.d_tiles32, tiles32, st);
       upload(L.d_pairs_by_slot, flat, st);
       std::vector<int32_t> so;
       for (auto& v : L.slot_off) { so.push_back(v[0]); so.push_back(v[1]); so.push_back(v[2]); }
