@@ -55,6 +55,11 @@ typedef enum { TDBEM_OBIE = 0, TDBEM_BMBIE = 1 } tdbem_bie;          /* eq. bie 
 typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1 } tdbem_bc;    /* u given (q unknown) / q given (u unknown) */
 typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1 } tdbem_m2l_prec;
 typedef enum { TDBEM_INC_GAUSS_MOD = 0, TDBEM_INC_RAISED_COS = 1 } tdbem_inc_kind;
+/* Starting point of the per-step GMRES solve (the paper names no solver):
+ * EXTRAP quadratic extrapolation of the last three solved rows (default),
+ * ZERO, PREV the previous row, MLP the learned guess (tdbem_mlp_load; falls
+ * back to EXTRAP for the first four rows or when no network is loaded). */
+typedef enum { TDBEM_GUESS_EXTRAP = 0, TDBEM_GUESS_ZERO = 1, TDBEM_GUESS_PREV = 2, TDBEM_GUESS_MLP = 3 } tdbem_guess;
 
 typedef struct {
   int32_t nv, nt;        /* vertices, triangles */
@@ -72,6 +77,7 @@ typedef struct {
   int gmres_restart; /* default 30 */
   int gmres_maxiter; /* default 300 */
   int nt_max;        /* largest Nt the context will march (sizes the history), default 4096 */
+  int guess;         /* tdbem_guess */
 } tdbem_opts;
 
 typedef struct {
@@ -93,6 +99,7 @@ typedef struct {
   int max_iters;        /* largest per-step iteration count */
   double max_resid;     /* largest final relative residual */
   double march_ms;      /* wall time of the march on the context stream (HIP events) */
+  int guesses_rejected; /* steps whose starting point had a larger residual than zero (solve restarted from 0) */
 } tdbem_run_info;
 
 typedef struct {
@@ -181,13 +188,82 @@ int tdbem_near_row(struct tdbem_ctx *ctx, int i, int cap, int32_t *j_out, int32_
 /* Kernel timing.  While enabled, every kernel launch of the context is
  * bracketed by HIP events on the context stream and attributed to a category:
  * 0 near-field history sum, 1 GMRES solve, 2 L2P, 3 P2M (with densities),
- * 4 M2L products, 5 M2L reduction + recurrence, 6 M2M, 7 L2L, 8 other.
+ * 4 M2L products, 5 M2L reduction + recurrence, 6 M2M, 7 L2L, 8 other,
+ * 9 learned guess (scale, features, network, proposal).
  * tdbem_profile(ctx, 1) clears the accumulators; tdbem_profile_read() waits
  * for the stream and writes per-category total milliseconds and launch counts
  * (arrays of n <= 16 entries). */
-#define TDBEM_PROF_KINDS 9
+#define TDBEM_PROF_KINDS 10
 int tdbem_profile(struct tdbem_ctx *ctx, int enable);
 int tdbem_profile_read(struct tdbem_ctx *ctx, double *ms, int64_t *launches, int n);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess (not part of the paper: the per-step system of eq.
+ * linear is solved by GMRES here, and a small network proposes where each
+ * solve starts; GMRES still runs to its tolerance, so the solution does not
+ * depend on the guess).
+ *
+ * Network: per element, 12 inputs -> three ReLU layers of width 256 -> one
+ * output.  Weights and every layer input are rounded to bfloat16 (nearest,
+ * ties to even) before entering a product; products are accumulated in FP32
+ * on the matrix cores; biases are FP32.
+ *
+ * Parameters: one packed FP32 vector of TDBEM_MLP_NPARAM floats, blocks in
+ * this order, W[o][i] mapping input i to output o (row-major):
+ *   W1 [256][16] (input columns 12..15 are padding and should stay 0), b1 [256],
+ *   W2 [256][256], b2 [256], W3 [256][256], b3 [256], W4 [256], b4 [1].
+ * Features (dev_feat): n x 16 FP32 per element, columns 12..15 ignored:
+ *   0..3  x^{beta-1..beta-4} / s  (the last four solved rows of the unknown)
+ *   4     (b_i / A_ii) / s        (right-hand side of the step, Jacobi-scaled)
+ *   5..7  outward unit normal
+ *   8     area / h^2              (h = mean edge length)
+ *   9..11 (centroid - bounding-box centre) / R   (R = largest vertex distance from it)
+ * with s the root mean square of the five scaled density columns.  The output
+ * y proposes x^beta = x^{beta-1} + s y; the training target is
+ * (x^beta - x^{beta-1}) / s.
+ * All calls below enqueue on hip_stream (NULL = null stream) and return
+ * after that stream has finished them; every pointer is caller-owned. */
+#define TDBEM_MLP_IN 12
+#define TDBEM_MLP_IN_PAD 16
+#define TDBEM_MLP_WIDTH 256
+#define TDBEM_MLP_NPARAM 136193
+
+/* Forward pass over n rows: dev_y (n) = network(dev_feat (n x 16)).
+ * dev_act: NULL, or 3 x n x 256 bf16 (uint16) that receives the rounded
+ * hidden activations h1, h2, h3 for tdbem_mlp_backward. */
+int tdbem_mlp_forward(const float *dev_params, int n, const float *dev_feat, float *dev_y,
+                      uint16_t *dev_act, void *hip_stream);
+
+/* FP32 floats of workspace tdbem_mlp_backward needs for n rows. */
+size_t tdbem_mlp_workspace_floats(int n);
+
+/* Gradient of sum_r dy_r y_r with respect to the parameters (rounding taken
+ * as the identity), written to dev_grad (TDBEM_MLP_NPARAM floats, overwritten).
+ * dev_act from the forward pass of the same parameters and features.
+ * dev_work: tdbem_mlp_workspace_floats(n) floats.  Deterministic. */
+int tdbem_mlp_backward(const float *dev_params, int n, const float *dev_feat, const uint16_t *dev_act,
+                       const float *dev_dy, float *dev_grad, float *dev_work, size_t work_floats,
+                       void *hip_stream);
+
+/* Mean squared error over n rows: dev_loss[0] = mean (y - t)^2 and
+ * dev_dy = 2 (y - t) / n.  Deterministic. */
+int tdbem_mlp_mse(int n, const float *dev_y, const float *dev_t, float *dev_dy, float *dev_loss,
+                  void *hip_stream);
+
+/* One Adam step (number t >= 1, bias-corrected) on TDBEM_MLP_NPARAM
+ * parameters with first/second moment buffers dev_m, dev_v (zero before t = 1). */
+int tdbem_mlp_adam_step(float *dev_params, const float *dev_grad, float *dev_m, float *dev_v, int t, float lr,
+                        float beta1, float beta2, float eps, void *hip_stream);
+
+/* Copy a parameter vector into the context; with opts.guess = TDBEM_GUESS_MLP
+ * the march starts each solve from the network's proposal (rows beta >= 4). */
+int tdbem_mlp_load(struct tdbem_ctx *ctx, const float *dev_params);
+
+/* Record training pairs during later steps: for every solved row beta >= 4,
+ * dev_feat + beta*Ns*16 receives the features and dev_target + beta*Ns the
+ * target (caller-owned, nt_max x Ns x 16 and nt_max x Ns FP32; other rows are
+ * not written).  NULL, NULL stops recording. */
+int tdbem_mlp_record(struct tdbem_ctx *ctx, float *dev_feat, float *dev_target);
 
 #ifdef __cplusplus
 }

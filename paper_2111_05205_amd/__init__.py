@@ -11,10 +11,11 @@ import ctypes
 import numpy as np
 
 from . import _native as N
-from ._native import (BMBIE, DIRICHLET, INC_GAUSS_MOD, INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
+from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
+                      INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
 
 __all__ = ["TDBEM", "TDBEMError", "incident", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
-           "INC_GAUSS_MOD", "INC_RAISED_COS"]
+           "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP"]
 
 
 class TDBEMError(RuntimeError):
@@ -56,7 +57,7 @@ class TDBEM:
 
     def __init__(self, xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, *, use_fmm=0, depth=4, p_s=4, p_t=4, mu=0,
                  m2l_prec=M2L_FP64, gmres_tol=1e-12, gmres_restart=30, gmres_maxiter=300, nt_max=4096,
-                 device=None):
+                 guess=GUESS_EXTRAP, device=None):
         torch = _torch()
         self._L = N.lib()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -65,7 +66,7 @@ class TDBEM:
         mesh = N.Mesh(xyz.shape[0], tri.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                       tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         o = N.Opts(int(use_fmm), int(depth), int(p_s), int(p_t), int(mu), int(m2l_prec), float(gmres_tol),
-                   int(gmres_restart), int(gmres_maxiter), int(nt_max))
+                   int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess))
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
         h = ctypes.c_void_p()
@@ -161,6 +162,19 @@ class TDBEM:
         cnt = (ctypes.c_int64 * n)()
         self._check(self._L.tdbem_profile_read(self._h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(N.PROF_KINDS)}
+
+    def mlp_load(self, params):
+        """Use the network with these packed FP32 parameters (CUDA tensor) when guess=GUESS_MLP."""
+        from .mlp import _fptr
+        self._check(self._L.tdbem_mlp_load(self._h, _fptr(params, N.MLP_NPARAM, "params")))
+
+    def mlp_record(self, feat=None, target=None):
+        """Record features (nt_max x Ns x 16) and targets (nt_max x Ns), float32 CUDA tensors, during
+        later steps (rows beta >= 4); no arguments stops recording."""
+        from .mlp import _fptr
+        self._rec = (feat, target)  # keep the buffers alive while recorded into
+        self._check(self._L.tdbem_mlp_record(self._h, _fptr(feat, self.nt_max * self.ns * N.MLP_IN_PAD, "feat"),
+                                             _fptr(target, self.nt_max * self.ns, "target")))
 
     def near_row(self, i):
         n = self._check(self._L.tdbem_near_row(self._h, int(i), 0, None, None, None, None))

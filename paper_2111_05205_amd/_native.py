@@ -9,6 +9,8 @@ OBIE, BMBIE = 0, 1
 DIRICHLET, NEUMANN = 0, 1
 M2L_FP64, M2L_FP32 = 0, 1
 INC_GAUSS_MOD, INC_RAISED_COS = 0, 1
+GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP = 0, 1, 2, 3
+MLP_IN, MLP_IN_PAD, MLP_WIDTH, MLP_NPARAM = 12, 16, 256, 136193
 
 
 class Mesh(ctypes.Structure):
@@ -19,7 +21,8 @@ class Mesh(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("use_fmm", ctypes.c_int), ("depth", ctypes.c_int), ("p_s", ctypes.c_int), ("p_t", ctypes.c_int),
                 ("mu", ctypes.c_int), ("m2l_prec", ctypes.c_int), ("gmres_tol", ctypes.c_double),
-                ("gmres_restart", ctypes.c_int), ("gmres_maxiter", ctypes.c_int), ("nt_max", ctypes.c_int)]
+                ("gmres_restart", ctypes.c_int), ("gmres_maxiter", ctypes.c_int), ("nt_max", ctypes.c_int),
+                ("guess", ctypes.c_int)]
 
 
 class Incident(ctypes.Structure):
@@ -33,7 +36,7 @@ class StepInfo(ctypes.Structure):
 
 class RunInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int), ("total_iters", ctypes.c_int), ("max_iters", ctypes.c_int),
-                ("max_resid", ctypes.c_double), ("march_ms", ctypes.c_double)]
+                ("max_resid", ctypes.c_double), ("march_ms", ctypes.c_double), ("guesses_rejected", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -45,7 +48,7 @@ class Info(ctypes.Structure):
                 ("m2l_variant", ctypes.c_int * 16)]
 
 
-PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other"]
+PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other", "mlp"]
 
 _lib = None
 
@@ -77,5 +80,14 @@ def lib():
                                      dp, dp]
         L.tdbem_profile.argtypes = [vp, ip]
         L.tdbem_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ip]
+        L.tdbem_mlp_forward.argtypes = [vp, ip, vp, vp, vp, vp]
+        L.tdbem_mlp_workspace_floats.argtypes = [ip]
+        L.tdbem_mlp_workspace_floats.restype = ctypes.c_size_t
+        L.tdbem_mlp_backward.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tdbem_mlp_mse.argtypes = [ip, vp, vp, vp, vp, vp]
+        L.tdbem_mlp_adam_step.argtypes = [vp, vp, vp, vp, ip, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, vp]
+        L.tdbem_mlp_load.argtypes = [vp, vp]
+        L.tdbem_mlp_record.argtypes = [vp, vp, vp]
         _lib = L
     return _lib

@@ -39,6 +39,10 @@ static int guarded(tdbem_ctx* ctx, F&& f) {
 
 static void fail(int code, const std::string& m) { throw Error(code, m); }
 
+namespace tdbem {
+void set_global_error(const std::string& msg) { g_create_err = msg; }
+}  // namespace tdbem
+
 // ---------------------------------------------------------------------------
 // Geometry and mesh validation (host).
 
@@ -135,13 +139,16 @@ __global__ void store_step_kernel(int ns, int beta, int bc, const double* __rest
   if (!isfinite(xv) || fabs(xv) > 1e100) atomicOr(&st->flags, 2);
 }
 
-// Initial guess of the per-step solve: quadratic extrapolation of the last
-// three solved coefficient rows (previous row, or zero, early in the march).
-__global__ void guess_kernel(int ns, int beta, const double* __restrict__ h, double* __restrict__ x) {
+// Starting point of the per-step solve: quadratic extrapolation of the last
+// three solved coefficient rows (previous row, or zero, early in the march),
+// zero, or the previous row.
+__global__ void guess_kernel(int ns, int beta, int mode, const double* __restrict__ h, double* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ns) return;
   double v = 0.0;
-  if (beta >= 3)
+  if (mode == TDBEM_GUESS_ZERO) v = 0.0;
+  else if (mode == TDBEM_GUESS_PREV) v = beta >= 1 ? h[(int64_t)(beta - 1) * ns + i] : 0.0;
+  else if (beta >= 3)
     v = 3.0 * h[(int64_t)(beta - 1) * ns + i] - 3.0 * h[(int64_t)(beta - 2) * ns + i] + h[(int64_t)(beta - 3) * ns + i];
   else if (beta >= 1)
     v = h[(int64_t)(beta - 1) * ns + i];
@@ -223,10 +230,18 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
     if (ctx->bc == TDBEM_DIRICHLET) launch_spmv_add(ctx, ctx->d_w1_val.p, -1.0, bcv, ctx->d_b.p);
     else launch_spmv_add(ctx, ctx->d_u1_val.p, 1.0, bcv, ctx->d_b.p);
   }
-  {
+  const bool use_mlp = ctx->opts.guess == TDBEM_GUESS_MLP && ctx->mlp_loaded && beta >= 4;
+  float* feat = nullptr;
+  if (beta >= 4 && (use_mlp || ctx->rec_feat)) {
+    feat = ctx->rec_feat ? ctx->rec_feat + (size_t)beta * ctx->ns * TDBEM_MLP_IN_PAD : ctx->d_mlp_feat.p;
+    launch_mlp_features(ctx, beta, ctx->d_b.p, feat);
+  }
+  if (use_mlp) {
+    launch_mlp_guess(ctx, beta, feat, ctx->d_x.p);
+  } else {
     ProfScope pg(ctx, K_OTHER);
     guess_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
-        ctx->ns, beta, ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p, ctx->d_x.p);
+        ctx->ns, beta, ctx->opts.guess, ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p, ctx->d_x.p);
     TDBEM_HIP(hipGetLastError());
   }
   launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, stat);
@@ -237,6 +252,7 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   TDBEM_HIP(hipGetLastError());
   if (ctx->bc == TDBEM_NEUMANN) { ctx->hist_u = true; if (bcv) ctx->hist_q = true; }
   else { ctx->hist_q = true; if (bcv) ctx->hist_u = true; }
+  if (feat && ctx->rec_target) launch_mlp_target(ctx, beta, ctx->rec_target + (size_t)beta * ctx->ns);
   if (ctx->fmm) fmm_advance(ctx, beta);
   ctx->alpha = alpha + 1;
 }
@@ -260,6 +276,7 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     if (o.gmres_restart <= 0) o.gmres_restart = 30;
     if (o.gmres_maxiter <= 0) o.gmres_maxiter = 300;
     if (o.nt_max <= 1) o.nt_max = 4096;
+    if (o.guess < TDBEM_GUESS_EXTRAP || o.guess > TDBEM_GUESS_MLP) fail(TDBEM_E_INVAL, "guess must be 0..3");
     ctx->stream = (hipStream_t)hip_stream;
     ctx->c = c;
     ctx->dt = dt;
@@ -496,6 +513,7 @@ int tdbem_run(tdbem_ctx* ctx, int nt, const double* dev_forcing, const tdbem_inc
       ri.total_iters += s.iters;
       ri.max_iters = std::max(ri.max_iters, s.iters);
       ri.max_resid = std::max(ri.max_resid, s.resid);
+      if (s.flags & 4) ri.guesses_rejected++;
       if ((s.flags & 2) && rc == TDBEM_OK) { rc = TDBEM_E_DIVERGED; ctx->err = "non-finite or exploding solution at step " + std::to_string(a); }
       else if ((s.flags & 1) && rc == TDBEM_OK) { rc = TDBEM_E_NOT_CONVERGED; ctx->err = "GMRES did not converge at step " + std::to_string(a); }
     }

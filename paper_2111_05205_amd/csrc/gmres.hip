@@ -120,7 +120,17 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
         V0[i] = r;
         rr += r * r;
       }
-      const double beta = sqrt(block_sum(rr, sh));
+      double beta = sqrt(block_sum(rr, sh));
+      if (it == 0 && !(beta <= bnorm)) {
+        // the starting point is worse than zero (or not finite): start from x = 0
+        for (int i = tid; i < ns; i += GM_THREADS) {
+          x[i] = 0.0;
+          V0[i] = b[i];
+        }
+        beta = bnorm;
+        flags |= 4;
+        __syncthreads();
+      }
       rel = beta / bnorm;
       if (!(beta > target) || it >= maxit) {
         if (!(beta == beta)) flags |= 2;
@@ -283,7 +293,17 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
         part[0] += r * r;
       }
       grid_multi_sum(1, part, gpart, flip, sh, grid);
-      const double beta = sqrt(sh.hv[0]);
+      double beta = sqrt(sh.hv[0]);
+      if (it == 0 && !(beta <= bnorm)) {
+        // the starting point is worse than zero (or not finite): start from x = 0
+        // (beta is the same in every workgroup, so all take this branch together)
+        for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+          x[i] = 0.0;
+          V0[i] = b[i];
+        }
+        beta = bnorm;
+        flags |= 4;
+      }
       rel = beta / bnorm;
       if (!(beta > target) || it >= maxit) {
         if (!(beta == beta)) flags |= 2;

@@ -115,6 +115,15 @@ struct tdbem_ctx {
 
   tdbem::Fmm* fmm = nullptr;
 
+  // learned initial guess
+  bool mlp_loaded = false;
+  tdbem::DevBuf<float> d_mlp_params;   // packed FP32 parameters
+  tdbem::DevBuf<float> d_mlp_feat, d_mlp_y;
+  tdbem::DevBuf<double> d_mlp_diag, d_mlp_s, d_area;
+  double mlp_geo[5] = {0, 0, 0, 0, 0};  // 1/h^2, bounding-box centre (3), 1/R
+  float* rec_feat = nullptr;           // caller-owned training records (tdbem_mlp_record)
+  float* rec_target = nullptr;
+
   // kernel timing (tdbem_profile)
   bool prof = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
@@ -125,7 +134,7 @@ struct tdbem_ctx {
 namespace tdbem {
 
 enum ProfKind { K_NEAR = 0, K_GMRES = 1, K_L2P = 2, K_P2M = 3, K_M2L_GEMM = 4, K_M2L_RED = 5, K_M2M = 6, K_L2L = 7,
-                K_OTHER = 8 };
+                K_OTHER = 8, K_MLP = 9 };
 
 // Brackets the launches in its scope with events when profiling is enabled.
 struct ProfScope {
@@ -156,7 +165,17 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat);
 int gmres_workgroups(int ns);
 
 // api.hip
+void set_global_error(const std::string& msg);  // message for tdbem_last_error(NULL)
 void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc, int a0, int n, double* out);
+
+// mlp.hip
+void mlp_prepare(tdbem_ctx* ctx);  // per-context buffers of the guess (diagonal of A, areas)
+// features of unknown row beta (>= 4) from the stored history and b into feat (Ns x 16); scale into d_mlp_s
+void launch_mlp_features(tdbem_ctx* ctx, int beta, const double* b, float* feat);
+// x = x^{beta-1} + s * network(feat)
+void launch_mlp_guess(tdbem_ctx* ctx, int beta, const float* feat, double* x);
+// training target of row beta (after it has been stored)
+void launch_mlp_target(tdbem_ctx* ctx, int beta, float* target);
 
 // fmm.hip
 Fmm* fmm_create(tdbem_ctx* ctx);
