@@ -58,7 +58,10 @@ typedef enum { TDBEM_INC_GAUSS_MOD = 0, TDBEM_INC_RAISED_COS = 1 } tdbem_inc_kin
 /* Starting point of the per-step GMRES solve (the paper names no solver):
  * EXTRAP quadratic extrapolation of the last three solved rows (default),
  * ZERO, PREV the previous row, MLP the learned guess (tdbem_mlp_load; falls
- * back to EXTRAP for the first four rows or when no network is loaded). */
+ * back to EXTRAP for the first four rows or when no network is loaded).  With
+ * MLP the solve computes the residuals of the network's proposal and of the
+ * extrapolation and starts from the smaller; any starting point whose residual
+ * exceeds |b| is replaced by zero. */
 typedef enum { TDBEM_GUESS_EXTRAP = 0, TDBEM_GUESS_ZERO = 1, TDBEM_GUESS_PREV = 2, TDBEM_GUESS_MLP = 3 } tdbem_guess;
 
 typedef struct {
@@ -99,7 +102,8 @@ typedef struct {
   int max_iters;        /* largest per-step iteration count */
   double max_resid;     /* largest final relative residual */
   double march_ms;      /* wall time of the march on the context stream (HIP events) */
-  int guesses_rejected; /* steps whose starting point had a larger residual than zero (solve restarted from 0) */
+  int guesses_rejected; /* steps whose starting point had a larger residual than zero (solve started from 0) */
+  int guesses_replaced; /* GUESS_MLP: steps where the extrapolation had the smaller residual and was used instead */
 } tdbem_run_info;
 
 typedef struct {
@@ -213,14 +217,17 @@ int tdbem_profile_read(struct tdbem_ctx *ctx, double *ms, int64_t *launches, int
  *   W1 [256][16] (input columns 12..15 are padding and should stay 0), b1 [256],
  *   W2 [256][256], b2 [256], W3 [256][256], b3 [256], W4 [256], b4 [1].
  * Features (dev_feat): n x 16 FP32 per element, columns 12..15 ignored:
- *   0..3  x^{beta-1..beta-4} / s  (the last four solved rows of the unknown)
- *   4     (b_i / A_ii) / s        (right-hand side of the step, Jacobi-scaled)
+ *   0..3  backward differences of the last four solved rows x1..x4 of the
+ *         unknown: x1, x1 - x2, x1 - 2 x2 + x3, x1 - 3 x2 + 3 x3 - x4, over s
+ *   4     (b_i / A_ii - e_i) / s  (Jacobi-scaled right-hand side of the step
+ *         relative to the extrapolation e defined below)
  *   5..7  outward unit normal
  *   8     area / h^2              (h = mean edge length)
  *   9..11 (centroid - bounding-box centre) / R   (R = largest vertex distance from it)
- * with s the root mean square of the five scaled density columns.  The output
- * y proposes x^beta = x^{beta-1} + s y; the training target is
- * (x^beta - x^{beta-1}) / s.
+ * with s the root mean square of x1..x4 and b_i / A_ii together.  The output
+ * y corrects the quadratic extrapolation e = 3 x^{beta-1} - 3 x^{beta-2} + x^{beta-3}:
+ * the proposal is x^beta = e + s y (e where y is not finite), and the training
+ * target is (x^beta - e) / s.
  * All calls below enqueue on hip_stream (NULL = null stream) and return
  * after that stream has finished them; every pointer is caller-owned. */
 #define TDBEM_MLP_IN 12

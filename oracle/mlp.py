@@ -15,7 +15,10 @@ so that the library's kernels can be compared with it:
                 treated as the identity (straight-through);
 * ``mse``       mean squared error and its derivative;
 * ``adam``      one step of Adam (Kingma and Ba, 2015) with bias correction;
-* ``features``  the per-element inputs and the normalisation of the target.
+* ``features``  the per-element inputs and the normalisation of the target;
+* ``extrapolate``, ``target``, ``guess``  the network output y corrects the
+                quadratic extrapolation of the last three rows: the proposal is
+                extrapolation + s y, so y = 0 reproduces the extrapolation.
 
 Parameter vector (FP32 master copy, packed, the layout the C ABI states):
 W1 [256][16] (input columns 12..15 are padding), b1 [256], W2 [256][256],
@@ -152,16 +155,19 @@ def features(hist, beta, b, diag, xyz, tri):
 
     hist: solved rows (>= beta, ns) of the unknown (u on Neumann faces, q on
     Dirichlet faces); b: right-hand side of step beta; diag: the diagonal of
-    the per-step matrix.  Densities and the Jacobi-scaled right-hand side b/diag
-    are divided by s, the root mean square of the last four rows and of b/diag;
-    geometry: outward unit normal, area / h^2, (centroid - centre) / R."""
+    the per-step matrix.  With x1..x4 the rows beta-1..beta-4, e the quadratic
+    extrapolation 3 x1 - 3 x2 + x3 and s the root mean square of x1..x4 and
+    b/diag, the density inputs are the backward differences of the history
+    x1, x1 - x2, x1 - 2 x2 + x3, x1 - 3 x2 + 3 x3 - x4 and the Jacobi-scaled
+    right-hand side relative to the extrapolation b/diag - e, each divided by
+    s; geometry: outward unit normal, area / h^2, (centroid - centre) / R."""
     hist = np.asarray(hist, dtype=np.float64)
     xyz = np.asarray(xyz, dtype=np.float64)
     tri = np.asarray(tri)
     ns = tri.shape[0]
     bj = np.asarray(b, dtype=np.float64) / np.asarray(diag, dtype=np.float64)
-    rows = [hist[beta - k] for k in range(1, 5)]
-    ssq = sum(float(x @ x) for x in rows) + float(bj @ bj)
+    x1, x2, x3, x4 = (hist[beta - k] for k in range(1, 5))
+    ssq = sum(float(x @ x) for x in (x1, x2, x3, x4)) + float(bj @ bj)
     s = np.sqrt(ssq / (5.0 * ns))
     inv = 1.0 / s if s > 0.0 else 0.0
     p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
@@ -170,23 +176,33 @@ def features(hist, beta, b, diag, xyz, tri):
     nout = cr / (2.0 * area[:, None])
     xc = (p0 + p1 + p2) / 3.0
     h, cen, rad = mesh_scales(xyz, tri)
+    e = 3.0 * x1 - 3.0 * x2 + x3
     f = np.zeros((ns, N_IN_PAD))
-    for k in range(4):
-        f[:, k] = rows[k] * inv
-    f[:, 4] = bj * inv
+    f[:, 0] = x1 * inv
+    f[:, 1] = (x1 - x2) * inv
+    f[:, 2] = (x1 - 2.0 * x2 + x3) * inv
+    f[:, 3] = (x1 - 3.0 * x2 + 3.0 * x3 - x4) * inv
+    f[:, 4] = (bj - e) * inv
     f[:, 5:8] = nout
     f[:, 8] = area / (h * h)
     f[:, 9:12] = (xc - cen) / rad
     return f, s
 
 
-def target(x_new, x_prev, s):
-    """Training target: the step increment of the unknown divided by s."""
+def extrapolate(hist, beta):
+    """Quadratic extrapolation of row beta from rows beta-1, beta-2, beta-3:
+    the value at beta of the parabola through them, 3 x1 - 3 x2 + x3."""
+    hist = np.asarray(hist, dtype=np.float64)
+    return 3.0 * hist[beta - 1] - 3.0 * hist[beta - 2] + hist[beta - 3]
+
+
+def target(x_new, base, s):
+    """Training target: what the extrapolation base misses, divided by s."""
     inv = 1.0 / s if s > 0.0 else 0.0
-    return (np.asarray(x_new, dtype=np.float64) - np.asarray(x_prev, dtype=np.float64)) * inv
+    return (np.asarray(x_new, dtype=np.float64) - np.asarray(base, dtype=np.float64)) * inv
 
 
-def guess(x_prev, s, y):
-    """Proposed starting point x_prev + s y (x_prev where y is not finite)."""
+def guess(base, s, y):
+    """Proposed starting point base + s y (base where y is not finite)."""
     y = np.asarray(y, dtype=np.float64)
-    return np.where(np.isfinite(y), np.asarray(x_prev, dtype=np.float64) + s * y, x_prev)
+    return np.where(np.isfinite(y), np.asarray(base, dtype=np.float64) + s * y, base)

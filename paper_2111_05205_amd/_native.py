@@ -36,7 +36,8 @@ class StepInfo(ctypes.Structure):
 
 class RunInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int), ("total_iters", ctypes.c_int), ("max_iters", ctypes.c_int),
-                ("max_resid", ctypes.c_double), ("march_ms", ctypes.c_double), ("guesses_rejected", ctypes.c_int)]
+                ("max_resid", ctypes.c_double), ("march_ms", ctypes.c_double), ("guesses_rejected", ctypes.c_int),
+                ("guesses_replaced", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

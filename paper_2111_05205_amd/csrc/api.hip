@@ -236,15 +236,17 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
     feat = ctx->rec_feat ? ctx->rec_feat + (size_t)beta * ctx->ns * TDBEM_MLP_IN_PAD : ctx->d_mlp_feat.p;
     launch_mlp_features(ctx, beta, ctx->d_b.p, feat);
   }
+  const double* xalt = nullptr;
   if (use_mlp) {
-    launch_mlp_guess(ctx, beta, feat, ctx->d_x.p);
+    launch_mlp_guess(ctx, beta, feat, ctx->d_x.p, ctx->d_x_alt.p);
+    xalt = ctx->d_x_alt.p;
   } else {
     ProfScope pg(ctx, K_OTHER);
     guess_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
         ctx->ns, beta, ctx->opts.guess, ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p, ctx->d_x.p);
     TDBEM_HIP(hipGetLastError());
   }
-  launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, stat);
+  launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, stat, xalt);
   ProfScope* ps = new ProfScope(ctx, K_OTHER);
   store_step_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(ctx->ns, beta, ctx->bc, ctx->d_x.p, bcv,
                                                                       ctx->d_hu.p, ctx->d_hq.p, stat);
@@ -514,6 +516,7 @@ int tdbem_run(tdbem_ctx* ctx, int nt, const double* dev_forcing, const tdbem_inc
       ri.max_iters = std::max(ri.max_iters, s.iters);
       ri.max_resid = std::max(ri.max_resid, s.resid);
       if (s.flags & 4) ri.guesses_rejected++;
+      if (s.flags & 8) ri.guesses_replaced++;
       if ((s.flags & 2) && rc == TDBEM_OK) { rc = TDBEM_E_DIVERGED; ctx->err = "non-finite or exploding solution at step " + std::to_string(a); }
       else if ((s.flags & 1) && rc == TDBEM_OK) { rc = TDBEM_E_NOT_CONVERGED; ctx->err = "GMRES did not converge at step " + std::to_string(a); }
     }

@@ -96,7 +96,8 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
                                                             const double* __restrict__ av,
                                                             const double* __restrict__ b, double* __restrict__ x,
                                                             double* __restrict__ V, int m, int maxit, double tol,
-                                                            StepStat* __restrict__ stat) {
+                                                            StepStat* __restrict__ stat,
+                                                            const double* __restrict__ xalt) {
   __shared__ GmresShared sh;
   const int tid = threadIdx.x;
   double bn2 = 0.0;
@@ -121,6 +122,27 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
         rr += r * r;
       }
       double beta = sqrt(block_sum(rr, sh));
+      if (it == 0 && xalt) {
+        // a second candidate starting point: keep whichever has the smaller residual
+        double* V1 = V + ns;
+        spmv(ns, ap, ac, av, xalt, V1);
+        double ra = 0.0;
+        for (int i = tid; i < ns; i += GM_THREADS) {
+          const double r = b[i] - V1[i];
+          V1[i] = r;
+          ra += r * r;
+        }
+        const double beta_a = sqrt(block_sum(ra, sh));
+        if (beta_a < beta || !(beta == beta)) {
+          for (int i = tid; i < ns; i += GM_THREADS) {
+            x[i] = xalt[i];
+            V0[i] = V1[i];
+          }
+          beta = beta_a;
+          flags |= 8;
+          __syncthreads();
+        }
+      }
       if (it == 0 && !(beta <= bnorm)) {
         // the starting point is worse than zero (or not finite): start from x = 0
         for (int i = tid; i < ns; i += GM_THREADS) {
@@ -263,7 +285,7 @@ __device__ inline void grid_multi_sum(int n, const double* part, double* __restr
 __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
     int ns, const int32_t* __restrict__ ap, const int32_t* __restrict__ ac, const double* __restrict__ av,
     const double* __restrict__ b, double* __restrict__ x, double* __restrict__ V, int m, int maxit, double tol,
-    StepStat* __restrict__ stat, double* __restrict__ gpart) {
+    StepStat* __restrict__ stat, double* __restrict__ gpart, const double* __restrict__ xalt) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ CoopShared sh;
   const int tid = threadIdx.x;
@@ -294,6 +316,29 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
       }
       grid_multi_sum(1, part, gpart, flip, sh, grid);
       double beta = sqrt(sh.hv[0]);
+      if (it == 0 && xalt) {
+        // a second candidate starting point: keep whichever has the smaller residual
+        // (both norms are grid-wide sums, so every workgroup takes the same branch)
+        double* V1 = V + ns;
+        part[0] = 0.0;
+        for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+          double sa = 0.0;
+          for (int k = ap[i]; k < ap[i + 1]; ++k) sa += av[k] * xalt[ac[k]];
+          const double r = b[i] - sa;
+          V1[i] = r;
+          part[0] += r * r;
+        }
+        grid_multi_sum(1, part, gpart, flip, sh, grid);
+        const double beta_a = sqrt(sh.hv[0]);
+        if (beta_a < beta || !(beta == beta)) {
+          for (int i = r0 + tid; i < r1; i += GC_THREADS) {
+            x[i] = xalt[i];
+            V0[i] = V1[i];
+          }
+          beta = beta_a;
+          flags |= 8;
+        }
+      }
       if (it == 0 && !(beta <= bnorm)) {
         // the starting point is worse than zero (or not finite): start from x = 0
         // (beta is the same in every workgroup, so all take this branch together)
@@ -401,7 +446,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
   }
 }
 
-void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat) {
+void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, const double* xalt) {
   ProfScope ps(ctx, K_GMRES);
   int m = ctx->opts.gmres_restart;
   if (m > GM_MAXM) m = GM_MAXM;
@@ -410,7 +455,7 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat) {
   if (nwg <= 1) {
     gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, b, x,
                                                      ctx->d_V.p, m, ctx->opts.gmres_maxiter, ctx->opts.gmres_tol,
-                                                     stat);
+                                                     stat, xalt);
     TDBEM_HIP(hipGetLastError());
     return;
   }
@@ -421,7 +466,7 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat) {
   const double* av = ctx->d_a_val.p;
   double* V = ctx->d_V.p;
   double* gp = ctx->d_gpart.p;
-  void* args[] = {&ns, &ap, &ac, &av, &b, &x, &V, &m, &maxit, &tol, &stat, &gp};
+  void* args[] = {&ns, &ap, &ac, &av, &b, &x, &V, &m, &maxit, &tol, &stat, &gp, &xalt};
   TDBEM_HIP(hipLaunchCooperativeKernel((const void*)gmres_coop_kernel, dim3(nwg), dim3(GC_THREADS), args, 0,
                                        ctx->stream));
 }

@@ -119,6 +119,7 @@ struct tdbem_ctx {
   bool mlp_loaded = false;
   tdbem::DevBuf<float> d_mlp_params;   // packed FP32 parameters
   tdbem::DevBuf<float> d_mlp_feat, d_mlp_y;
+  tdbem::DevBuf<double> d_x_alt;       // extrapolated starting point offered beside the network's
   tdbem::DevBuf<double> d_mlp_diag, d_mlp_s, d_area;
   double mlp_geo[5] = {0, 0, 0, 0, 0};  // 1/h^2, bounding-box centre (3), 1/R
   float* rec_feat = nullptr;           // caller-owned training records (tdbem_mlp_record)
@@ -161,7 +162,9 @@ void launch_spmv_add(tdbem_ctx* ctx, const double* vals, double scale, const dou
 void upload_gl_rule();
 
 // gmres.hip
-void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat);
+// xalt: NULL or a second starting point; the solve starts from whichever of x,
+// xalt has the smaller residual (from zero when both are worse than zero)
+void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, const double* xalt = nullptr);
 int gmres_workgroups(int ns);
 
 // api.hip
@@ -172,8 +175,8 @@ void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc, int a0, int n, do
 void mlp_prepare(tdbem_ctx* ctx);  // per-context buffers of the guess (diagonal of A, areas)
 // features of unknown row beta (>= 4) from the stored history and b into feat (Ns x 16); scale into d_mlp_s
 void launch_mlp_features(tdbem_ctx* ctx, int beta, const double* b, float* feat);
-// x = x^{beta-1} + s * network(feat)
-void launch_mlp_guess(tdbem_ctx* ctx, int beta, const float* feat, double* x);
+// x = quadratic extrapolation of the last three rows + s * network(feat); xe = the extrapolation
+void launch_mlp_guess(tdbem_ctx* ctx, int beta, const float* feat, double* x, double* xe);
 // training target of row beta (after it has been stored)
 void launch_mlp_target(tdbem_ctx* ctx, int beta, float* target);
 

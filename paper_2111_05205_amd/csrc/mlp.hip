@@ -332,8 +332,14 @@ __global__ void mlp_features_kernel(int ns, int beta, const double* __restrict__
   const double sv = s[0];
   const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
   float f[NINP];
-  for (int k = 0; k < 4; ++k) f[k] = (float)(h[(int64_t)(beta - 1 - k) * ns + i] * inv);
-  f[4] = (float)(b[i] / diag[i] * inv);
+  const double x1 = h[(int64_t)(beta - 1) * ns + i], x2 = h[(int64_t)(beta - 2) * ns + i];
+  const double x3 = h[(int64_t)(beta - 3) * ns + i], x4 = h[(int64_t)(beta - 4) * ns + i];
+  // backward differences of the history and the Jacobi-scaled rhs relative to the extrapolation
+  f[0] = (float)(x1 * inv);
+  f[1] = (float)((x1 - x2) * inv);
+  f[2] = (float)((x1 - 2.0 * x2 + x3) * inv);
+  f[3] = (float)((x1 - 3.0 * x2 + 3.0 * x3 - x4) * inv);
+  f[4] = (float)((b[i] / diag[i] - (3.0 * x1 - 3.0 * x2 + x3)) * inv);
   for (int k = 0; k < 3; ++k) f[5 + k] = (float)(-nrm[3 * i + k]);  // outward = -(paper normal)
   f[8] = (float)(area[i] * g.inv_h2);
   for (int k = 0; k < 3; ++k) f[9 + k] = (float)((xc[3 * i + k] - g.cen[k]) * g.inv_r);
@@ -342,13 +348,20 @@ __global__ void mlp_features_kernel(int ns, int beta, const double* __restrict__
   for (int q = 0; q < 4; ++q) o[q] = float4{f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
 }
 
+// Value at beta of the parabola through rows beta-1, beta-2, beta-3.
+__device__ inline double extrapolated(const double* __restrict__ h, int beta, int ns, int i) {
+  return 3.0 * h[(int64_t)(beta - 1) * ns + i] - 3.0 * h[(int64_t)(beta - 2) * ns + i] + h[(int64_t)(beta - 3) * ns + i];
+}
+
+// The network corrects the extrapolation: x = extrapolation + s y.
 __global__ void mlp_guess_kernel(int ns, int beta, const double* __restrict__ h, const double* __restrict__ s,
-                                 const float* __restrict__ y, double* __restrict__ x) {
+                                 const float* __restrict__ y, double* __restrict__ x, double* __restrict__ xe) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ns) return;
-  const double prev = h[(int64_t)(beta - 1) * ns + i];
+  const double base = extrapolated(h, beta, ns, i);
   const float yi = y[i];
-  x[i] = isfinite(yi) ? prev + s[0] * (double)yi : prev;
+  x[i] = isfinite(yi) ? base + s[0] * (double)yi : base;
+  if (xe) xe[i] = base;
 }
 
 __global__ void mlp_target_kernel(int ns, int beta, const double* __restrict__ h, const double* __restrict__ s,
@@ -357,7 +370,7 @@ __global__ void mlp_target_kernel(int ns, int beta, const double* __restrict__ h
   if (i >= ns) return;
   const double sv = s[0];
   const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
-  t[i] = (float)((h[(int64_t)beta * ns + i] - h[(int64_t)(beta - 1) * ns + i]) * inv);
+  t[i] = (float)((h[(int64_t)beta * ns + i] - extrapolated(h, beta, ns, i)) * inv);
 }
 
 void launch_fwd(const float* P, int n, const float* feat, float* y, uint16_t* act, hipStream_t st) {
@@ -398,6 +411,7 @@ void mlp_prepare(tdbem_ctx* ctx) {
   ctx->d_area.alloc(ns);
   ctx->d_mlp_feat.alloc((size_t)ns * NINP);
   ctx->d_mlp_y.alloc(ns);
+  ctx->d_x_alt.alloc(ns);
   TDBEM_HIP(hipMemcpyAsync(ctx->d_area.p, ctx->geo.area.data(), ns * sizeof(double), hipMemcpyHostToDevice,
                            ctx->stream));
   diag_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p,
@@ -422,12 +436,13 @@ void launch_mlp_features(tdbem_ctx* ctx, int beta, const double* b, float* feat)
   TDBEM_HIP(hipGetLastError());
 }
 
-void launch_mlp_guess(tdbem_ctx* ctx, int beta, const float* feat, double* x) {
+void launch_mlp_guess(tdbem_ctx* ctx, int beta, const float* feat, double* x, double* xe) {
   ProfScope ps(ctx, K_MLP);
   const int ns = ctx->ns;
   const double* h = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
   launch_fwd(ctx->d_mlp_params.p, ns, feat, ctx->d_mlp_y.p, nullptr, ctx->stream);
-  mlp_guess_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(ns, beta, h, ctx->d_mlp_s.p, ctx->d_mlp_y.p, x);
+  mlp_guess_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(ns, beta, h, ctx->d_mlp_s.p, ctx->d_mlp_y.p, x,
+                                                               xe);
   TDBEM_HIP(hipGetLastError());
 }
 

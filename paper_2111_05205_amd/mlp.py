@@ -157,7 +157,7 @@ def make_solver(xyz, tri, d=2, bie=1, bc=1, nt=256, p=4, guess=N.GUESS_EXTRAP, g
     raise last
 
 
-def generate(shapes, nt=256, rows_per_run=None, seed=0, **solver_kw):
+def generate(shapes, nt=256, rows_per_run=None, seed=0, verbose=False, **solver_kw):
     """March each shape under its incident pulse while recording features and
     targets; returns (feat (N x 16), target (N)) float32 device tensors, with
     rows_per_run seeded rows kept per run (all when None)."""
@@ -181,6 +181,8 @@ def generate(shapes, nt=256, rows_per_run=None, seed=0, **solver_kw):
             f, t = f[idx], t[idx]
         feats.append(f.contiguous())
         targets.append(t.contiguous())
+        if verbose:
+            print(f"run {k}: ns={ns} depth={solver.info()['depth']} rows={t.numel()}", flush=True)
         solver.close()
         del fb, tb
     return torch.cat(feats).contiguous(), torch.cat(targets).contiguous()
@@ -208,6 +210,30 @@ def train(feat, target, steps=2000, batch=8192, lr=1e-3, lr_final=1e-4, seed=0, 
         opt.step(params, grad, lr * (lr_final / lr) ** (it / max(steps - 1, 1)))
         losses.append(float(loss.item()) if (log_every and it % log_every == 0) or it == steps - 1 else None)
     return params, losses
+
+
+def evaluate(params, xyz, tri, nt, inc, modes=("ZERO", "PREV", "EXTRAP", "MLP"), **solver_kw):
+    """GMRES iterations of one march per starting-point mode (same solution for
+    every mode): {mode: {total, per_step_mean, per_step_max, rejected, march_ms}}."""
+    torch = _torch()
+    out = {}
+    ref = None
+    for mode in modes:
+        solver, _ = make_solver(xyz, tri, nt=nt, guess=getattr(N, "GUESS_" + mode), **solver_kw)
+        if mode == "MLP":
+            solver.mlp_load(params)
+        x, ri = solver.run(nt, inc=inc)
+        it = ri["total_iters"]
+        out[mode] = {"total": it, "per_step_mean": it / ri["steps"], "per_step_max": ri["max_iters"],
+                     "rejected": ri["guesses_rejected"], "replaced": ri["guesses_replaced"],
+                     "march_ms": round(ri["march_ms"], 1),
+                     "ns": solver.ns, "depth": solver.info()["depth"]}
+        if ref is None:
+            ref = x
+        else:
+            out[mode]["rel_diff_vs_first"] = float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+        solver.close()
+    return out
 
 
 def save(params, path):
@@ -239,18 +265,36 @@ def main():
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=1000)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--params", default="", help="evaluate these parameters (.npy) instead of training")
+    ap.add_argument("--eval", default="", help="comma list of evaluation meshes: icoL<level>:<nt>")
+    ap.add_argument("--gmres-tol", type=float, default=1e-8)
     a = ap.parse_args()
-    t0 = time.time()
-    shapes = training_shapes(a.runs, seed=a.seed, freq_range=(a.freq_min, a.freq_max))
-    feat, target = generate(shapes, nt=a.nt, rows_per_run=a.rows_per_run)
-    t1 = time.time()
-    print(json.dumps({"runs": a.runs, "rows": int(target.numel()), "generate_s": round(t1 - t0, 1)}), flush=True)
-    params, losses = train(feat, target, steps=a.steps, batch=a.batch, lr=a.lr, log_every=max(a.steps // 20, 1))
-    t2 = time.time()
-    print(json.dumps({"train_s": round(t2 - t1, 1), "loss": [x for x in losses if x is not None]}), flush=True)
-    save(params, a.out)
+    if a.params:
+        params = load(a.params)
+    else:
+        t0 = time.time()
+        shapes = training_shapes(a.runs, seed=a.seed, freq_range=(a.freq_min, a.freq_max))
+        feat, target = generate(shapes, nt=a.nt, rows_per_run=a.rows_per_run, verbose=True, gmres_tol=a.gmres_tol)
+        t1 = time.time()
+        print(json.dumps({"runs": a.runs, "rows": int(target.numel()), "generate_s": round(t1 - t0, 1)}), flush=True)
+        params, losses = train(feat, target, steps=a.steps, batch=a.batch, lr=a.lr, lr_final=a.lr_final,
+                               log_every=max(a.steps // 20, 1))
+        del feat, target
+        t2 = time.time()
+        print(json.dumps({"train_s": round(t2 - t1, 1), "loss": [x for x in losses if x is not None]}), flush=True)
+        save(params, a.out)
+    import synth
+    for spec in filter(None, a.eval.split(",")):
+        mesh, nt = spec.split(":")
+        xyz, tri = synth.icosphere(int(mesh[4:]))
+        inc = synth.incident_params(xyz, seed=0)
+        t3 = time.time()
+        res = evaluate(params, xyz, tri, int(nt), inc, gmres_tol=a.gmres_tol)
+        print(json.dumps({"eval": spec, "gmres_tol": a.gmres_tol, "seconds": round(time.time() - t3, 1),
+                          "iterations": res}), flush=True)
 
 
 if __name__ == "__main__":

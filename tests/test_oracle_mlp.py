@@ -142,13 +142,20 @@ def test_features_invariants():
     diag = rng.uniform(0.5, 2.0, size=ns)
     f, s = mlp.features(hist, 6, b, diag, xyz, tri)
     assert f.shape == (ns, 16) and np.all(f[:, 12:] == 0.0)
-    # s is the RMS of the five normalised columns: their mean square is 1
-    assert abs(np.mean(f[:, :5] ** 2) - 1.0) < 1e-13
+    # s is the RMS of the last four rows and of b / diag together
+    assert abs(s - np.sqrt((np.sum(hist[2:6] ** 2) + np.sum((b / diag) ** 2)) / (5 * ns))) < 1e-14 * s
     # densities and rhs scale together; geometry does not
     f2, s2 = mlp.features(3.0 * hist, 6, 3.0 * b, diag, xyz, tri)
     assert abs(s2 - 3.0 * s) < 1e-12 * s and np.allclose(f2, f, rtol=1e-13, atol=1e-13)
-    assert np.allclose(f[:, 0], hist[5] / s) and np.allclose(f[:, 3], hist[2] / s)
-    assert np.allclose(f[:, 4], b / diag / s)
+    # backward differences: a quadratic history has zero third difference and its
+    # extrapolation is exact, so b / diag - e is b / diag - (the next quadratic value)
+    t = np.arange(8, dtype=np.float64)[:, None]
+    quad = (1.0 + 0.5 * t - 0.25 * t * t) * rng.normal(size=ns)
+    fq, sq = mlp.features(quad, 6, b, diag, xyz, tri)
+    assert np.allclose(fq[:, 0] * sq, quad[5]) and np.allclose(fq[:, 1] * sq, quad[5] - quad[4])
+    assert np.allclose(fq[:, 2] * sq, quad[5] - 2 * quad[4] + quad[3])
+    assert np.allclose(fq[:, 3], 0.0, atol=1e-12)
+    assert np.allclose(fq[:, 4] * sq, b / diag - quad[6])
     # outward unit normals on a sphere, areas near the equilateral value, centroids inside
     n = f[:, 5:8]
     xc = f[:, 9:12]
@@ -168,3 +175,15 @@ def test_guess_inverts_target():
     y[3] = np.nan
     g = mlp.guess(xp, 0.7, y)
     assert g[3] == xp[3]
+
+
+def test_extrapolation_exact_on_quadratics_only():
+    t = np.arange(10, dtype=np.float64)[:, None]
+    rng = np.random.default_rng(9)
+    a, b, c = rng.normal(size=(3, 5))
+    q = a + b * t + c * t * t
+    for beta in range(3, 10):
+        assert np.allclose(mlp.extrapolate(q, beta), q[beta], rtol=1e-13, atol=1e-12)
+    cub = t ** 3 * np.ones(5)
+    # third difference of t^3 is 6: the parabola through three points misses by exactly 6
+    assert np.allclose(cub[6] - mlp.extrapolate(cub, 6), 6.0)
