@@ -7,7 +7,10 @@ starting from a reset context; inputs (mesh tables, M2L operators) are
 resident in HBM before the timed region.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload sphere5k] [--mode fmm|direct]
-                  [--m2l fp64|fp32] [--no-cpu-baseline]
+                  [--form both|mixed|plain] [--gmres-tol 1e-8] [--no-cpu-baseline]
+
+The headline value is the mixed form (FP32 M2L products, learned GMRES starting
+point); the plain FP64 form is timed beside it (plain_fp64, speedup_vs_fp64_plain).
 """
 import argparse
 import json
@@ -74,6 +77,58 @@ def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0):
                       f"their {nt - 1} history sums ({sec:.1f} s); rate = rows*(Nt-1)/s"}
 
 
+def run_form(P, w, args, prec, guess, params=None):
+    """Time one form of the march: K marches from a reset context after W warm-up marches."""
+    import torch
+    use_fmm = int(args.mode == "fmm" and w["use_fmm"])
+    s = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=use_fmm,
+                depth=w["depth"] or 4, p_s=w["p_s"] or 4, p_t=w["p_t"] or 4, m2l_prec=prec, nt_max=w["nt"],
+                gmres_tol=args.gmres_tol, guess=guess)
+    if params is not None:
+        s.mlp_load(params)
+    info = s.info()
+    ns, nt = info["ns"], w["nt"]
+    for _ in range(args.warmup):
+        s.reset()
+        x, _ = s.run(nt, inc=w["inc"])
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(args.steps):
+        s.reset()
+        x, ri = s.run(nt, inc=w["inc"])
+        iters += ri["total_iters"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    sec = (t1 - t0) / args.steps
+    out = {"value": round(ns * nt / sec, 1), "ms_per_step": round(sec * 1e3, 3),
+           "gmres_iters_per_march": iters // args.steps, "setup_ms": round(info["setup_ms"], 1)}
+    if use_fmm:
+        Pn = info["p_s"] ** 3 * info["p_t"]
+        G = info["mu"] + 1 + info["d"]
+        flops = m2l_flops_per_march(info, nt, info["m_leaf"], info["depth"], G, Pn) * args.steps
+        ms, n = prof["m2l_gemm"]
+        peak = PEAK_FP32_TFLOPS if prec == P.M2L_FP32 else PEAK_FP64_TFLOPS
+        achieved = flops / (ms * 1e-3) / 1e12
+        roof = {"kernel": "m2l_gemm", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
+    else:
+        ms, n = prof["near_history"]
+        byts = (info["near_coefs"] * 8 + info["near_pairs"] * 16 + ns * 8) * n
+        achieved = byts / (ms * 1e-3) / 1e9
+        roof = {"kernel": "near_history", "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
+    out["roofline"] = roof
+    out["kernel_ms_per_march"] = {k: round(v[0] / args.steps, 2) for k, v in prof.items()}
+    return s, info, x, out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,7 +136,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere5k")
     ap.add_argument("--mode", default="fmm", choices=["fmm", "direct"])
-    ap.add_argument("--m2l", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--form", default="both", choices=["both", "mixed", "plain"],
+                    help="mixed: FP32 M2L products + learned starting point; plain: FP64 M2L + extrapolated "
+                         "starting point; both: time both, value = mixed")
+    ap.add_argument("--gmres-tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -104,79 +162,63 @@ def main():
     import torch
     import synth
     import paper_2111_05205_amd as P
+    from paper_2111_05205_amd import mlp
 
     torch.cuda.set_device(0)
     w = synth.workload(args.workload)
-    use_fmm = int(args.mode == "fmm" and w["use_fmm"])
-    prec = P.M2L_FP32 if args.m2l == "fp32" else P.M2L_FP64
-    s = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=use_fmm,
-                depth=w["depth"] or 4, p_s=w["p_s"] or 4, p_t=w["p_t"] or 4, m2l_prec=prec, nt_max=w["nt"])
-    info = s.info()
+    params = mlp.load(os.path.join(ROOT, "paper_2111_05205_amd", "data", "mlp_guess.npy"))
+    forms = {}
+    xs = {}
+    if args.form in ("both", "plain"):
+        s, info, xs["plain"], forms["plain"] = run_form(P, w, args, P.M2L_FP64, P.GUESS_EXTRAP)
+        s.close()
+    if args.form in ("both", "mixed"):
+        s, info, xs["mixed"], forms["mixed"] = run_form(P, w, args, P.M2L_FP32, P.GUESS_MLP, params)
+        s.close()
+    head = forms["mixed"] if "mixed" in forms else forms["plain"]
+    for k, f in forms.items():
+        print(f"{k}: kernel time per march (ms): {f['kernel_ms_per_march']}", file=sys.stderr)
     ns, nt = info["ns"], w["nt"]
-    for _ in range(args.warmup):
-        s.reset()
-        x, _ = s.run(nt, inc=w["inc"])
-    torch.cuda.synchronize()
-    s.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    for _ in range(args.steps):
-        s.reset()
-        x, ri = s.run(nt, inc=w["inc"])
-        iters += ri["total_iters"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = s.profile_read()
-    s.profile(False)
-    sec = (t1 - t0) / args.steps
-    value = ns * nt / sec
-
-    # roofline of the dominant kernel
-    if use_fmm:
-        Pn = info["p_s"] ** 3 * info["p_t"]
-        G = info["mu"] + 1 + info["d"]
-        flops = m2l_flops_per_march(info, nt, info["m_leaf"], info["depth"], G, Pn) * args.steps
-        ms, n = prof["m2l_gemm"]
-        peak = PEAK_FP32_TFLOPS if args.m2l == "fp32" else PEAK_FP64_TFLOPS
-        achieved = flops / (ms * 1e-3) / 1e12
-        roof = {"kernel": "m2l_gemm", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
-    else:
-        ms, n = prof["near_history"]
-        byts = (info["near_coefs"] * 8 + info["near_pairs"] * 16 + ns * 8) * n
-        achieved = byts / (ms * 1e-3) / 1e9
-        roof = {"kernel": "near_history", "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
-    print("kernel time per march (ms): " + ", ".join(f"{k} {v[0] / args.steps:.2f} ({v[1] // args.steps})"
-                                                     for k, v in prof.items()), file=sys.stderr)
-
-    out = {"metric": METRIC, "value": round(value, 1), "unit": "Ns*Nt/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64" if args.m2l == "fp64" else "f64 (M2L products f32)",
+    use_fmm = info["use_fmm"]
+    mixed = "mixed" in forms
+    out = {"metric": METRIC, "value": head["value"], "unit": "Ns*Nt/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None,
+           "dtype": "f64 (M2L products f32, starting-point network bf16)" if mixed else "f64",
            "data": "synthetic",
            "config": {"workload": args.workload + ": " + WORKLOAD_TEXT.get(args.workload, ""),
+                      "form": "mixed: FP32 M2L products, FP64 near field/recurrences/solve, learned GMRES "
+                              "starting point" if mixed else "plain FP64",
                       "mode": "fmm" if use_fmm else "direct", "ns": ns, "nt": nt, "d": info["d"],
                       "mu": info["mu"], "m_leaf": info["m_leaf"], "near_pairs": info["near_pairs"],
                       "il_pairs": info["il_pairs"][: (info["depth"] or 0) + 1],
                       "m2l_tile_variant": info["m2l_variant"][: (info["depth"] or 0) + 1],
-                      "gmres_iters_per_march": iters // args.steps, "setup_ms": round(info["setup_ms"], 1)},
-           "roofline": roof}
+                      "gmres_tol": args.gmres_tol,
+                      "gmres_iters_per_march": head["gmres_iters_per_march"], "setup_ms": head["setup_ms"]},
+           "roofline": head["roofline"]}
+    if "plain" in forms and mixed:
+        out["plain_fp64"] = {k: forms["plain"][k] for k in ("value", "ms_per_step", "gmres_iters_per_march",
+                                                             "roofline")}
+        out["speedup_vs_fp64_plain"] = round(forms["mixed"]["value"] / forms["plain"]["value"], 4)
 
     if not args.no_accuracy and use_fmm:
-        d = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0, nt_max=nt)
+        d = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0, nt_max=nt,
+                    gmres_tol=1e-12)
         xd, _ = d.run(nt, inc=w["inc"])
-        err = float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))
-        out["accuracy"] = {"rel_l2_vs_direct": err, "direct_ms_per_march": None}
+        acc = {}
+        for k, x in xs.items():
+            acc[f"rel_l2_{k}_vs_direct"] = float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))
+        if len(xs) == 2:
+            acc["rel_l2_mixed_vs_plain"] = float(torch.linalg.norm(xs["mixed"] - xs["plain"]) /
+                                                 torch.linalg.norm(xs["plain"]))
         d.reset()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         d.run(nt, inc=w["inc"])
         torch.cuda.synchronize()
-        out["accuracy"]["direct_ms_per_march"] = round((time.perf_counter() - t2) * 1e3, 3)
-        del d
+        acc["direct_ms_per_march"] = round((time.perf_counter() - t2) * 1e3, 3)
+        out["accuracy"] = acc
+        d.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

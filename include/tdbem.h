@@ -117,7 +117,9 @@ typedef struct {
   int64_t il_pairs[16]; /* interaction-list pairs per level (FMM) */
   int64_t m2l_matrix_bytes;
   double setup_ms;
-  int m2l_variant[16];   /* autotuned M2L tile variant per level: 0 128x16, 1 128x32, 2 64x16, 3 64x32, 4 32x16, 5 32x32 (columns x K step) */
+  int m2l_variant[16];  /* [n], n = 1..depth-1: autotuned M2L launch for the n finest levels ending an interval
+                           together, 2 * tile + persistent; tile 0 128x16, 1 128x32, 2 64x16, 3 64x32,
+                           4 32x16, 5 32x32 (columns x K step) */
 } tdbem_info;
 
 /* Build a context: copies and validates the mesh (closed, consistently

@@ -31,6 +31,9 @@
 
 #include <algorithm>
 #include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -55,7 +58,6 @@ struct FmmLevel {
   DevBuf<int32_t> d_tiles128, d_tiles64, d_tiles32;  // GEMM column tiles (slot, first, count) by width
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
   int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
-  int variant = 0;                          // chosen M2L tile variant (autotuned)
   DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
   DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
   DevBuf<float> d_U32, d_stage32;           // FP32 operators and staging (mixed-precision M2L)
@@ -75,6 +77,8 @@ struct Fmm {
   DevBuf<double> d_tau, d_sig;
   DevBuf<double> d_S, d_T;                 // 1-D re-interpolation matrices [side][parent][child]
   double Cd = 0;
+  int m2l_choice[16] = {0};                // per number of levels in a launch: 2 * tile variant + persistent
+  int persistent_grid = 0;                 // workgroups of a persistent M2L launch
 };
 
 // ---------------------------------------------------------------------------
@@ -404,11 +408,28 @@ __global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double*
   Uf[(int64_t)slot * per + idx] = (T)v;
 }
 
-template <class T, int NCB, int KS>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, int KB, const int32_t* __restrict__ tiles,
-                                                       const int32_t* __restrict__ pairs_by_slot,
-                                                       const int32_t* __restrict__ il_src, const T* __restrict__ Uf,
-                                                       const double* __restrict__ mom, T* __restrict__ stage) {
+// One M2L launch covers every level whose source interval ends at this step:
+// per level, its column tiles (at the launch's tile width), operators, moments
+// and staging; work items are (level, row block, tile), numbered level by level.
+constexpr int M2L_MAXLEV = 12;
+struct M2LLevelWork {
+  const int32_t* tiles;          // (slot, first pair, count) per tile
+  const int32_t* pairs_by_slot;
+  const int32_t* il_src;
+  const void* Uf;                // T operators in fragment order
+  const double* mom;
+  void* stage;                   // T per-pair products
+  int ntiles;
+  int item0;                     // first work item of this level
+};
+struct M2LWork {
+  M2LLevelWork lev[M2L_MAXLEV];
+  int nlev;
+  int total;                     // work items over all levels
+};
+
+template <class T, int NCB, int KS, bool PERS>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, int KB, M2LWork W) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int BN = NCB * 16;              // columns (interaction pairs) per tile
   constexpr int LD = BN + 4;                // LDS row stride of the moment tile
@@ -417,17 +438,32 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   constexpr int QS = KS / 4;                // MFMA k-substeps per K step
   __shared__ T Bs[2][KS][LD];
   __shared__ int src[BN], pid[BN];
+  const int total = W.total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // PERS: a grid smaller than the work, workgroup b takes items b, b + grid, ...
+  // (a grid that is a multiple of 8 keeps each workgroup on one XCD for all its
+  // items); otherwise one item per workgroup and no loop (fewer live registers).
+  int w = blockIdx.x;
+  do {
   // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
   // give each XCD a contiguous range of (row block, column tile) items with the
   // tiles of one offset adjacent; the second tile of an offset then finds that
   // row block of U in the XCD's L2.
-  const int total = gridDim.x * gridDim.y;
-  const int w = blockIdx.x + blockIdx.y * gridDim.x;
   const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
   const int item = x8 * q8 + min(x8, r8) + w / 8;
-  const int tile = item % gridDim.x, rowblk = item / gridDim.x;
+  int lv = 0;
+  while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
+  const M2LLevelWork& Lw = W.lev[lv];
+  const int local = item - Lw.item0;
+  const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
+  const int32_t* __restrict__ tiles = Lw.tiles;
+  const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
+  const int32_t* __restrict__ il_src = Lw.il_src;
+  const T* __restrict__ Uf = static_cast<const T*>(Lw.Uf);
+  const double* __restrict__ mom = Lw.mom;
+  T* __restrict__ stage = static_cast<T*>(Lw.stage);
   const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if constexpr (PERS) __syncthreads();  // the previous item's readers of src / pid / Bs are done
   const int rb0 = rowblk * (MB_M / 16) + wave * 2;       // this wave: row blocks rb0, rb0+1 (32 rows)
   if (tid < BN) {
     const int p = tid < cnt ? pairs_by_slot[first + tid] : -1;
@@ -500,28 +536,37 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
         if (p >= 0 && row < GP) stage[(int64_t)p * GP + row] = acc[h][cb][r];
       }
     }
+    if constexpr (!PERS) break;
+    w += gridDim.x;
+  } while (w < total);
 }
 
-// Tile variants of the M2L products: (columns per tile, K step).  The choice per
-// level is made once per context by timing every variant (autotuning).
+// Tile variants of the M2L products: (columns per tile, K step).  The variant
+// and whether the launch is persistent are chosen by timing (autotuning).
 constexpr int M2L_VARIANTS = 6;
 static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64, 32, 32};
 static const int kVariantKs[M2L_VARIANTS] = {16, 32, 16, 32, 16, 32};
 
-template <class T>
-static void launch_m2l_variant(int v, dim3 grid, hipStream_t st, int P, int GP, int RB, int KB, const int32_t* tiles,
-                               const int32_t* pbs, const int32_t* il_src, const T* Uf, const double* mom, T* stage) {
+template <class T, bool PERS>
+static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
   switch (v) {
-    case 0: m2l_mfma_kernel<T, 8, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    case 0: m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     case 1:  // the FP64 tile would need 68 KB of LDS: FP64 uses the K=16 kernel here
-      if (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage);
-      else m2l_mfma_kernel<T, 8, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage);
+      if (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
+      else m2l_mfma_kernel<T, 8, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
       break;
-    case 2: m2l_mfma_kernel<T, 4, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
-    case 3: m2l_mfma_kernel<T, 4, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
-    case 4: m2l_mfma_kernel<T, 2, 16><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
-    default: m2l_mfma_kernel<T, 2, 32><<<grid, 256, 0, st>>>(P, GP, RB, KB, tiles, pbs, il_src, Uf, mom, stage); break;
+    case 2: m2l_mfma_kernel<T, 4, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 3: m2l_mfma_kernel<T, 4, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 4: m2l_mfma_kernel<T, 2, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    default: m2l_mfma_kernel<T, 2, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
   }
+}
+
+template <class T>
+static void launch_m2l_variant(int v, bool persistent, int grid, hipStream_t st, int P, int GP, int RB, int KB,
+                               const M2LWork& W) {
+  if (persistent) launch_m2l_tile<T, true>(v, grid, st, P, GP, RB, KB, W);
+  else launch_m2l_tile<T, false>(v, grid, st, P, GP, RB, KB, W);
 }
 
 // Reduce the staged products per target cell: grid (ncell, G, ceil(P/256)).
@@ -765,45 +810,95 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
   if (!v.empty()) TDBEM_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-static void launch_m2l_level(const Fmm* f, const FmmLevel& L, int P, int G, hipStream_t st, int variant = -1) {
-  const int v = variant >= 0 ? variant : L.variant;
-  const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
+// Levels D, D-1, ..., D-n+1 end a source interval together (n = 1..D-1): one
+// launch does their products.  choice = 2 * variant + persistent.
+static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
+  const int P = f->P, G = f->G;
+  const int v = choice >> 1, persistent = choice & 1;
+  const int RB = (G * P + 15) / 16, KB = (P + 3) / 4, nrb = (G * P + MB_M - 1) / MB_M;
   const int cols = kVariantCols[v];
-  dim3 grid(cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32, (G * P + MB_M - 1) / MB_M);
-  const int32_t* tl = cols == 128 ? L.d_tiles128.p : cols == 64 ? L.d_tiles64.p : L.d_tiles32.p;
-  if (f->f32)
-    launch_m2l_variant<float>(v, grid, st, P, G * P, RB, KB, tl, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_U32.p,
-                              L.d_mom.p, L.d_stage32.p);
-  else
-    launch_m2l_variant<double>(v, grid, st, P, G * P, RB, KB, tl, L.d_pairs_by_slot.p, L.d_il_src.p, L.d_Uf.p,
-                               L.d_mom.p, L.d_stage.p);
+  M2LWork W{};
+  int total = 0;
+  for (int l = f->D; l > f->D - n && l >= 2; --l) {
+    const FmmLevel& L = f->lev[l];
+    if (L.npair == 0) continue;
+    M2LLevelWork& Lw = W.lev[W.nlev++];
+    Lw.ntiles = cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32;
+    Lw.tiles = cols == 128 ? L.d_tiles128.p : cols == 64 ? L.d_tiles64.p : L.d_tiles32.p;
+    Lw.pairs_by_slot = L.d_pairs_by_slot.p;
+    Lw.il_src = L.d_il_src.p;
+    Lw.mom = L.d_mom.p;
+    if (f->f32) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
+    else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
+    Lw.item0 = total;
+    total += Lw.ntiles * nrb;
+  }
+  W.total = total;
+  if (total == 0) return;
+  const bool pers = persistent && total > f->persistent_grid;
+  const int grid = pers ? f->persistent_grid : total;
+  if (f->f32) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
+  else launch_m2l_variant<double>(v, pers, grid, st, P, G * P, RB, KB, W);
   TDBEM_HIP(hipGetLastError());
 }
 
-// Pick the fastest tile variant per level: each variant runs a few times on the
-// level's real interaction lists (moments are zero at this point; the work does
-// not depend on their values) and is timed with HIP events.
-static void autotune_m2l(Fmm* f, int P, int G, hipStream_t st) {
-  hipEvent_t e0, e1;
-  TDBEM_HIP(hipEventCreate(&e0));
-  TDBEM_HIP(hipEventCreate(&e1));
-  for (int l = 2; l <= f->D; ++l) {
-    FmmLevel& L = f->lev[l];
-    if (L.npair == 0) continue;
+// Autotuner table shared by all contexts of the process: the fastest
+// (tile variant, persistent) for a launch, keyed by operator size P, blocks G,
+// precision, levels in the launch and the work size in powers of two.
+struct M2LKey {
+  int P, G, f32, nlev, bucket;
+  bool operator<(const M2LKey& o) const {
+    return std::tie(P, G, f32, nlev, bucket) < std::tie(o.P, o.G, o.f32, o.nlev, o.bucket);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<M2LKey, int> g_tune_table;
+
+static int m2l_work_items(const Fmm* f, int n, int cols) {
+  const int nrb = (f->G * f->P + MB_M - 1) / MB_M;
+  int total = 0;
+  for (int l = f->D; l > f->D - n && l >= 2; --l) {
+    const FmmLevel& L = f->lev[l];
+    if (L.npair) total += (cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32) * nrb;
+  }
+  return total;
+}
+
+static void autotune_m2l(Fmm* f, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (int n = 1; n <= f->D - 1; ++n) {
+    const int items = m2l_work_items(f, n, 64);
+    int bucket = 0;
+    while ((1 << bucket) < items) ++bucket;
+    const M2LKey key{f->P, f->G, f->f32 ? 1 : 0, n, bucket};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_table.find(key);
+      if (it != g_tune_table.end()) { f->m2l_choice[n] = it->second; continue; }
+    }
+    if (!e0) {
+      TDBEM_HIP(hipEventCreate(&e0));
+      TDBEM_HIP(hipEventCreate(&e1));
+    }
     float best = 1e30f;
-    for (int v = 0; v < M2L_VARIANTS; ++v) {
-      launch_m2l_level(f, L, P, G, st, v);  // warm-up
+    int bestc = 4;
+    for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
+      if ((c & 1) && m2l_work_items(f, n, kVariantCols[c >> 1]) <= f->persistent_grid) continue;
+      launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
-      for (int r = 0; r < 3; ++r) launch_m2l_level(f, L, P, G, st, v);
+      for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
       TDBEM_HIP(hipEventRecord(e1, st));
       TDBEM_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) { best = ms; L.variant = v; }
+      if (ms < best) { best = ms; bestc = c; }
     }
+    f->m2l_choice[n] = bestc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_table[key] = bestc;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
 }
 
 Fmm* fmm_create(tdbem_ctx* ctx) {
@@ -965,7 +1060,13 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       TDBEM_HIP(hipStreamSynchronize(st));  // temporaries (d_so) are released at scope end
     }
     TDBEM_HIP(hipStreamSynchronize(st));
-    autotune_m2l(f, P, G, st);
+    {
+      int dev = 0, ncu = 0;
+      TDBEM_HIP(hipGetDevice(&dev));
+      TDBEM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      f->persistent_grid = std::max(8, (ncu * 2 / 8) * 8);  // two workgroups per CU, a multiple of 8
+    }
+    autotune_m2l(f, st);
     return f;
   } catch (...) {
     delete f;
@@ -1041,41 +1142,55 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
   const double* St = T + 2 * f->pt * f->pt;
   const double* Tt = St + 2 * f->ps * f->ps;
   const size_t shm = 2 * (size_t)P * sizeof(double);
+  // levels whose source interval ends now: D, D-1, ..., D-ndue+1
+  int ndue = 0;
   for (int l = D; l >= 2; --l) {
     const int Ml = f->m_leaf * (1 << (D - l));
     if ((beta + 2) % Ml != 0) break;
-    const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
-    FmmLevel& L = f->lev[l];
-    if (L.npair > 0) {
-      {
-        ProfScope ps(ctx, K_M2L_GEMM);
-        launch_m2l_level(f, L, P, G, st);
-      }
-      ProfScope ps(ctx, K_M2L_RED);
-      dim3 g2(L.ncell, G, (P + 255) / 256);
-      const int bs = std::min(256, ((P + 63) / 64) * 64);
-      if (f->f32)
-        m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
-                                                     L.d_ring.p, L.d_dp.p);
-      else
-        m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage.p, L.ncell,
-                                                      L.d_ring.p, L.d_dp.p);
-      TDBEM_HIP(hipGetLastError());
-      const int64_t nrec = (int64_t)L.ncell * P;
-      m2l_recurrence_kernel<<<(unsigned)((nrec + 255) / 256), 256, 0, st>>>(P, f->mu, ctx->d, f->R, k,
-                                                                             ctx->c * Ml * ctx->dt, L.ncell,
-                                                                             L.d_dp.p, L.d_ring.p, L.d_lp.p,
-                                                                             L.d_aux.p);
-      TDBEM_HIP(hipGetLastError());
-    }
-    if (l > 2) {
+    ++ndue;
+  }
+  if (ndue > 0) {
+    // M2M first (bottom-up: a parent's moments are complete before its own
+    // products); it only reads each level's moments, so one M2L launch can then
+    // take every due level
+    for (int l = D; l > D - ndue && l > 2; --l) {
+      const int Ml = f->m_leaf * (1 << (D - l));
+      const int k = (beta + 2) / Ml - 1;
+      FmmLevel& L = f->lev[l];
       FmmLevel& Pl = f->lev[l - 1];
       ProfScope ps(ctx, K_M2M);
       m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
                                                          L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p);
       TDBEM_HIP(hipGetLastError());
     }
-    TDBEM_HIP(hipMemsetAsync(L.d_mom.p, 0, L.d_mom.n * sizeof(double), st));
+    {
+      ProfScope ps(ctx, K_M2L_GEMM);
+      launch_m2l_levels(f, ndue, f->m2l_choice[ndue], st);
+    }
+    for (int l = D; l > D - ndue; --l) {
+      const int Ml = f->m_leaf * (1 << (D - l));
+      const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
+      FmmLevel& L = f->lev[l];
+      if (L.npair > 0) {
+        ProfScope ps(ctx, K_M2L_RED);
+        dim3 g2(L.ncell, G, (P + 255) / 256);
+        const int bs = std::min(256, ((P + 63) / 64) * 64);
+        if (f->f32)
+          m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
+                                                       L.d_ring.p, L.d_dp.p);
+        else
+          m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage.p, L.ncell,
+                                                        L.d_ring.p, L.d_dp.p);
+        TDBEM_HIP(hipGetLastError());
+        const int64_t nrec = (int64_t)L.ncell * P;
+        m2l_recurrence_kernel<<<(unsigned)((nrec + 255) / 256), 256, 0, st>>>(P, f->mu, ctx->d, f->R, k,
+                                                                               ctx->c * Ml * ctx->dt, L.ncell,
+                                                                               L.d_dp.p, L.d_ring.p, L.d_lp.p,
+                                                                               L.d_aux.p);
+        TDBEM_HIP(hipGetLastError());
+      }
+      TDBEM_HIP(hipMemsetAsync(L.d_mom.p, 0, L.d_mom.n * sizeof(double), st));
+    }
   }
   // L2L for the target intervals that start at the next step, top-down
   const int anext = beta + 2;
@@ -1099,9 +1214,9 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   info->mu = f->mu;
   info->m_leaf = f->m_leaf;
   int64_t bytes = 0;
+  for (int n = 1; n < f->D && n < 16; ++n) info->m2l_variant[n] = f->m2l_choice[n];
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
-    info->m2l_variant[l] = f->lev[l].variant;
     bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
   }
   info->m2l_matrix_bytes = bytes;

@@ -35,7 +35,8 @@ constexpr int NPARAM = OFF_B4 + 1;
 static_assert(NPARAM == TDBEM_MLP_NPARAM, "packed parameter layout");
 static_assert(OFF_W2 % 4 == 0 && OFF_W3 % 4 == 0, "16-byte aligned weight rows");
 
-constexpr int FR = 64;          // rows per workgroup (forward, backward)
+constexpr int FR = 64;          // rows per workgroup (backward)
+constexpr int FFR = 32;         // rows per workgroup (forward)
 constexpr int HS = WID + 8;     // LDS row stride of bf16 activations (elements)
 constexpr int DS = WID + 4;     // LDS row stride of FP32 gradients
 constexpr int WG_SPLIT = 8;     // row splits of the weight-gradient products
@@ -52,12 +53,17 @@ __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t
 __device__ inline float round_bf16(float f) { return from_bf16(to_bf16(f)); }
 
 // ---------------------------------------------------------------------------
-// Forward: one workgroup (4 waves) per 64 rows; activations stay in LDS as
-// bf16; wave w computes output neurons [64 w, 64 w + 64) for all 64 rows.
+// Forward: one workgroup (4 waves) per FR rows; activations stay in LDS as
+// bf16; wave w computes output neurons [64 w, 64 w + 64) for all FR rows.  The
+// weight fragments of the next K step are loaded while the current one is
+// multiplied.
 
+template <int FR>
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ P, int n,
                                                       const float* __restrict__ feat, float* __restrict__ y,
                                                       uint16_t* __restrict__ act) {
+  constexpr int RT = FR / 16;     // row tiles per wave
+  constexpr int TPR = 256 / FR;   // threads per row in the output layer
   __shared__ __align__(16) uint16_t H[2][FR * HS];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -75,25 +81,30 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
     const float* B = P + (layer == 0 ? OFF_B1 : layer == 1 ? OFF_B2 : OFF_B3);
     const uint16_t* Hin = H[layer & 1];
     uint16_t* Hout = H[(layer + 1) & 1];
-    f4 acc[4][4];
+    f4 acc[4][RT];
     for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < RT; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    float4 wn[4];
+    for (int t = 0; t < 4; ++t)
+      wn[t] = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + 4 * lk);
     for (int k0 = 0; k0 < K; k0 += 16) {
-      s4 av[4], bv[4];
-      for (int t = 0; t < 4; ++t) {
-        const int o = w * 64 + t * 16 + li;
-        const float4 wv = *reinterpret_cast<const float4*>(W + (int64_t)o * K + k0 + 4 * lk);
-        av[t] = s4{(short)to_bf16(wv.x), (short)to_bf16(wv.y), (short)to_bf16(wv.z), (short)to_bf16(wv.w)};
-        const uint2 hv = *reinterpret_cast<const uint2*>(Hin + (t * 16 + li) * HS + k0 + 4 * lk);
-        bv[t] = __builtin_bit_cast(s4, hv);
+      s4 av[4], bv[RT];
+      for (int t = 0; t < 4; ++t)
+        av[t] = s4{(short)to_bf16(wn[t].x), (short)to_bf16(wn[t].y), (short)to_bf16(wn[t].z), (short)to_bf16(wn[t].w)};
+      if (k0 + 16 < K)
+        for (int t = 0; t < 4; ++t)
+          wn[t] = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + k0 + 16 + 4 * lk);
+      for (int b = 0; b < RT; ++b) {
+        const uint2 hv = *reinterpret_cast<const uint2*>(Hin + (b * 16 + li) * HS + k0 + 4 * lk);
+        bv[b] = __builtin_bit_cast(s4, hv);
       }
       for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < RT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     for (int a = 0; a < 4; ++a) {
       const int o0 = w * 64 + a * 16 + 4 * lk;
       const float4 bias = *reinterpret_cast<const float4*>(B + o0);
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < RT; ++b) {
         const int r = b * 16 + li;
         const uint16_t h0 = to_bf16(fmaxf(acc[a][b][0] + bias.x, 0.f));
         const uint16_t h1 = to_bf16(fmaxf(acc[a][b][1] + bias.y, 0.f));
@@ -106,12 +117,11 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
     }
     __syncthreads();
   }
-  // output layer (h3 is in H[1]): 4 lanes per row, 64 inputs each
-  const int r = tid >> 2, q = tid & 3;
+  // output layer (h3 is in H[1]): TPR lanes per row, WID / TPR inputs each
+  const int r = tid / TPR, q = tid % TPR;
   float s = 0.f;
-  for (int k = q * 64; k < q * 64 + 64; ++k) s += round_bf16(P[OFF_W4 + k]) * from_bf16(H[1][r * HS + k]);
-  s += __shfl_xor(s, 1);
-  s += __shfl_xor(s, 2);
+  for (int k = q * (WID / TPR); k < (q + 1) * (WID / TPR); ++k) s += round_bf16(P[OFF_W4 + k]) * from_bf16(H[1][r * HS + k]);
+  for (int m = 1; m < TPR; m <<= 1) s += __shfl_xor(s, m);
   if (q == 0 && row0 + r < n) y[row0 + r] = s + P[OFF_B4];
 }
 
@@ -375,7 +385,7 @@ __global__ void mlp_target_kernel(int ns, int beta, const double* __restrict__ h
 
 void launch_fwd(const float* P, int n, const float* feat, float* y, uint16_t* act, hipStream_t st) {
   if (n <= 0) return;
-  mlp_fwd_kernel<<<(n + FR - 1) / FR, 256, 0, st>>>(P, n, feat, y, act);
+  mlp_fwd_kernel<FFR><<<(n + FFR - 1) / FFR, 256, 0, st>>>(P, n, feat, y, act);
   TDBEM_HIP(hipGetLastError());
 }
 
