@@ -81,6 +81,9 @@ typedef struct {
   int gmres_maxiter; /* default 300 */
   int nt_max;        /* largest Nt the context will march (sizes the history), default 4096 */
   int guess;         /* tdbem_guess */
+  int graph;         /* 1: tdbem_run from a reset context captures the whole march into a HIP graph once and
+                        replays it on later runs with the same nt and forcing (per-step solves then use the
+                        single-workgroup GMRES kernel; profiling and training records run without the graph) */
 } tdbem_opts;
 
 typedef struct {
@@ -176,6 +179,19 @@ int tdbem_step(struct tdbem_ctx *ctx, const double *dev_forcing, const double *d
  * boundary condition.  info may be NULL. */
 int tdbem_run(struct tdbem_ctx *ctx, int nt, const double *dev_forcing, const tdbem_incident *inc,
               double *dev_x_hist_out, tdbem_run_info *info);
+
+/* March n independent contexts together (many scatterers on one GPU).
+ * Context i marches from its current position to alpha = nt[i]-1 under the
+ * incident wave inc[i] (inc NULL: zero forcing), homogeneous boundary
+ * condition, like tdbem_run.  Contexts created with opts.graph = 1 launch
+ * their captured march graphs; the others are stepped in lock-step, one step
+ * of every context in turn.  Contexts on distinct HIP streams run
+ * concurrently.  dev_x_hist_out: NULL or n pointers ((nt[i]-1) x Ns each, or
+ * NULL); info: NULL or n records.  *wall_ms (may be NULL): host wall time from
+ * the first launch to the end of the last context.  Returns the first error;
+ * each context's message is in its tdbem_last_error. */
+int tdbem_run_batch(struct tdbem_ctx *const *ctxs, int n, const int *nt, const tdbem_incident *inc,
+                    double *const *dev_x_hist_out, tdbem_run_info *info, double *wall_ms);
 
 /* Copy the stored coefficients beta = 0..nsteps-1 to dev_u, dev_q (nsteps x Ns each; either may be NULL). */
 int tdbem_get_history(struct tdbem_ctx *ctx, int nsteps, double *dev_u, double *dev_q);

@@ -14,7 +14,7 @@ from . import _native as N
 from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
                       INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
 
-__all__ = ["TDBEM", "TDBEMError", "incident", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
+__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
            "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP"]
 
 
@@ -52,12 +52,38 @@ def incident(inc: dict):
     return s
 
 
+def run_batch(solvers, nts, incs=None, out=True):
+    """March several contexts together (tdbem_run_batch).  nts: steps per context;
+    incs: incident dicts (or None for zero forcing).  Returns (histories or None,
+    per-context run info dicts, wall milliseconds)."""
+    torch = _torch()
+    n = len(solvers)
+    L = N.lib()
+    ctxs = (ctypes.c_void_p * n)(*[s._h for s in solvers])
+    nt_arr = (ctypes.c_int * n)(*[int(x) for x in nts])
+    inc_arr = None
+    if incs is not None:
+        inc_arr = (N.Incident * n)(*[incident(x) for x in incs])
+    outs = None
+    out_arr = None
+    if out:
+        outs = [torch.empty(int(nts[i]) - 1, s.ns, dtype=torch.float64, device=s.device) for i, s in enumerate(solvers)]
+        out_arr = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    infos = (N.RunInfo * n)()
+    wall = ctypes.c_double(0.0)
+    rc = L.tdbem_run_batch(ctxs, n, nt_arr, inc_arr, out_arr, infos, ctypes.byref(wall))
+    if rc < 0:
+        msgs = [L.tdbem_last_error(s._h).decode() for s in solvers]
+        raise TDBEMError(rc, "; ".join(m for m in msgs if m) or L.tdbem_last_error(None).decode())
+    return outs, [{k: getattr(r, k) for k, _ in N.RunInfo._fields_} for r in infos], wall.value
+
+
 class TDBEM:
     """One scatterer: a context of the HIP library (tdbem_create ... tdbem_destroy)."""
 
     def __init__(self, xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, *, use_fmm=0, depth=4, p_s=4, p_t=4, mu=0,
                  m2l_prec=M2L_FP64, gmres_tol=1e-12, gmres_restart=30, gmres_maxiter=300, nt_max=4096,
-                 guess=GUESS_EXTRAP, device=None):
+                 guess=GUESS_EXTRAP, graph=False, stream=None, device=None):
         torch = _torch()
         self._L = N.lib()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -66,9 +92,13 @@ class TDBEM:
         mesh = N.Mesh(xyz.shape[0], tri.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                       tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         o = N.Opts(int(use_fmm), int(depth), int(p_s), int(p_t), int(mu), int(m2l_prec), float(gmres_tol),
-                   int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess))
-        with torch.cuda.device(self.device):
-            stream = torch.cuda.current_stream(self.device).cuda_stream
+                   int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess), int(bool(graph)))
+        self.stream = stream  # a torch.cuda.Stream the context works on (kept alive), or None
+        if stream is not None:
+            stream = stream.cuda_stream
+        else:
+            with torch.cuda.device(self.device):
+                stream = torch.cuda.current_stream(self.device).cuda_stream
         h = ctypes.c_void_p()
         rc = self._L.tdbem_create(ctypes.byref(mesh), float(c), float(dt), int(d), int(bie), int(bc),
                                   ctypes.byref(o), ctypes.c_void_p(stream), ctypes.byref(h))

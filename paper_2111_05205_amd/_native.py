@@ -22,7 +22,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("use_fmm", ctypes.c_int), ("depth", ctypes.c_int), ("p_s", ctypes.c_int), ("p_t", ctypes.c_int),
                 ("mu", ctypes.c_int), ("m2l_prec", ctypes.c_int), ("gmres_tol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int), ("gmres_maxiter", ctypes.c_int), ("nt_max", ctypes.c_int),
-                ("guess", ctypes.c_int)]
+                ("guess", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 class Incident(ctypes.Structure):
@@ -88,6 +88,8 @@ def lib():
         L.tdbem_mlp_mse.argtypes = [ip, vp, vp, vp, vp, vp]
         L.tdbem_mlp_adam_step.argtypes = [vp, vp, vp, vp, ip, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                           ctypes.c_float, vp]
+        L.tdbem_run_batch.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Incident),
+                                      ctypes.POINTER(vp), ctypes.POINTER(RunInfo), dp]
         L.tdbem_mlp_load.argtypes = [vp, vp]
         L.tdbem_mlp_record.argtypes = [vp, vp, vp]
         _lib = L

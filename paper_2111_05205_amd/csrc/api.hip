@@ -39,6 +39,8 @@ static int guarded(tdbem_ctx* ctx, F&& f) {
 
 static void fail(int code, const std::string& m) { throw Error(code, m); }
 
+#define TDBEM_HIP_NOTHROW(call) (void)(call)
+
 namespace tdbem {
 void set_global_error(const std::string& msg) { g_create_err = msg; }
 }  // namespace tdbem
@@ -259,6 +261,132 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   ctx->alpha = alpha + 1;
 }
 
+// ---------------------------------------------------------------------------
+// March drivers shared by tdbem_run and tdbem_run_batch.
+
+static const double* run_prepare(tdbem_ctx* ctx, int nt, const double* dev_forcing, const tdbem_incident* inc) {
+  if (nt < 2 || nt > ctx->nt_max) fail(TDBEM_E_INVAL, "nt out of range [2, nt_max]");
+  if (ctx->alpha > nt - 1) fail(TDBEM_E_STATE, "march already past nt-1; call tdbem_reset");
+  if (dev_forcing) return dev_forcing;
+  if (!inc) return nullptr;
+  const size_t need = (size_t)(nt - 1) * ctx->ns;
+  if (ctx->d_forc.n < need) ctx->d_forc.alloc(need);
+  launch_forcing(ctx, *inc, 1, nt - 1, ctx->d_forc.p);
+  return ctx->d_forc.p;
+}
+
+static bool use_graph(const tdbem_ctx* ctx) {
+  return ctx->opts.graph && ctx->alpha == 1 && !ctx->prof && !ctx->rec_feat;
+}
+
+static void march_steps(tdbem_ctx* ctx, int nt, const double* forc) {
+  for (int alpha = ctx->alpha; alpha <= nt - 1; ++alpha)
+    do_step(ctx, forc ? forc + (size_t)(alpha - 1) * ctx->ns : ctx->d_zero.p, nullptr, ctx->d_stat.p + (alpha - 1));
+}
+
+// Capture the march from alpha = 1 to nt-1 into a graph (host work only: the
+// launches are recorded, not run) unless one for (nt, forcing) exists.  The
+// host-side state a march leaves behind is kept for the replays.
+static void ensure_graph(tdbem_ctx* ctx, int nt, const double* forc) {
+  if (ctx->g_exec && ctx->g_nt == nt && ctx->g_forc == forc) return;
+  if (ctx->g_exec) {
+    (void)hipGraphExecDestroy(ctx->g_exec);
+    ctx->g_exec = nullptr;
+  }
+  if (!ctx->cap_stream) TDBEM_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  const hipStream_t user = ctx->stream;
+  const int a0 = ctx->alpha;
+  const bool hu0 = ctx->hist_u, hq0 = ctx->hist_q;
+  ctx->stream = ctx->cap_stream;
+  ctx->capturing = true;
+  hipGraph_t g = nullptr;
+  TDBEM_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  try {
+    march_steps(ctx, nt, forc);
+  } catch (...) {
+    (void)hipStreamEndCapture(ctx->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    ctx->stream = user;
+    ctx->capturing = false;
+    ctx->alpha = a0;
+    ctx->hist_u = hu0;
+    ctx->hist_q = hq0;
+    throw;
+  }
+  e = hipStreamEndCapture(ctx->stream, &g);
+  ctx->stream = user;
+  ctx->capturing = false;
+  ctx->g_alpha = ctx->alpha;
+  ctx->g_hu = ctx->hist_u;
+  ctx->g_hq = ctx->hist_q;
+  ctx->alpha = a0;
+  ctx->hist_u = hu0;
+  ctx->hist_q = hq0;
+  if (e != hipSuccess) fail(TDBEM_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&ctx->g_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ctx->g_exec = nullptr;
+    fail(TDBEM_E_DEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+  }
+  ctx->g_nt = nt;
+  ctx->g_forc = forc;
+}
+
+// Issue the march on the context stream: the captured graph, or step by step.
+static void run_launch(tdbem_ctx* ctx, int nt, const double* forc) {
+  if (use_graph(ctx)) {
+    ensure_graph(ctx, nt, forc);
+    TDBEM_HIP(hipGraphLaunch(ctx->g_exec, ctx->stream));
+    ctx->alpha = ctx->g_alpha;
+    ctx->hist_u = ctx->g_hu;
+    ctx->hist_q = ctx->g_hq;
+  } else {
+    march_steps(ctx, nt, forc);
+  }
+}
+
+// Wait for the march, copy the history out and summarise the per-step records.
+static int run_finish(tdbem_ctx* ctx, int nt, int a_first, double* dev_x_hist_out, tdbem_run_info* info,
+                      hipEvent_t e0, hipEvent_t e1) {
+  const int ns = ctx->ns;
+  int rc = TDBEM_OK;
+  if (dev_x_hist_out) {
+    const double* src = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
+    TDBEM_HIP(hipMemcpyAsync(dev_x_hist_out, src, (size_t)(nt - 1) * ns * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->stream));
+  }
+  std::vector<StepStat> st(nt - 1);
+  TDBEM_HIP(hipMemcpyAsync(st.data(), ctx->d_stat.p, (nt - 1) * sizeof(StepStat), hipMemcpyDeviceToHost,
+                           ctx->stream));
+  TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  float ms = 0.f;
+  TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tdbem_run_info ri{};
+  ri.march_ms = ms;
+  for (int a = a_first; a <= nt - 1; ++a) {
+    const StepStat& s = st[a - 1];
+    ri.steps++;
+    ri.total_iters += s.iters;
+    ri.max_iters = std::max(ri.max_iters, s.iters);
+    ri.max_resid = std::max(ri.max_resid, s.resid);
+    if (s.flags & 4) ri.guesses_rejected++;
+    if (s.flags & 8) ri.guesses_replaced++;
+    if ((s.flags & 2) && rc == TDBEM_OK) {
+      rc = TDBEM_E_DIVERGED;
+      ctx->err = "non-finite or exploding solution at step " + std::to_string(a);
+    } else if ((s.flags & 1) && rc == TDBEM_OK) {
+      rc = TDBEM_E_NOT_CONVERGED;
+      ctx->err = "GMRES did not converge at step " + std::to_string(a);
+    }
+  }
+  if (info) *info = ri;
+  return rc;
+}
+
 extern "C" {
 
 int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, int bc, const tdbem_opts* opts,
@@ -379,6 +507,8 @@ void tdbem_destroy(tdbem_ctx* ctx) {
   if (!ctx) return;
   for (auto& e : ctx->prof_ev) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
   if (ctx->fmm) fmm_destroy(ctx->fmm);
+  if (ctx->g_exec) (void)hipGraphExecDestroy(ctx->g_exec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -477,52 +607,77 @@ int tdbem_run(tdbem_ctx* ctx, int nt, const double* dev_forcing, const tdbem_inc
   if (!ctx) return TDBEM_E_INVAL;
   int rc = TDBEM_OK;
   int r = guarded(ctx, [&] {
-    if (nt < 2 || nt > ctx->nt_max) fail(TDBEM_E_INVAL, "nt out of range [2, nt_max]");
     const int a_first = ctx->alpha;
-    if (a_first > nt - 1) fail(TDBEM_E_STATE, "march already past nt-1; call tdbem_reset");
-    const int ns = ctx->ns;
-    const double* forc = dev_forcing;
-    if (!forc && inc) {
-      ctx->d_forc.alloc((size_t)(nt - 1) * ns);
-      launch_forcing(ctx, *inc, 1, nt - 1, ctx->d_forc.p);
-      forc = ctx->d_forc.p;
-    }
+    const double* forc = run_prepare(ctx, nt, dev_forcing, inc);
     hipEvent_t e0, e1;
     TDBEM_HIP(hipEventCreate(&e0));
     TDBEM_HIP(hipEventCreate(&e1));
     TDBEM_HIP(hipEventRecord(e0, ctx->stream));
-    for (int alpha = a_first; alpha <= nt - 1; ++alpha)
-      do_step(ctx, forc ? forc + (size_t)(alpha - 1) * ns : ctx->d_zero.p, nullptr, ctx->d_stat.p + (alpha - 1));
+    run_launch(ctx, nt, forc);
     TDBEM_HIP(hipEventRecord(e1, ctx->stream));
-    if (dev_x_hist_out) {
-      const double* src = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
-      TDBEM_HIP(hipMemcpyAsync(dev_x_hist_out, src, (size_t)(nt - 1) * ns * sizeof(double),
-                               hipMemcpyDeviceToDevice, ctx->stream));
-    }
-    std::vector<StepStat> st(nt - 1);
-    TDBEM_HIP(hipMemcpyAsync(st.data(), ctx->d_stat.p, (nt - 1) * sizeof(StepStat), hipMemcpyDeviceToHost,
-                             ctx->stream));
-    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
-    float ms = 0.f;
-    TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    tdbem_run_info ri{};
-    ri.march_ms = ms;
-    for (int a = a_first; a <= nt - 1; ++a) {
-      const StepStat& s = st[a - 1];
-      ri.steps++;
-      ri.total_iters += s.iters;
-      ri.max_iters = std::max(ri.max_iters, s.iters);
-      ri.max_resid = std::max(ri.max_resid, s.resid);
-      if (s.flags & 4) ri.guesses_rejected++;
-      if (s.flags & 8) ri.guesses_replaced++;
-      if ((s.flags & 2) && rc == TDBEM_OK) { rc = TDBEM_E_DIVERGED; ctx->err = "non-finite or exploding solution at step " + std::to_string(a); }
-      else if ((s.flags & 1) && rc == TDBEM_OK) { rc = TDBEM_E_NOT_CONVERGED; ctx->err = "GMRES did not converge at step " + std::to_string(a); }
-    }
-    if (info) *info = ri;
+    rc = run_finish(ctx, nt, a_first, dev_x_hist_out, info, e0, e1);
   });
   return r != TDBEM_OK ? r : rc;
+}
+
+int tdbem_run_batch(tdbem_ctx* const* ctxs, int n, const int* nt, const tdbem_incident* inc,
+                    double* const* dev_x_hist_out, tdbem_run_info* info, double* wall_ms) {
+  if (!ctxs || !nt || n < 0) { g_create_err = "run_batch: ctxs and nt are required"; return TDBEM_E_INVAL; }
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) { g_create_err = "run_batch: NULL context"; return TDBEM_E_INVAL; }
+  std::vector<const double*> forc(n);
+  std::vector<int> a_first(n);
+  std::vector<hipEvent_t> e0(n, nullptr), e1(n, nullptr);
+  std::vector<char> graphed(n, 0);
+  int first_rc = TDBEM_OK;
+  auto note = [&](int rc) { if (rc != TDBEM_OK && first_rc == TDBEM_OK) first_rc = rc; };
+  // forcing and (host-side) graph capture before anything is timed
+  for (int i = 0; i < n && first_rc == TDBEM_OK; ++i)
+    note(guarded(ctxs[i], [&] {
+      a_first[i] = ctxs[i]->alpha;
+      forc[i] = run_prepare(ctxs[i], nt[i], nullptr, inc ? &inc[i] : nullptr);
+      TDBEM_HIP(hipEventCreate(&e0[i]));
+      TDBEM_HIP(hipEventCreate(&e1[i]));
+      graphed[i] = use_graph(ctxs[i]);
+      if (graphed[i]) ensure_graph(ctxs[i], nt[i], forc[i]);
+    }));
+  if (first_rc == TDBEM_OK) {
+    for (int i = 0; i < n; ++i) TDBEM_HIP_NOTHROW(hipStreamSynchronize(ctxs[i]->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < n; ++i)
+      note(guarded(ctxs[i], [&] {
+        TDBEM_HIP(hipEventRecord(e0[i], ctxs[i]->stream));
+        if (graphed[i]) run_launch(ctxs[i], nt[i], forc[i]);
+      }));
+    // contexts without a graph: one step of each in turn
+    int amax = 0;
+    for (int i = 0; i < n; ++i) amax = std::max(amax, nt[i] - 1);
+    for (int alpha = 1; alpha <= amax && first_rc == TDBEM_OK; ++alpha)
+      for (int i = 0; i < n; ++i) {
+        tdbem_ctx* c = ctxs[i];
+        if (graphed[i] || c->alpha != alpha || alpha > nt[i] - 1) continue;
+        note(guarded(c, [&] {
+          do_step(c, forc[i] ? forc[i] + (size_t)(alpha - 1) * c->ns : c->d_zero.p, nullptr, c->d_stat.p + (alpha - 1));
+        }));
+      }
+    for (int i = 0; i < n; ++i) note(guarded(ctxs[i], [&] { TDBEM_HIP(hipEventRecord(e1[i], ctxs[i]->stream)); }));
+    for (int i = 0; i < n; ++i) TDBEM_HIP_NOTHROW(hipStreamSynchronize(ctxs[i]->stream));
+    if (wall_ms) *wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < n; ++i) {
+      int rc = TDBEM_OK;
+      note(guarded(ctxs[i], [&] {
+        rc = run_finish(ctxs[i], nt[i], a_first[i], dev_x_hist_out ? dev_x_hist_out[i] : nullptr,
+                        info ? &info[i] : nullptr, e0[i], e1[i]);
+        e0[i] = e1[i] = nullptr;
+      }));
+      note(rc);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (e0[i]) (void)hipEventDestroy(e0[i]);
+    if (e1[i]) (void)hipEventDestroy(e1[i]);
+  }
+  return first_rc;
 }
 
 int tdbem_get_history(tdbem_ctx* ctx, int nsteps, double* dev_u, double* dev_q) {

@@ -1112,6 +1112,11 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out) {
   TDBEM_HIP(hipGetLastError());
 }
 
+__global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 static int sep_threads(int P) { return std::min(1024, ((P + 63) / 64) * 64); }
 
 void fmm_advance(tdbem_ctx* ctx, int beta) {
@@ -1189,7 +1194,9 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
                                                                                L.d_aux.p);
         TDBEM_HIP(hipGetLastError());
       }
-      TDBEM_HIP(hipMemsetAsync(L.d_mom.p, 0, L.d_mom.n * sizeof(double), st));
+      // a kernel, not a memset node, so that a captured march replays correctly
+      fill_zero_kernel<<<(unsigned)((L.d_mom.n + 255) / 256), 256, 0, st>>>(L.d_mom.p, (int64_t)L.d_mom.n);
+      TDBEM_HIP(hipGetLastError());
     }
   }
   // L2L for the target intervals that start at the next step, top-down

@@ -451,7 +451,9 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, co
   int m = ctx->opts.gmres_restart;
   if (m > GM_MAXM) m = GM_MAXM;
   if (m < 1) m = 1;
-  const int nwg = ctx->gmres_wg;
+  // a cooperative launch is not captured into a graph: the single-workgroup
+  // solver serves captured marches
+  const int nwg = ctx->capturing ? 1 : ctx->gmres_wg;
   if (nwg <= 1) {
     gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, b, x,
                                                      ctx->d_V.p, m, ctx->opts.gmres_maxiter, ctx->opts.gmres_tol,

@@ -125,6 +125,15 @@ struct tdbem_ctx {
   float* rec_feat = nullptr;           // caller-owned training records (tdbem_mlp_record)
   float* rec_target = nullptr;
 
+  // captured march (opts.graph): replayed by later runs with the same nt and forcing
+  hipStream_t cap_stream = nullptr;  // non-blocking stream used only while capturing
+  bool capturing = false;
+  hipGraphExec_t g_exec = nullptr;
+  int g_nt = 0;
+  const double* g_forc = nullptr;
+  int g_alpha = 1;
+  bool g_hu = false, g_hq = false;
+
   // kernel timing (tdbem_profile)
   bool prof = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
