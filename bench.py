@@ -129,6 +129,80 @@ def run_form(P, w, args, prec, guess, params=None):
     return s, info, x, out
 
 
+def batch_bench(args):
+    """Many independent scatterers on one GPU: every instance's march is a captured
+    graph on its own stream, all launched together (tdbem_run_batch); the same
+    graphs run one after another are timed beside it."""
+    import torch
+    import synth
+    import paper_2111_05205_amd as P
+    torch.cuda.set_device(0)
+    insts = synth.batch_workload(64)
+    solvers = []
+    t0 = time.perf_counter()
+    n_direct = 0
+    for w in insts:
+        kw = dict(nt_max=w["nt"], gmres_tol=args.gmres_tol, graph=True, stream=torch.cuda.Stream())
+        try:
+            s = P.create_fmm(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], p_s=3, p_t=3,
+                             m2l_prec=P.M2L_FP32, **kw)
+        except P.TDBEMError:
+            # the surface spans only a few c*dt: no octree level is wide enough, all pairs are near
+            s = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0, **kw)
+            n_direct += 1
+        solvers.append(s)
+    setup_s = time.perf_counter() - t0
+    nts = [w["nt"] for w in insts]
+    incs = [w["inc"] for w in insts]
+    work = sum(s.ns * nt for s, nt in zip(solvers, nts))
+    for _ in range(max(args.warmup, 1)):  # the first run also captures the graphs
+        for s in solvers:
+            s.reset()
+        P.run_batch(solvers, nts, incs, out=False)
+    walls, iters = [], 0
+    for _ in range(args.steps):
+        for s in solvers:
+            s.reset()
+        torch.cuda.synchronize()
+        _, infos, wall = P.run_batch(solvers, nts, incs, out=False)
+        walls.append(wall)
+        iters += sum(r["total_iters"] for r in infos)
+    wall = sum(walls) / len(walls)
+    # the same graphs, one instance after another
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s, nt, inc in zip(solvers, nts, incs):
+        s.reset()
+        s.run(nt, inc=inc)
+        torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    flops = 0
+    for s, nt in zip(solvers, nts):
+        info = s.info()
+        if not info["use_fmm"]:
+            continue
+        G = info["mu"] + 1 + info["d"]
+        flops += m2l_flops_per_march(info, nt, info["m_leaf"], info["depth"], G, info["p_s"] ** 3 * info["p_t"])
+    achieved = flops / (wall * 1e-3) / 1e12
+    out = {"metric": METRIC, "value": round(work / (wall * 1e-3), 1), "unit": "Ns*Nt/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 (M2L products f32)", "data": "synthetic",
+           "config": {"workload": "batch64: 64 independent scatterers (ellipsoids / rounded cubes, Ns 500-8000, "
+                                  "Nt 128-512, d 1 or 2, Burton-Miller Neumann), FMM with 3 Chebyshev nodes per "
+                                  "axis, deepest octree the step allows, each march a captured graph on its own "
+                                  "stream",
+                      "instances": len(solvers), "direct_instances": n_direct, "sum_ns_nt": work,
+                      "setup_s": round(setup_s, 1),
+                      "gmres_tol": args.gmres_tol, "gmres_iters_per_batch": iters // args.steps,
+                      "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+           "roofline": {"kernel": "m2l_gemm (all instances)", "bound": "mfma", "achieved": round(achieved, 3),
+                        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                        "traffic": None, "note": "algorithmic M2L flops of the whole batch over its wall time"},
+           "sequential": {"value": round(work / seq, 1), "ms_per_step": round(seq * 1e3, 3)},
+           "batch_speedup_vs_sequential": round(seq * 1e3 / wall, 3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +232,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(value is the single-GPU throughput); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        # more hardware queues so that more instance streams run side by side (HIP reads it at start-up)
+        os.environ["GPU_MAX_HW_QUEUES"] = os.environ.get("TDBEM_BATCH_HW_QUEUES", "16")
+        batch_bench(args)
+        return
 
     import torch
     import synth

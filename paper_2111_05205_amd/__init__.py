@@ -14,7 +14,7 @@ from . import _native as N
 from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
                       INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
 
-__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
+__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
            "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP"]
 
 
@@ -50,6 +50,20 @@ def incident(inc: dict):
     s.f0, s.sigma, s.t0, s.rb = float(inc.get("f0", 1.0)), float(inc["sigma"]), float(inc.get("t0", 0.0)), \
         float(inc.get("rb", 0.0))
     return s
+
+
+def create_fmm(xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, max_depth=7, **kw):
+    """FMM context with the deepest octree (<= max_depth) whose leaves are wide
+    enough for the time step (M_leaf >= 1); other options as for TDBEM."""
+    last = None
+    for depth in range(max_depth, 1, -1):
+        try:
+            return TDBEM(xyz, tri, c, dt, d, bie, bc, use_fmm=1, depth=depth, **kw)
+        except TDBEMError as e:
+            if e.code != N.E_INVAL:
+                raise
+            last = e
+    raise last
 
 
 def run_batch(solvers, nts, incs=None, out=True):

@@ -143,18 +143,10 @@ def training_shapes(n_runs, seed=1000, freq_range=(10, 31)):
 def make_solver(xyz, tri, d=2, bie=1, bc=1, nt=256, p=4, guess=N.GUESS_EXTRAP, gmres_tol=1e-8, m2l_prec=0):
     """FMM context with the deepest octree the time step allows (dt = mean edge / c, c = 1)."""
     import synth
-    from . import TDBEM, TDBEMError
+    from . import create_fmm
     dt = synth.mean_edge_length(xyz, tri)
-    last = None
-    for depth in range(7, 1, -1):
-        try:
-            return TDBEM(xyz, tri, 1.0, dt, d, bie, bc, use_fmm=1, depth=depth, p_s=p, p_t=p, nt_max=nt,
-                         gmres_tol=gmres_tol, guess=guess, m2l_prec=m2l_prec), dt
-        except TDBEMError as e:
-            last = e
-            if e.code != N.E_INVAL:
-                raise
-    raise last
+    return create_fmm(xyz, tri, 1.0, dt, d, bie, bc, p_s=p, p_t=p, nt_max=nt, gmres_tol=gmres_tol, guess=guess,
+                      m2l_prec=m2l_prec), dt
 
 
 def generate(shapes, nt=256, rows_per_run=None, seed=0, verbose=False, **solver_kw):

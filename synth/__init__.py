@@ -177,6 +177,32 @@ def random_history(ns: int, nsteps: int, seed: int = 0, smooth: bool = True):
     return amp * np.sin(2 * np.pi * fr * t + ph) + 0.1 * rng.standard_normal((nsteps, ns))
 
 
+def batch_workload(n: int = 64, seed0: int = 0):
+    """Independent scatterers: per seed, a coin picks an ellipsoid (semi-axes
+    uniform in [0.5, 2]) or a rounded cube (half side uniform in [0.5, 2]); the
+    face count Ns = 20 f^2 with f = round(sqrt(Ns'/20)) for Ns' log-uniform in
+    [500, 8000]; Nt uniform in [128, 512]; B-spline order d in {1, 2};
+    Burton-Miller, Neumann; c = 1, dt = mean edge; plane Gaussian pulse with a
+    seeded direction."""
+    out = []
+    for k in range(n):
+        rng = np.random.default_rng(seed0 + k)
+        ns_target = float(np.exp(rng.uniform(np.log(500.0), np.log(8000.0))))
+        freq = int(np.clip(round(np.sqrt(ns_target / 20.0)), 5, 20))
+        if rng.uniform() < 0.5:
+            shape = "ellipsoid"
+            xyz, tri = ellipsoid(freq, rng.uniform(0.5, 2.0, size=3))
+        else:
+            shape = "rounded_cube"
+            xyz, tri = rounded_cube(freq, half=float(rng.uniform(0.5, 2.0)))
+        nt = int(rng.integers(128, 513))
+        d = int(rng.integers(1, 3))
+        dt = mean_edge_length(xyz, tri)
+        out.append(dict(xyz=xyz, tri=tri, shape=shape, freq=freq, ns=tri.shape[0], nt=nt, d=d, bie=1, bc=1, c=1.0,
+                        dt=dt, inc=incident_params(xyz, seed=seed0 + k)))
+    return out
+
+
 def workload(name: str):
     """Named workloads: surface, wave speed, step, order and problem type.
 
