@@ -77,6 +77,23 @@ def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0):
                       f"their {nt - 1} history sums ({sec:.1f} s); rate = rows*(Nt-1)/s"}
 
 
+def measured_traffic(prec):
+    """HBM bytes per M2L launch from the committed rocprofv3 counter summary, if it
+    was taken on the current M2L source (else None)."""
+    import hashlib
+    if prec != 1:
+        return None
+    path = os.path.join(ROOT, "profiles", "m2l_fp32_sphere5k_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2111_05205_amd", "csrc", "fmm.hip"), "rb").read()
+    except OSError:
+        return None
+    if rec.get("fmm_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def run_form(P, w, args, prec, guess, params=None):
     """Time one form of the march: K marches from a reset context after W warm-up marches."""
     import torch
@@ -115,7 +132,9 @@ def run_form(P, w, args, prec, guess, params=None):
         peak = PEAK_FP32_TFLOPS if prec == P.M2L_FP32 else PEAK_FP64_TFLOPS
         achieved = flops / (ms * 1e-3) / 1e12
         roof = {"kernel": "m2l_gemm", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(prec) if args.workload == "sphere5k" else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
     else:
         ms, n = prof["near_history"]
@@ -234,7 +253,7 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         # more hardware queues so that more instance streams run side by side (HIP reads it at start-up)
-        os.environ["GPU_MAX_HW_QUEUES"] = os.environ.get("TDBEM_BATCH_HW_QUEUES", "16")
+        os.environ["GPU_MAX_HW_QUEUES"] = os.environ.get("TDBEM_BATCH_HW_QUEUES", "32")
         batch_bench(args)
         return
 
