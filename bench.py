@@ -291,7 +291,7 @@ def main():
                       "mu": info["mu"], "m_leaf": info["m_leaf"], "near_pairs": info["near_pairs"],
                       "il_pairs": info["il_pairs"][: (info["depth"] or 0) + 1],
                       "m2l_tile_variant": info["m2l_variant"][: (info["depth"] or 0) + 1],
-                      "gmres_tol": args.gmres_tol,
+                      "gmres_tol": args.gmres_tol, "gmres_workgroups": info["gmres_workgroups"],
                       "gmres_iters_per_march": head["gmres_iters_per_march"], "setup_ms": head["setup_ms"]},
            "roofline": head["roofline"]}
     if "plain" in forms and mixed:

@@ -123,6 +123,7 @@ typedef struct {
   int m2l_variant[16];  /* [n], n = 1..depth-1: autotuned M2L launch for the n finest levels ending an interval
                            together, 2 * tile + persistent; tile 0 128x16, 1 128x32, 2 64x16, 3 64x32,
                            4 32x16, 5 32x32 (columns x K step) */
+  int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
 } tdbem_info;
 
 /* Build a context: copies and validates the mesh (closed, consistently

@@ -458,6 +458,7 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_zero.p, 0, ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    autotune_gmres(ctx);
     TDBEM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
@@ -528,6 +529,7 @@ int tdbem_get_info(const tdbem_ctx* ctx, tdbem_info* info) {
   info->near_coefs = ctx->ncoef;
   info->a_nnz = ctx->a_nnz;
   info->setup_ms = ctx->setup_ms;
+  info->gmres_workgroups = ctx->gmres_wg;
   if (ctx->fmm) fmm_info(ctx, info);
   return TDBEM_OK;
 }

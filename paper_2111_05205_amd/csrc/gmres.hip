@@ -473,16 +473,65 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, co
                                        ctx->stream));
 }
 
-int gmres_workgroups(int ns) {
-  // one workgroup per 512 rows, capped by what is guaranteed co-resident
-  int want = (ns + 511) / 512;
-  if (ns <= 2048) return 1;
+// Largest cooperative grid that is guaranteed co-resident (one workgroup per CU at most).
+static int gmres_max_workgroups() {
   int dev = 0, ncu = 0, per = 0;
   TDBEM_HIP(hipGetDevice(&dev));
   TDBEM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   TDBEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)gmres_coop_kernel, GC_THREADS, 0));
-  const int cap = std::max(1, std::min(ncu * std::max(per, 1), ncu));
-  return std::max(1, std::min(want, cap));
+  return std::max(1, std::min(ncu * std::max(per, 1), ncu));
+}
+
+int gmres_workgroups(int ns) {
+  // one workgroup per 512 rows, capped by what is guaranteed co-resident
+  if (ns <= 2048) return 1;
+  return std::max(1, std::min((ns + 511) / 512, gmres_max_workgroups()));
+}
+
+// Time the per-step solve on a fixed right-hand side (all ones, zero start) for
+// 128 ... 1024 rows per workgroup and keep the fastest workgroup count.
+void autotune_gmres(tdbem_ctx* ctx) {
+  const int ns = ctx->ns;
+  if (ns <= 2048) return;
+  const int cap = gmres_max_workgroups();
+  std::vector<int> cand;
+  for (int rows : {1024, 512, 256, 128}) {
+    const int w = std::max(1, std::min((ns + rows - 1) / rows, cap));
+    if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
+  }
+  const int wmax = *std::max_element(cand.begin(), cand.end());
+  if (ctx->d_gpart.n < (size_t)2 * wmax * 33) ctx->d_gpart.alloc((size_t)2 * wmax * 33);
+  std::vector<double> ones(ns, 1.0);
+  TDBEM_HIP(hipMemcpyAsync(ctx->d_b.p, ones.data(), ns * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  hipEvent_t e0, e1;
+  TDBEM_HIP(hipEventCreate(&e0));
+  TDBEM_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestw = ctx->gmres_wg;
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  for (int w : cand) {
+    ctx->gmres_wg = w;
+    float tot = 0.f;
+    for (int r = 0; r < 3; ++r) {
+      TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ns * sizeof(double), ctx->stream));
+      TDBEM_HIP(hipEventRecord(e0, ctx->stream));
+      launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, ctx->d_stat.p);
+      TDBEM_HIP(hipEventRecord(e1, ctx->stream));
+      TDBEM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (r > 0) tot += ms;
+    }
+    if (tot < best) { best = tot; bestw = w; }
+  }
+  ctx->prof = prof;
+  ctx->gmres_wg = bestw;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ns * sizeof(double), ctx->stream));
+  TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, sizeof(StepStat), ctx->stream));
+  TDBEM_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 }  // namespace tdbem

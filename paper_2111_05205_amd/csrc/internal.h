@@ -175,6 +175,7 @@ void upload_gl_rule();
 // xalt has the smaller residual (from zero when both are worse than zero)
 void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, const double* xalt = nullptr);
 int gmres_workgroups(int ns);
+void autotune_gmres(tdbem_ctx* ctx);  // pick the solver's workgroup count by timing (Ns > 2048)
 
 // api.hip
 void set_global_error(const std::string& msg);  // message for tdbem_last_error(NULL)
