@@ -194,6 +194,21 @@ int tdbem_run(struct tdbem_ctx *ctx, int nt, const double *dev_forcing, const td
 int tdbem_run_batch(struct tdbem_ctx *const *ctxs, int n, const int *nt, const tdbem_incident *inc,
                     double *const *dev_x_hist_out, tdbem_run_info *info, double *wall_ms);
 
+/* Checkpoint of the march state into caller-owned host memory: the position
+ * alpha, the solved coefficient rows beta = 0..alpha-2 (u and q), the FMM state
+ * carried between steps (partial moments, locals ring, recurrence terms of every
+ * level) and the learned-guess parameters if loaded.  host_buf NULL: *bytes
+ * receives the size needed.  Otherwise *bytes is the buffer size on entry and
+ * the size written on return; too small: TDBEM_E_INVAL with the size needed
+ * in *bytes. */
+int tdbem_checkpoint(struct tdbem_ctx *ctx, void *host_buf, size_t *bytes);
+
+/* Continue from a checkpoint: the context must have been created with the same
+ * mesh size, d, BIE, boundary condition and FMM parameters (else TDBEM_E_INVAL);
+ * the next tdbem_step / tdbem_run continues at the checkpoint's alpha and gives
+ * the same results as the uninterrupted march. */
+int tdbem_restore(struct tdbem_ctx *ctx, const void *host_buf, size_t bytes);
+
 /* Copy the stored coefficients beta = 0..nsteps-1 to dev_u, dev_q (nsteps x Ns each; either may be NULL). */
 int tdbem_get_history(struct tdbem_ctx *ctx, int nsteps, double *dev_u, double *dev_q);
 

@@ -207,6 +207,19 @@ class TDBEM:
         self._check(self._L.tdbem_profile_read(self._h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(N.PROF_KINDS)}
 
+    def checkpoint(self):
+        """State of the march as bytes (tdbem_checkpoint)."""
+        n = ctypes.c_size_t(0)
+        self._check(self._L.tdbem_checkpoint(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self._L.tdbem_checkpoint(self._h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def restore(self, data: bytes):
+        """Continue from a checkpoint taken by checkpoint() (tdbem_restore)."""
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        self._check(self._L.tdbem_restore(self._h, buf, len(data)))
+
     def mlp_load(self, params):
         """Use the network with these packed FP32 parameters (CUDA tensor) when guess=GUESS_MLP."""
         from .mlp import _fptr

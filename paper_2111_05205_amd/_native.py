@@ -90,6 +90,8 @@ def lib():
                                           ctypes.c_float, vp]
         L.tdbem_run_batch.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Incident),
                                       ctypes.POINTER(vp), ctypes.POINTER(RunInfo), dp]
+        L.tdbem_checkpoint.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.tdbem_restore.argtypes = [vp, vp, ctypes.c_size_t]
         L.tdbem_mlp_load.argtypes = [vp, vp]
         L.tdbem_mlp_record.argtypes = [vp, vp, vp]
         _lib = L

@@ -682,6 +682,112 @@ int tdbem_run_batch(tdbem_ctx* const* ctxs, int n, const int* nt, const tdbem_in
   return first_rc;
 }
 
+// Checkpoint layout: header, then u rows 0..alpha-2, q rows 0..alpha-2, the FMM
+// state arrays in fmm_state_buffers order, then the network parameters if loaded.
+struct CkptHeader {
+  char magic[8];
+  int32_t version, ns, d, bie, bc, use_fmm, depth, p_s, p_t, nstate;
+  int32_t alpha, hist_u, hist_q, mlp;
+  int64_t state_doubles;
+};
+
+static size_t ckpt_bytes(const tdbem_ctx* ctx, const std::vector<std::pair<double*, size_t>>& st) {
+  size_t n = sizeof(CkptHeader) + (size_t)2 * (ctx->alpha - 1) * ctx->ns * sizeof(double);
+  for (const auto& b : st) n += b.second * sizeof(double);
+  if (ctx->mlp_loaded) n += (size_t)TDBEM_MLP_NPARAM * sizeof(float);
+  return n;
+}
+
+int tdbem_checkpoint(tdbem_ctx* ctx, void* host_buf, size_t* bytes) {
+  if (!ctx || !bytes) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    std::vector<std::pair<double*, size_t>> st;
+    if (ctx->fmm) fmm_state_buffers(ctx, st);
+    const size_t need = ckpt_bytes(ctx, st);
+    if (!host_buf) { *bytes = need; return; }
+    if (*bytes < need) {
+      *bytes = need;
+      fail(TDBEM_E_INVAL, "checkpoint buffer too small (" + std::to_string(need) + " bytes needed)");
+    }
+    CkptHeader h{};
+    std::memcpy(h.magic, "TDBEMCK1", 8);
+    h.version = 1;
+    h.ns = ctx->ns; h.d = ctx->d; h.bie = ctx->bie; h.bc = ctx->bc;
+    h.use_fmm = ctx->fmm ? 1 : 0;
+    h.depth = ctx->opts.depth; h.p_s = ctx->opts.p_s; h.p_t = ctx->opts.p_t;
+    h.nstate = (int32_t)st.size();
+    h.alpha = ctx->alpha; h.hist_u = ctx->hist_u; h.hist_q = ctx->hist_q; h.mlp = ctx->mlp_loaded;
+    for (const auto& b : st) h.state_doubles += (int64_t)b.second;
+    char* p = static_cast<char*>(host_buf);
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    const size_t rows = (size_t)(ctx->alpha - 1) * ctx->ns * sizeof(double);
+    if (rows) {
+      TDBEM_HIP(hipMemcpyAsync(p, ctx->d_hu.p, rows, hipMemcpyDeviceToHost, ctx->stream));
+      p += rows;
+      TDBEM_HIP(hipMemcpyAsync(p, ctx->d_hq.p, rows, hipMemcpyDeviceToHost, ctx->stream));
+      p += rows;
+    }
+    for (const auto& b : st) {
+      TDBEM_HIP(hipMemcpyAsync(p, b.first, b.second * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      p += b.second * sizeof(double);
+    }
+    if (ctx->mlp_loaded)
+      TDBEM_HIP(hipMemcpyAsync(p, ctx->d_mlp_params.p, TDBEM_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+    *bytes = need;
+  });
+}
+
+int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
+  if (!ctx || !host_buf) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    if (bytes < sizeof(CkptHeader)) fail(TDBEM_E_INVAL, "restore: buffer smaller than a checkpoint header");
+    CkptHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (std::memcmp(h.magic, "TDBEMCK1", 8) != 0 || h.version != 1) fail(TDBEM_E_INVAL, "restore: not a checkpoint");
+    std::vector<std::pair<double*, size_t>> st;
+    if (ctx->fmm) fmm_state_buffers(ctx, st);
+    int64_t sd = 0;
+    for (const auto& b : st) sd += (int64_t)b.second;
+    if (h.ns != ctx->ns || h.d != ctx->d || h.bie != ctx->bie || h.bc != ctx->bc || h.use_fmm != (ctx->fmm ? 1 : 0) ||
+        (h.use_fmm && (h.depth != ctx->opts.depth || h.p_s != ctx->opts.p_s || h.p_t != ctx->opts.p_t)) ||
+        h.nstate != (int32_t)st.size() || h.state_doubles != sd)
+      fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a context with a different configuration");
+    if (h.alpha < 1 || h.alpha > ctx->nt_max) fail(TDBEM_E_INVAL, "restore: step beyond this context's nt_max");
+    const size_t rows = (size_t)(h.alpha - 1) * ctx->ns * sizeof(double);
+    size_t need = sizeof(CkptHeader) + 2 * rows + (size_t)sd * sizeof(double) +
+                  (h.mlp ? (size_t)TDBEM_MLP_NPARAM * sizeof(float) : 0);
+    if (bytes < need) fail(TDBEM_E_INVAL, "restore: truncated checkpoint");
+    const char* p = static_cast<const char*>(host_buf) + sizeof(CkptHeader);
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hu.p, 0, ctx->d_hu.n * sizeof(double), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_hq.p, 0, ctx->d_hq.n * sizeof(double), ctx->stream));
+    if (rows) {
+      TDBEM_HIP(hipMemcpyAsync(ctx->d_hu.p, p, rows, hipMemcpyHostToDevice, ctx->stream));
+      p += rows;
+      TDBEM_HIP(hipMemcpyAsync(ctx->d_hq.p, p, rows, hipMemcpyHostToDevice, ctx->stream));
+      p += rows;
+    }
+    for (const auto& b : st) {
+      TDBEM_HIP(hipMemcpyAsync(b.first, p, b.second * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      p += b.second * sizeof(double);
+    }
+    if (h.mlp) {
+      mlp_prepare(ctx);
+      ctx->d_mlp_params.alloc(TDBEM_MLP_NPARAM);
+      TDBEM_HIP(hipMemcpyAsync(ctx->d_mlp_params.p, p, TDBEM_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                               ctx->stream));
+      ctx->mlp_loaded = true;
+    }
+    TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->alpha = h.alpha;
+    ctx->hist_u = h.hist_u != 0;
+    ctx->hist_q = h.hist_q != 0;
+  });
+}
+
 int tdbem_get_history(tdbem_ctx* ctx, int nsteps, double* dev_u, double* dev_q) {
   if (!ctx) return TDBEM_E_INVAL;
   return guarded(ctx, [&] {

@@ -1087,6 +1087,17 @@ void fmm_reset(tdbem_ctx* ctx) {
   }
 }
 
+void fmm_state_buffers(const tdbem_ctx* ctx, std::vector<std::pair<double*, size_t>>& out) {
+  const Fmm* f = ctx->fmm;
+  for (int l = 2; l <= f->D; ++l) {
+    const FmmLevel& L = f->lev[l];
+    out.push_back({L.d_mom.p, L.d_mom.n});
+    out.push_back({L.d_ring.p, L.d_ring.n});
+    out.push_back({L.d_lp.p, L.d_lp.n});
+    out.push_back({L.d_aux.p, L.d_aux.n});
+  }
+}
+
 static TimeWeights time_weights(const Fmm* f, double xi, double ht) {
   TimeWeights tw{};
   for (int m = 0; m < f->pt; ++m) {

@@ -200,5 +200,7 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out);
 void fmm_advance(tdbem_ctx* ctx, int beta);
 void fmm_info(const tdbem_ctx* ctx, tdbem_info* info);
 void fmm_near_pairs(const tdbem_ctx* ctx, std::vector<int64_t>& row_ptr, std::vector<int32_t>& pair_j);
+// device arrays that carry FMM state from one step to the next (moments, locals, recurrence terms)
+void fmm_state_buffers(const tdbem_ctx* ctx, std::vector<std::pair<double*, size_t>>& out);
 
 }  // namespace tdbem
