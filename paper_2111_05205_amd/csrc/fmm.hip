@@ -375,8 +375,11 @@ typedef double dbl4_t __attribute__((ext_vector_type(4)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
 
 template <class T> struct Mfma;
+// kTransposed: the product is formed as (moments^T U^T) so that the output tile's
+// lanes hold consecutive operator rows of one pair (coalesced staging stores).
 template <> struct Mfma<double> {
   typedef dbl4_t acc_t;
+  static constexpr bool kTransposed = true;
   static __device__ inline acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -384,6 +387,7 @@ template <> struct Mfma<double> {
 };
 template <> struct Mfma<float> {
   typedef flt4_t acc_t;
+  static constexpr bool kTransposed = false;
   static __device__ inline acc_t op(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -517,8 +521,14 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
       for (int cb = 0; cb < NCB; ++cb) {
         if (cb < ncb) {
           const T bf = Bs[buf][4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
-          acc[0][cb] = Mfma<T>::op(ca[0][q], bf, acc[0][cb]);
-          acc[1][cb] = Mfma<T>::op(ca[1][q], bf, acc[1][cb]);
+          if constexpr (Mfma<T>::kTransposed) {
+            // A = moment tile (pair cb*16 + lane%16, k 4q + lane/16), B = operator fragment
+            acc[0][cb] = Mfma<T>::op(bf, ca[0][q], acc[0][cb]);
+            acc[1][cb] = Mfma<T>::op(bf, ca[1][q], acc[1][cb]);
+          } else {
+            acc[0][cb] = Mfma<T>::op(ca[0][q], bf, acc[0][cb]);
+            acc[1][cb] = Mfma<T>::op(ca[1][q], bf, acc[1][cb]);
+          }
         }
       }
     }
@@ -529,7 +539,26 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       if (cb >= ncb) continue;
+      if constexpr (Mfma<T>::kTransposed) {
+        // lane holds operator row lane%16 of pairs 4 r + lane/16 (r = 0..3)
+        const int row = (rb0 + h) * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int pr = pid[cb * 16 + 4 * r + (lane >> 4)];
+          if (pr >= 0 && row < GP) stage[(int64_t)pr * GP + row] = acc[h][cb][r];
+        }
+        continue;
+      }
       const int p = pid[cb * 16 + (lane & 15)];
+      if constexpr (sizeof(T) == 4) {
+        // FP32 output: the lane holds rows 4 (lane/16) .. +3 of its pair, so write
+        // them as one 16-byte vector (the four lanes of a pair: 64 contiguous bytes)
+        const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
+        if (p >= 0 && (GP & 3) == 0 && row0 + 3 < GP) {
+          *reinterpret_cast<flt4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
+          continue;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = (rb0 + h) * 16 + Mfma<T>::row(lane, r);
