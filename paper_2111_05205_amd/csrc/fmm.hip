@@ -652,25 +652,47 @@ __global__ void m2l_recurrence_kernel(int P, int mu, int d, int R, int k, double
 }
 
 // L2P: far field at (x_i, t_alpha) from the leaf local of the current interval.
-__global__ void l2p_kernel(int ns, int Ps, int pt, int bie, double inv_c, TimeWeights tw,
-                           const int32_t* __restrict__ leaf_of, const double* __restrict__ E0,
-                           const double* __restrict__ E1, const double* __restrict__ L, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ns) return;
-  const int P = Ps * pt;
-  const double* Lc = L + (int64_t)leaf_of[i] * P;
-  double s = 0.0;
-  for (int a = 0; a < Ps; ++a) {
-    double lw = 0.0, ldw = 0.0;
-    for (int m = 0; m < pt; ++m) {
-      const double v = Lc[a + Ps * m];
-      lw += v * tw.w[m];
-      ldw += v * tw.dw[m];
-    }
-    if (bie) s += E1[(int64_t)i * Ps + a] * lw - inv_c * E0[(int64_t)i * Ps + a] * ldw;
-    else s += E0[(int64_t)i * Ps + a] * lw;
+// One 64-lane wave per leaf cell: lane a takes basis functions a, a + 64, ...;
+// the local is combined in time once per leaf (value and time derivative), then
+// every element of the leaf takes a coalesced dot product with its table row.
+constexpr int L2P_MAXA = (MAXP * MAXP * MAXP + 63) / 64;
+__global__ __launch_bounds__(64) void l2p_kernel(int Ps, int pt, int bie, double inv_c, TimeWeights tw,
+                                                 const int32_t* __restrict__ leaf_ptr,
+                                                 const int32_t* __restrict__ leaf_elems, const double* __restrict__ E0,
+                                                 const double* __restrict__ E1, const double* __restrict__ L,
+                                                 double* __restrict__ out) {
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int e_begin = leaf_ptr[leaf], e_end = leaf_ptr[leaf + 1];
+  if (e_begin == e_end) return;
+  const double* Lc = L + (int64_t)leaf * Ps * pt;
+  double lw[L2P_MAXA], ldw[L2P_MAXA];
+#pragma unroll
+  for (int t = 0; t < L2P_MAXA; ++t) {
+    const int a = lane + 64 * t;
+    double v0 = 0.0, v1 = 0.0;
+    if (a < Ps)
+      for (int m = 0; m < pt; ++m) {
+        const double v = Lc[a + Ps * m];
+        v0 += v * tw.w[m];
+        v1 += v * tw.dw[m];
+      }
+    lw[t] = v0;
+    ldw[t] = v1;
   }
-  out[i] += s;
+  for (int e = e_begin; e < e_end; ++e) {
+    const int el = leaf_elems[e];
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < L2P_MAXA; ++t) {
+      const int a = lane + 64 * t;
+      if (a < Ps) {
+        if (bie) s += E1[(int64_t)el * Ps + a] * lw[t] - inv_c * E0[(int64_t)el * Ps + a] * ldw[t];
+        else s += E0[(int64_t)el * Ps + a] * lw[t];
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) out[el] += s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1147,8 +1169,8 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out) {
   TimeWeights tw = time_weights(f, (alpha * ctx->dt - center) / ht, ht);
   const double* Lk = L.d_ring.p + (int64_t)(k % f->R) * L.ncell * f->P;
   ProfScope ps(ctx, K_L2P);
-  l2p_kernel<<<(ctx->ns + 127) / 128, 128, 0, ctx->stream>>>(ctx->ns, f->Ps, f->pt, ctx->bie, 1.0 / ctx->c, tw,
-                                                             f->d_leaf_of.p, f->d_E0.p, f->d_E1.p, Lk, out);
+  l2p_kernel<<<L.ncell, 64, 0, ctx->stream>>>(f->Ps, f->pt, ctx->bie, 1.0 / ctx->c, tw, f->d_leaf_ptr.p,
+                                               f->d_leaf_elems.p, f->d_E0.p, f->d_E1.p, Lk, out);
   TDBEM_HIP(hipGetLastError());
 }
 
