@@ -11,6 +11,7 @@
 // Matrix-core lane layouts used below (16x16 output tiles, 64 lanes, lane l):
 //   bf16 16x16x16: A[i][k] at lane i + 16 (k / 4), element k % 4;
 //                  B[k][j] at lane j + 16 (k / 4), element k % 4
+//   bf16 16x16x32: the same with 8 elements per lane (k / 8, k % 8)
 //   f32  16x16x4:  A[i][k] at lane i + 16 k;  B[k][j] at lane j + 16 k
 //   output (both): D[4 (l / 16) + r][l % 16] in accumulator element r
 #include "internal.h"
@@ -42,6 +43,7 @@ constexpr int DS = WID + 4;     // LDS row stride of FP32 gradients
 constexpr int WG_SPLIT = 8;     // row splits of the weight-gradient products
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t to_bf16(float f) {
@@ -65,6 +67,7 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
   constexpr int RT = FR / 16;     // row tiles per wave
   constexpr int TPR = 256 / FR;   // threads per row in the output layer
   __shared__ __align__(16) uint16_t H[2][FR * HS];
+  __shared__ float w4s[WID];  // output-layer weights, bf16-rounded
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * FR;
@@ -74,6 +77,8 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
     if (row0 + r < n && k < NIN) v = feat[(int64_t)(row0 + r) * NINP + k];
     H[0][r * HS + k] = to_bf16(v);
   }
+  for (int k = tid; k < WID; k += 256) w4s[k] = round_bf16(P[OFF_W4 + k]);
+  const float b4 = P[OFF_B4];
   __syncthreads();
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? NINP : WID;
@@ -84,32 +89,53 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
     f4 acc[4][RT];
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < RT; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    float4 wn[4];
-    for (int t = 0; t < 4; ++t)
-      wn[t] = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + 4 * lk);
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    float4 bias[4];  // loaded ahead of the products
+    for (int a = 0; a < 4; ++a) bias[a] = *reinterpret_cast<const float4*>(B + w * 64 + a * 16 + 4 * lk);
+    if (layer == 0) {
+      // K = 16 (12 inputs and padding): one v_mfma_f32_16x16x16_bf16 step
       s4 av[4], bv[RT];
-      for (int t = 0; t < 4; ++t)
-        av[t] = s4{(short)to_bf16(wn[t].x), (short)to_bf16(wn[t].y), (short)to_bf16(wn[t].z), (short)to_bf16(wn[t].w)};
-      if (k0 + 16 < K)
-        for (int t = 0; t < 4; ++t)
-          wn[t] = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + k0 + 16 + 4 * lk);
-      for (int b = 0; b < RT; ++b) {
-        const uint2 hv = *reinterpret_cast<const uint2*>(Hin + (b * 16 + li) * HS + k0 + 4 * lk);
-        bv[b] = __builtin_bit_cast(s4, hv);
+      for (int t = 0; t < 4; ++t) {
+        const float4 wv = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + 4 * lk);
+        av[t] = s4{(short)to_bf16(wv.x), (short)to_bf16(wv.y), (short)to_bf16(wv.z), (short)to_bf16(wv.w)};
       }
+      for (int b = 0; b < RT; ++b)
+        bv[b] = __builtin_bit_cast(s4, *reinterpret_cast<const uint2*>(Hin + (b * 16 + li) * HS + 4 * lk));
       for (int a = 0; a < 4; ++a)
         for (int b = 0; b < RT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+    } else {
+      // K = 256 in 8 steps of v_mfma_f32_16x16x32_bf16: A[i][k] at lane i + 16 (k / 8), element k % 8
+      float4 wn[4][2];
+      for (int t = 0; t < 4; ++t)
+        for (int h = 0; h < 2; ++h)
+          wn[t][h] = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + 8 * lk + 4 * h);
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        b8 av[4], bv[RT];
+        for (int t = 0; t < 4; ++t) {
+          const uint4 pk = uint4{(uint32_t)to_bf16(wn[t][0].x) | ((uint32_t)to_bf16(wn[t][0].y) << 16),
+                                 (uint32_t)to_bf16(wn[t][0].z) | ((uint32_t)to_bf16(wn[t][0].w) << 16),
+                                 (uint32_t)to_bf16(wn[t][1].x) | ((uint32_t)to_bf16(wn[t][1].y) << 16),
+                                 (uint32_t)to_bf16(wn[t][1].z) | ((uint32_t)to_bf16(wn[t][1].w) << 16)};
+          av[t] = __builtin_bit_cast(b8, pk);
+        }
+        if (k0 + 32 < K)
+          for (int t = 0; t < 4; ++t)
+            for (int h = 0; h < 2; ++h)
+              wn[t][h] = *reinterpret_cast<const float4*>(W + (int64_t)(w * 64 + t * 16 + li) * K + k0 + 32 + 8 * lk +
+                                                          4 * h);
+        for (int b = 0; b < RT; ++b)
+          bv[b] = __builtin_bit_cast(b8, *reinterpret_cast<const uint4*>(Hin + (b * 16 + li) * HS + k0 + 8 * lk));
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < RT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
     }
     for (int a = 0; a < 4; ++a) {
       const int o0 = w * 64 + a * 16 + 4 * lk;
-      const float4 bias = *reinterpret_cast<const float4*>(B + o0);
       for (int b = 0; b < RT; ++b) {
         const int r = b * 16 + li;
-        const uint16_t h0 = to_bf16(fmaxf(acc[a][b][0] + bias.x, 0.f));
-        const uint16_t h1 = to_bf16(fmaxf(acc[a][b][1] + bias.y, 0.f));
-        const uint16_t h2 = to_bf16(fmaxf(acc[a][b][2] + bias.z, 0.f));
-        const uint16_t h3 = to_bf16(fmaxf(acc[a][b][3] + bias.w, 0.f));
+        const uint16_t h0 = to_bf16(fmaxf(acc[a][b][0] + bias[a].x, 0.f));
+        const uint16_t h1 = to_bf16(fmaxf(acc[a][b][1] + bias[a].y, 0.f));
+        const uint16_t h2 = to_bf16(fmaxf(acc[a][b][2] + bias[a].z, 0.f));
+        const uint16_t h3 = to_bf16(fmaxf(acc[a][b][3] + bias[a].w, 0.f));
         const uint2 pk = uint2{(uint32_t)h0 | ((uint32_t)h1 << 16), (uint32_t)h2 | ((uint32_t)h3 << 16)};
         *reinterpret_cast<uint2*>(Hout + r * HS + o0) = pk;
         if (act && row0 + r < n) *reinterpret_cast<uint2*>(act + ((int64_t)layer * n + row0 + r) * WID + o0) = pk;
@@ -120,9 +146,9 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
   // output layer (h3 is in H[1]): TPR lanes per row, WID / TPR inputs each
   const int r = tid / TPR, q = tid % TPR;
   float s = 0.f;
-  for (int k = q * (WID / TPR); k < (q + 1) * (WID / TPR); ++k) s += round_bf16(P[OFF_W4 + k]) * from_bf16(H[1][r * HS + k]);
+  for (int k = q * (WID / TPR); k < (q + 1) * (WID / TPR); ++k) s += w4s[k] * from_bf16(H[1][r * HS + k]);
   for (int m = 1; m < TPR; m <<= 1) s += __shfl_xor(s, m);
-  if (q == 0 && row0 + r < n) y[row0 + r] = s + P[OFF_B4];
+  if (q == 0 && row0 + r < n) y[row0 + r] = s + b4;
 }
 
 // ---------------------------------------------------------------------------
