@@ -131,8 +131,7 @@ typedef struct {
  * C^{(g)}_ij = sum_kappa w^kappa X^{(g-kappa)}_ij (App. A, App. B) in FP64 on the
  * device, the constant per-step matrix A (eq. linear), and with use_fmm the
  * octree, space-time hierarchy and M2L operators (Section 3, Remark precomp).
- * d in {1, 2} (d = 3 with use_fmm = 0 only: the FMM's recurrence is built for
- * d <= 2; the paper finds d = 3 unstable).  c > 0, dt > 0.  hip_stream: hipStream_t or NULL (null stream).
+ * d in {1, 2, 3} (the paper finds d = 3 unstable).  c > 0, dt > 0.  hip_stream: hipStream_t or NULL (null stream).
  * opts NULL = defaults.  On success *out owns all device memory.
  * Errors: TDBEM_E_INVAL (bad argument or mesh), TDBEM_E_NOMEM, TDBEM_E_DEVICE. */
 int tdbem_create(const tdbem_mesh *mesh, double c, double dt, int d, int bie, int bc,

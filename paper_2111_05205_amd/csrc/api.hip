@@ -398,7 +398,6 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     auto t0 = std::chrono::steady_clock::now();
     if (!(c > 0.0) || !(dt > 0.0)) fail(TDBEM_E_INVAL, "c and dt must be > 0");
     if (d < 1 || d > 3) fail(TDBEM_E_INVAL, "B-spline order d must be 1, 2 or 3");
-    if (d == 3 && opts && opts->use_fmm) fail(TDBEM_E_INVAL, "the FMM supports d <= 2; d = 3 runs with use_fmm = 0");
     if (bie != TDBEM_OBIE && bie != TDBEM_BMBIE) fail(TDBEM_E_INVAL, "bie must be OBIE (0) or BMBIE (1)");
     if (bc != TDBEM_DIRICHLET && bc != TDBEM_NEUMANN) fail(TDBEM_E_INVAL, "bc must be DIRICHLET (0) or NEUMANN (1)");
     ctx->opts = opts ? *opts : default_opts();

@@ -628,19 +628,30 @@ __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int G, int mu, i
 }
 
 // Recurrence of Algorithm 1 for source interval k, per (cell, coefficient):
-// eq. m2l_expand_rec1 (derivatives, using the auxiliaries of k-1), eq. m2l_rec
-// (local of interval k+mu+2), eq. m2l_expand_rec2 (auxiliaries).  d <= 2, so
-// the only coefficient is c_0^2(k) = 2 and the only auxiliary L^{(2,0)}.
+// eq. m2l_expand_rec1 (derivatives L^{(p)}, using the auxiliaries L^{(p,m)} of
+// k-1 with the coefficients c_m^p(k) of eq. cmp), eq. m2l_rec (local of interval
+// k+mu+2), eq. m2l_expand_rec2 (auxiliaries += L^{(p)}_{k+mu+1,k} k^m).
+// d <= 3: auxiliaries (p, m) = (2, 0), (3, 0), (3, 1) stored at (p-1)(p-2)/2 + m.
+__device__ inline double cmp_coef(int p, int m, double k) {
+  double bin = 1.0;
+  for (int q = 0; q < m; ++q) bin = bin * (p - q) / (q + 1);
+  const int e = p - m;
+  double km1 = 1.0, k0 = 1.0, kp1 = 1.0;
+  for (int q = 0; q < e; ++q) { km1 *= k - 1.0; k0 *= k; kp1 *= k + 1.0; }
+  return bin * (km1 - 2.0 * k0 + kp1) * ((m & 1) ? -1.0 : 1.0);
+}
+
 __global__ void m2l_recurrence_kernel(int P, int mu, int d, int R, int k, double T, int ncell,
                                       const double* __restrict__ dp, double* __restrict__ ring,
                                       double* __restrict__ lp, double* __restrict__ aux) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)ncell * P;
   if (idx >= n) return;
-  double Lnew[3] = {0, 0, 0};
+  const double kd = (double)k;
+  double Lnew[4] = {0, 0, 0, 0};
   for (int q = 1; q <= d; ++q) {
     double v = lp[(q - 1) * n + idx] + dp[(q - 1) * n + idx];
-    if (q == 2) v += 2.0 * aux[idx];
+    for (int m = 0; m <= q - 2; ++m) v += cmp_coef(q, m, kd) * aux[((q - 1) * (q - 2) / 2 + m) * n + idx];
     Lnew[q] = v;
     lp[(q - 1) * n + idx] = v;
   }
@@ -648,7 +659,13 @@ __global__ void m2l_recurrence_kernel(int P, int mu, int d, int R, int k, double
   double Tp = 1.0;
   for (int q = 1; q <= d; ++q) { Tp *= T; next += Lnew[q] * Tp; }
   ring[(int64_t)((k + mu + 2) % R) * n + idx] = next;
-  if (d >= 2) aux[idx] += dp[n + idx];
+  for (int q = 2; q <= d; ++q) {
+    double km = 1.0;
+    for (int m = 0; m <= q - 2; ++m) {
+      aux[((q - 1) * (q - 2) / 2 + m) * n + idx] += dp[(q - 1) * n + idx] * km;
+      km *= kd;
+    }
+  }
 }
 
 // L2P: far field at (x_i, t_alpha) from the leaf local of the current interval.
@@ -1087,7 +1104,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_mom.alloc((size_t)L.ncell * P);
       L.d_ring.alloc((size_t)f->R * L.ncell * P);
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
-      L.d_aux.alloc((size_t)std::max(1, ctx->d - 1) * L.ncell * P);
+      L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
       {
         const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;

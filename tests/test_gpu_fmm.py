@@ -46,6 +46,24 @@ def test_fmm_history_sum_matches_oracle(s3, d, bie, bc):
         assert _rel(got, want) < 1e-10, (nsteps, _rel(got, want))
 
 
+def test_fmm_history_sum_d3_matches_oracle(s3):
+    """d = 3: the recurrence with c_0^3(k) = 6k, c_1^3 = -6 and three auxiliaries.
+    Single-layer history only (the oracle's closed-form derivatives stop at d = 2)."""
+    P = _P()
+    xyz, tri, dt = s3
+    g = P.TDBEM(xyz, tri, 1.0, dt, 3, P.OBIE, P.DIRICHLET, use_fmm=1, depth=3, p_s=3, p_t=4, nt_max=64)
+    R = F.ReferenceFMM(xyz, tri, 1.0, dt, 3, 0, 3, 3, 4)
+    assert g.info()["mu"] == R.mu
+    q = synth.random_history(g.ns, 40, seed=21)
+    u0 = np.zeros_like(q)
+    dev = torch.device("cuda")
+    for nsteps in (5, 18, 37):
+        g.set_history(None, torch.tensor(q[:nsteps], device=dev))
+        got = g.fmm_eval(nsteps + 1).cpu().numpy()
+        want = R.history_rhs(nsteps + 1, u0, q)
+        assert _rel(got, want) < 1e-10, (nsteps, _rel(got, want))
+
+
 def test_fmm_single_level_p4_matches_oracle():
     P = _P()
     xyz, tri = synth.icosphere(2)
