@@ -488,13 +488,14 @@ int gmres_workgroups(int ns) {
   return std::max(1, std::min((ns + 511) / 512, gmres_max_workgroups()));
 }
 
-// Time the per-step solve on a fixed right-hand side (all ones, zero start) for
-// 128 ... 1024 rows per workgroup and keep the fastest workgroup count.
+// Time the per-step solve on a fixed right-hand side (all ones, zero start) with
+// the single-workgroup kernel and with 128 ... 1024 rows per workgroup of the
+// cooperative kernel, and keep the fastest.
 void autotune_gmres(tdbem_ctx* ctx) {
   const int ns = ctx->ns;
   if (ns <= 2048) return;
   const int cap = gmres_max_workgroups();
-  std::vector<int> cand;
+  std::vector<int> cand = {1};  // 1: the single-workgroup kernel (no grid barriers)
   for (int rows : {1024, 512, 256, 128}) {
     const int w = std::max(1, std::min((ns + rows - 1) / rows, cap));
     if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
