@@ -117,7 +117,9 @@ def run_form(P, w, args, prec, guess, params=None):
         s.reset()
         x, _ = s.run(nt, inc=w["inc"])
     torch.cuda.synchronize()
-    s.profile(True)
+    # timed region: only the dominant kernel's launches are bracketed by events
+    dom = "m2l_gemm" if use_fmm else "near_history"
+    s.profile(True, kinds=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
@@ -130,6 +132,12 @@ def run_form(P, w, args, prec, guess, params=None):
     prof = s.profile_read()
     s.profile(False)
     sec = (t1 - t0) / args.steps
+    # one more march, outside the timed region, with every category bracketed
+    s.profile(True)
+    s.reset()
+    s.run(nt, inc=w["inc"])
+    breakdown = s.profile_read()
+    s.profile(False)
     out = {"value": round(ns * nt / sec, 1), "ms_per_step": round(sec * 1e3, 3),
            "gmres_iters_per_march": iters // args.steps, "setup_ms": round(info["setup_ms"], 1)}
     if use_fmm:
@@ -152,7 +160,7 @@ def run_form(P, w, args, prec, guess, params=None):
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                 "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4)}
     out["roofline"] = roof
-    out["kernel_ms_per_march"] = {k: round(v[0] / args.steps, 2) for k, v in prof.items()}
+    out["kernel_ms_per_march"] = {k: round(v[0], 2) for k, v in breakdown.items()}
     return s, info, x, out
 
 

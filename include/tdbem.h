@@ -234,6 +234,9 @@ int tdbem_near_row(struct tdbem_ctx *ctx, int i, int cap, int32_t *j_out, int32_
 #define TDBEM_PROF_KINDS 10
 int tdbem_profile(struct tdbem_ctx *ctx, int enable);
 int tdbem_profile_read(struct tdbem_ctx *ctx, double *ms, int64_t *launches, int n);
+/* Like tdbem_profile(ctx, 1) but only the categories whose bit is set in mask
+ * are bracketed (fewer events in the stream); mask 0 disables profiling. */
+int tdbem_profile_mask(struct tdbem_ctx *ctx, unsigned mask);
 
 /* ------------------------------------------------------------------------
  * Learned initial guess (not part of the paper: the per-step system of eq.

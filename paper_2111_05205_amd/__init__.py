@@ -195,9 +195,16 @@ class TDBEM:
         self._check(self._L.tdbem_incident_forcing(self._h, ctypes.byref(incs), int(a0), int(n), _dptr(out)))
         return out
 
-    def profile(self, enable=True):
-        """Start (clear) or stop per-kernel timing of this context."""
-        self._check(self._L.tdbem_profile(self._h, int(bool(enable))))
+    def profile(self, enable=True, kinds=None):
+        """Start (clear) or stop per-kernel timing of this context; kinds: None (all)
+        or an iterable of category names (see PROF_KINDS) to bracket only those."""
+        if kinds is None or not enable:
+            self._check(self._L.tdbem_profile(self._h, int(bool(enable))))
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << N.PROF_KINDS.index(k)
+            self._check(self._L.tdbem_profile_mask(self._h, mask))
 
     def profile_read(self):
         """{category: (total ms, launches)} accumulated since profile(True)."""

@@ -490,6 +490,17 @@ int tdbem_profile(tdbem_ctx* ctx, int enable) {
     prof_collect(ctx);
     for (int k = 0; k < 16; ++k) { ctx->prof_ms[k] = 0.0; ctx->prof_cnt[k] = 0; }
     ctx->prof = enable != 0;
+    ctx->prof_mask = 0xffffffffu;
+  });
+}
+
+int tdbem_profile_mask(tdbem_ctx* ctx, unsigned mask) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    prof_collect(ctx);
+    for (int k = 0; k < 16; ++k) { ctx->prof_ms[k] = 0.0; ctx->prof_cnt[k] = 0; }
+    ctx->prof = mask != 0;
+    ctx->prof_mask = mask;
   });
 }
 

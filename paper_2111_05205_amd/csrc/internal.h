@@ -136,6 +136,7 @@ struct tdbem_ctx {
 
   // kernel timing (tdbem_profile)
   bool prof = false;
+  uint32_t prof_mask = 0xffffffffu;  // categories bracketed while profiling
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
   double prof_ms[16] = {0};
   int64_t prof_cnt[16] = {0};
@@ -152,7 +153,8 @@ struct ProfScope {
   int kind;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ProfScope(tdbem_ctx* ctx, int k) : c(ctx), kind(k) {
-    if (c->prof && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+    if (c->prof && ((c->prof_mask >> k) & 1u) && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess)
       (void)hipEventRecord(e0, c->stream);
   }
   ~ProfScope() {

@@ -44,7 +44,7 @@ def test_invalid_meshes_rejected_before_device_work():
     bad = tri.copy(); bad[3, 1] = 10 ** 6
     assert create(xyz, bad)[0] == N.E_INVAL                           # index out of range
     assert create(xyz, tri, c=-1.0)[0] == N.E_INVAL
-    assert create(xyz, tri, d=3)[0] == N.E_INVAL
+    assert create(xyz, tri, d=4)[0] == N.E_INVAL
     assert create(xyz, tri, dt=0.0)[0] == N.E_INVAL
 
 
