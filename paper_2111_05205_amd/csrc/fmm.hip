@@ -360,19 +360,27 @@ __global__ void l2l_kernel(int ps, int pt, int R, int kp, const int32_t* __restr
 // pair, count <= 128) and each block of 128 operator rows:
 //   stage[pair][row] = sum_col U[slot][row][col] * mom[src(pair)][col],   rows = G*P.
 // The moments of the tile's source cells are gathered into LDS, so each block
-// of U is read once per column tile (most offsets fit one tile).  Four waves
-// each own 32 rows x 128 columns as 2 x 8 blocks of 16 x 16 MFMA accumulators;
-// K advances in steps of 16.  FP64 uses
-// v_mfma_f64_16x16x4 (D row = 4 r + lane/16), FP32 v_mfma_f32_16x16x4
-// (D row = 4 (lane/16) + r); in both, A[i][k] sits in lane i + 16 k and
-// B[k][j] in lane j + 16 k.  The operators are stored in that fragment order,
-// so each wave streams its A fragments from memory with fully coalesced
-// 64-lane loads (one K step ahead); the gathered moments go through LDS.
+// of U is read once per column tile.  Four waves each own 32 rows x (16 NCB)
+// columns as 2 x NCB blocks of 16 x 16 MFMA accumulators; K advances in steps
+// of KS.  FP64 uses v_mfma_f64_16x16x4 (D row = 4 r + lane/16), FP32
+// v_mfma_f32_16x16x4 (D row = 4 (lane/16) + r); in both, A[i][k] sits in lane
+// i + 16 k and B[k][j] in lane j + 16 k.  The operators are stored in that
+// fragment order with consecutive k blocks interleaved per lane, so each wave
+// streams its A fragments straight into registers with 16-byte loads, one
+// (FP64) or two (FP32) K steps ahead; the gathered moments go through LDS.
 constexpr int MB_M = 128;        // operator rows per workgroup (4 waves x 32)
 constexpr int MB_NMAX = 128;     // widest column tile
 
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+
+// k blocks of 4 operator columns, padded to a multiple of 4 so that a lane's
+// consecutive k blocks form one 16-byte load (4 FP32 or 2 FP64 values).
+static inline int m2l_kblocks(int P) { return ((P + 3) / 4 + 3) / 4 * 4; }
+template <class T> struct Vec16;
+template <> struct Vec16<float> { typedef flt4_t type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef dbl2_t type; static constexpr int n = 2; };
 
 template <class T> struct Mfma;
 // kTransposed: the product is formed as (moments^T U^T) so that the output tile's
@@ -394,19 +402,22 @@ template <> struct Mfma<float> {
   static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// Operators in MFMA fragment order: Uf[slot][rb][kb][lane] = U[16 rb + lane%16][4 kb + lane/16],
-// rows padded to RB = ceil(GP/16) blocks and columns to KB = ceil(P/4) blocks (zeros), so one
-// A fragment is 64 consecutive values.
+// Operators in MFMA fragment order, V = 16 / sizeof(T) k blocks interleaved per lane:
+// Uf[slot][rb][kb / V][lane][kb % V] = U[16 rb + lane%16][4 kb + lane/16], rows padded to
+// RB = ceil(GP/16) blocks and columns to KB = m2l_kblocks(P) blocks (zeros).  A lane's A
+// fragments of V consecutive k blocks are then one 16-byte load, and a wave's load is
+// 1 KB of contiguous memory.
 template <class T>
 __global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double* __restrict__ U,
                                     T* __restrict__ Uf) {
+  constexpr int V = Vec16<T>::n;
   const int slot = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)RB * KB * 64;
   if (idx >= per) return;
-  const int lane = (int)(idx & 63);
-  const int64_t blk = idx >> 6;
-  const int kb = (int)(blk % KB), rb = (int)(blk / KB);
+  const int e = (int)(idx % V), lane = (int)((idx / V) & 63);
+  const int64_t blk = idx / (64 * V);
+  const int kb = (int)(blk % (KB / V)) * V + e, rb = (int)(blk / (KB / V));
   const int row = rb * 16 + (lane & 15), col = kb * 4 + (lane >> 4);
   const double v = (row < GP && col < P) ? U[((int64_t)slot * GP + row) * P + col] : 0.0;
   Uf[(int64_t)slot * per + idx] = (T)v;
@@ -476,9 +487,14 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   }
   __syncthreads();
   const int64_t per = (int64_t)RB * KB * 64;
-  const T* A0 = Uf + (int64_t)slot * per + ((int64_t)rb0 * KB) * 64 + lane;   // row block rb0
-  const T* A1 = A0 + (int64_t)KB * 64;                                         // row block rb0+1
-  const bool rlive0 = rb0 < RB, rlive1 = rb0 + 1 < RB;
+  // Row blocks past the operator's end (rb >= RB) read the last block again:
+  // their products are never stored.  k blocks past KB likewise read the last
+  // block and meet zero moments, so every load below is unconditional.
+  typedef typename Vec16<T>::type vec_t;
+  constexpr int V = Vec16<T>::n;
+  static_assert(QS % V == 0, "a K step spans whole 16-byte groups");
+  const vec_t* A0 = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0, RB - 1) * KB) * 64) + lane;
+  const vec_t* A1 = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0 + 1, RB - 1) * KB) * 64) + lane;
   const int ncb = (cnt + 15) >> 4;                                             // live column blocks
   acc_t acc[2][NCB];
 #pragma unroll
@@ -488,51 +504,93 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   const int bc = tid / TPC, bk = (tid % TPC) * BPT;
   const int bsrc = src[bc];
   const double* mrow = mom + (int64_t)(bsrc >= 0 ? bsrc : 0) * P;
-  // one K step ahead in registers: A fragments (QS k-blocks x 2 row blocks) and
-  // this thread's BPT moment values of the B tile
-  T fa[2][QS], fb[BPT];
-  auto load = [&](int k0) {
-    const int kb0 = k0 >> 2;
+  // DEPTH K steps ahead in registers (DEPTH sets, used in turn): A fragments
+  // (QS k-blocks x 2 row blocks) and this thread's BPT raw moment values of the
+  // B tile.  The moments are masked and converted only when they are written
+  // to LDS one step before their use, so with DEPTH = 2 the loads of the two
+  // following steps stay in flight across each step's products.  (FP64 keeps
+  // DEPTH = 1: the second set costs it occupancy.)
+  // DEPTH + 1 register sets rotate so that no set is copied: step s reads set
+  // s % NSET while the loads of step s + DEPTH fill set (s + DEPTH) % NSET.
+  constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+  constexpr int NSET = DEPTH + 1;
+  T fa[NSET][2][QS];
+  double fb[NSET][BPT];
+  auto load = [&](int set, int k0) {
+    const int g0 = (k0 >> 2) / V;
 #pragma unroll
-    for (int q = 0; q < QS; ++q) {
-      const int kb = kb0 + q;
-      fa[0][q] = (rlive0 && kb < KB) ? A0[(int64_t)kb * 64] : T(0);
-      fa[1][q] = (rlive1 && kb < KB) ? A1[(int64_t)kb * 64] : T(0);
+    for (int g = 0; g < QS / V; ++g) {
+      const int kg = min(g0 + g, KB / V - 1);
+      const vec_t a0 = A0[(int64_t)kg * 64], a1 = A1[(int64_t)kg * 64];
+#pragma unroll
+      for (int e = 0; e < V; ++e) { fa[set][0][g * V + e] = a0[e]; fa[set][1][g * V + e] = a1[e]; }
     }
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int k = k0 + bk + i;
-      fb[i] = (bsrc >= 0 && k < P) ? (T)mrow[k] : T(0);
-    }
+    for (int i = 0; i < BPT; ++i) fb[set][i] = mrow[min(k0 + bk + i, P - 1)];
   };
-  load(0);
-  int buf = 0;
-  for (int k0 = 0; k0 < P; k0 += KS) {
+  auto stage_b = [&](int set, int k0, int b) {
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) Bs[buf][bk + i][bc] = fb[i];
-    __syncthreads();   // tile k0 complete; every wave is done with the buffer written two steps ago
-    T ca[2][QS];
+    for (int i = 0; i < BPT; ++i)
+      Bs[b][bk + i][bc] = (bsrc >= 0 && k0 + bk + i < P) ? (T)fb[set][i] : T(0);
+  };
+  // the products of one K step; full: every column block of the tile is live
+  auto products = [&](auto full, const T (&ca)[2][QS], int b) {
+    T bf[QS][NCB];
 #pragma unroll
-    for (int q = 0; q < QS; ++q) { ca[0][q] = fa[0][q]; ca[1][q] = fa[1][q]; }
-    if (k0 + KS < P) load(k0 + KS);
+    for (int q = 0; q < QS; ++q)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) bf[q][cb] = Bs[b][4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        if (cb < ncb) {
-          const T bf = Bs[buf][4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
+        if (decltype(full)::value || cb < ncb) {
           if constexpr (Mfma<T>::kTransposed) {
             // A = moment tile (pair cb*16 + lane%16, k 4q + lane/16), B = operator fragment
-            acc[0][cb] = Mfma<T>::op(bf, ca[0][q], acc[0][cb]);
-            acc[1][cb] = Mfma<T>::op(bf, ca[1][q], acc[1][cb]);
+            acc[0][cb] = Mfma<T>::op(bf[q][cb], ca[0][q], acc[0][cb]);
+            acc[1][cb] = Mfma<T>::op(bf[q][cb], ca[1][q], acc[1][cb]);
           } else {
-            acc[0][cb] = Mfma<T>::op(ca[0][q], bf, acc[0][cb]);
-            acc[1][cb] = Mfma<T>::op(ca[1][q], bf, acc[1][cb]);
+            acc[0][cb] = Mfma<T>::op(ca[0][q], bf[q][cb], acc[0][cb]);
+            acc[1][cb] = Mfma<T>::op(ca[1][q], bf[q][cb], acc[1][cb]);
           }
         }
       }
     }
+  };
+#pragma unroll
+  for (int h = 0; h < DEPTH; ++h) load(h, h * KS);  // in bounds past P too (clamped)
+  stage_b(0, 0, 0);
+  __syncthreads();
+  int buf = 0;
+  const int nsteps = (P + KS - 1) / KS;
+  // K step s, whose fragments are in set h = s % NSET.  steady: the loads
+  // DEPTH steps ahead and the LDS tile of the next step both exist, so neither
+  // is behind a branch and the memory counters wait only for what the step needs.
+  auto step = [&](auto hc, int s, auto steady) {
+    constexpr int h = decltype(hc)::value;
+    constexpr bool st = decltype(steady)::value;
+    if (st || s + DEPTH < nsteps) load((h + DEPTH) % NSET, (s + DEPTH) * KS);
+    if (sizeof(T) == 4 && ncb == NCB) products(std::true_type{}, fa[h], buf);
+    else products(std::false_type{}, fa[h], buf);
+    // the other LDS buffer was last read in the previous step, before its barrier
+    if (st || s + 1 < nsteps) stage_b((h + 1) % NSET, (s + 1) * KS, buf ^ 1);
+    __syncthreads();
     buf ^= 1;
+  };
+  typedef std::integral_constant<int, 0> set0;
+  typedef std::integral_constant<int, 1> set1;
+  typedef std::integral_constant<int, 2 % NSET> set2;
+  int s = 0;
+  for (; s + NSET - 1 + DEPTH < nsteps; s += NSET) {
+    step(set0{}, s, std::true_type{});
+    step(set1{}, s + 1, std::true_type{});
+    if constexpr (NSET == 3) step(set2{}, s + 2, std::true_type{});
+  }
+  for (; s < nsteps; ++s) {
+    const int j = s % NSET;
+    if (j == 0) step(set0{}, s, std::false_type{});
+    else if (j == 1) step(set1{}, s, std::false_type{});
+    else step(set2{}, s, std::false_type{});
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -581,7 +639,7 @@ static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int 
   switch (v) {
     case 0: m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     case 1:  // the FP64 tile would need 68 KB of LDS: FP64 uses the K=16 kernel here
-      if (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
+      if constexpr (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
       else m2l_mfma_kernel<T, 8, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
       break;
     case 2: m2l_mfma_kernel<T, 4, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
@@ -883,7 +941,7 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
 static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   const int P = f->P, G = f->G;
   const int v = choice >> 1, persistent = choice & 1;
-  const int RB = (G * P + 15) / 16, KB = (P + 3) / 4, nrb = (G * P + MB_M - 1) / MB_M;
+  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + MB_M - 1) / MB_M;
   const int cols = kVariantCols[v];
   M2LWork W{};
   int total = 0;
@@ -1107,7 +1165,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
       {
-        const int RB = (G * P + 15) / 16, KB = (P + 3) / 4;
+        const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
         const int64_t per = (int64_t)RB * KB * 64;
         dim3 gf((unsigned)((per + 255) / 256), std::max(nslot, 1));
         if (f->f32) {
