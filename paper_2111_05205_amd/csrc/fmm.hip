@@ -54,9 +54,10 @@ struct FmmLevel {
   std::vector<int> il_src, il_slot;         // npair
   std::vector<std::array<int, 3>> slot_off; // offset vector of each matrix slot present at this level
   // device
-  DevBuf<int32_t> d_il_ptr, d_il_src, d_parent, d_octant, d_child_ptr, d_child;
+  DevBuf<int32_t> d_il_ptr, d_parent, d_octant, d_child_ptr, d_child;
   DevBuf<int32_t> d_tiles128, d_tiles64, d_tiles32;  // GEMM column tiles (slot, first, count) by width
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
+  DevBuf<int32_t> d_src_by_slot;            // their source cells (so the two loads are independent)
   int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
   DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
   DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
@@ -368,7 +369,7 @@ __global__ void l2l_kernel(int ps, int pt, int R, int kp, const int32_t* __restr
 // fragment order with consecutive k blocks interleaved per lane, so each wave
 // streams its A fragments straight into registers with 16-byte loads, one
 // (FP64) or two (FP32) K steps ahead; the gathered moments go through LDS.
-constexpr int MB_M = 128;        // operator rows per workgroup (4 waves x 32)
+// A workgroup covers 64 RPW operator rows (4 waves x RPW row blocks of 16).
 constexpr int MB_NMAX = 128;     // widest column tile
 
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
@@ -430,7 +431,7 @@ constexpr int M2L_MAXLEV = 12;
 struct M2LLevelWork {
   const int32_t* tiles;          // (slot, first pair, count) per tile
   const int32_t* pairs_by_slot;
-  const int32_t* il_src;
+  const int32_t* src_by_slot;
   const void* Uf;                // T operators in fragment order
   const double* mom;
   void* stage;                   // T per-pair products
@@ -443,7 +444,7 @@ struct M2LWork {
   int total;                     // work items over all levels
 };
 
-template <class T, int NCB, int KS, bool PERS>
+template <class T, int NCB, int KS, int RPW, bool PERS>
 __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, int KB, M2LWork W) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int BN = NCB * 16;              // columns (interaction pairs) per tile
@@ -473,17 +474,17 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
   const int32_t* __restrict__ tiles = Lw.tiles;
   const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
-  const int32_t* __restrict__ il_src = Lw.il_src;
+  const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
   const T* __restrict__ Uf = static_cast<const T*>(Lw.Uf);
   const double* __restrict__ mom = Lw.mom;
   T* __restrict__ stage = static_cast<T*>(Lw.stage);
   const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
   if constexpr (PERS) __syncthreads();  // the previous item's readers of src / pid / Bs are done
-  const int rb0 = rowblk * (MB_M / 16) + wave * 2;       // this wave: row blocks rb0, rb0+1 (32 rows)
+  const int rb0 = (rowblk * 4 + wave) * RPW;             // this wave: row blocks rb0 .. rb0+RPW-1
   if (tid < BN) {
     const int p = tid < cnt ? pairs_by_slot[first + tid] : -1;
     pid[tid] = p;
-    src[tid] = p >= 0 ? il_src[p] : -1;
+    src[tid] = tid < cnt ? src_by_slot[first + tid] : -1;
   }
   __syncthreads();
   const int64_t per = (int64_t)RB * KB * 64;
@@ -493,12 +494,14 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   typedef typename Vec16<T>::type vec_t;
   constexpr int V = Vec16<T>::n;
   static_assert(QS % V == 0, "a K step spans whole 16-byte groups");
-  const vec_t* A0 = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0, RB - 1) * KB) * 64) + lane;
-  const vec_t* A1 = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0 + 1, RB - 1) * KB) * 64) + lane;
-  const int ncb = (cnt + 15) >> 4;                                             // live column blocks
-  acc_t acc[2][NCB];
+  const vec_t* Ar[RPW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int r = 0; r < RPW; ++r)
+    Ar[r] = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0 + r, RB - 1) * KB) * 64) + lane;
+  const int ncb = (cnt + 15) >> 4;                                             // live column blocks
+  acc_t acc[RPW][NCB];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
 #pragma unroll
     for (int j = 0; j < NCB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
   const int bc = tid / TPC, bk = (tid % TPC) * BPT;
@@ -514,16 +517,19 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   // s % NSET while the loads of step s + DEPTH fill set (s + DEPTH) % NSET.
   constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
   constexpr int NSET = DEPTH + 1;
-  T fa[NSET][2][QS];
+  T fa[NSET][RPW][QS];
   double fb[NSET][BPT];
   auto load = [&](int set, int k0) {
     const int g0 = (k0 >> 2) / V;
 #pragma unroll
     for (int g = 0; g < QS / V; ++g) {
       const int kg = min(g0 + g, KB / V - 1);
-      const vec_t a0 = A0[(int64_t)kg * 64], a1 = A1[(int64_t)kg * 64];
 #pragma unroll
-      for (int e = 0; e < V; ++e) { fa[set][0][g * V + e] = a0[e]; fa[set][1][g * V + e] = a1[e]; }
+      for (int r = 0; r < RPW; ++r) {
+        const vec_t a = Ar[r][(int64_t)kg * 64];
+#pragma unroll
+        for (int e = 0; e < V; ++e) fa[set][r][g * V + e] = a[e];
+      }
     }
 #pragma unroll
     for (int i = 0; i < BPT; ++i) fb[set][i] = mrow[min(k0 + bk + i, P - 1)];
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
       Bs[b][bk + i][bc] = (bsrc >= 0 && k0 + bk + i < P) ? (T)fb[set][i] : T(0);
   };
   // the products of one K step; full: every column block of the tile is live
-  auto products = [&](auto full, const T (&ca)[2][QS], int b) {
+  auto products = [&](auto full, const T (&ca)[RPW][QS], int b) {
     T bf[QS][NCB];
 #pragma unroll
     for (int q = 0; q < QS; ++q)
@@ -545,13 +551,12 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         if (decltype(full)::value || cb < ncb) {
-          if constexpr (Mfma<T>::kTransposed) {
-            // A = moment tile (pair cb*16 + lane%16, k 4q + lane/16), B = operator fragment
-            acc[0][cb] = Mfma<T>::op(bf[q][cb], ca[0][q], acc[0][cb]);
-            acc[1][cb] = Mfma<T>::op(bf[q][cb], ca[1][q], acc[1][cb]);
-          } else {
-            acc[0][cb] = Mfma<T>::op(ca[0][q], bf[q][cb], acc[0][cb]);
-            acc[1][cb] = Mfma<T>::op(ca[1][q], bf[q][cb], acc[1][cb]);
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            if constexpr (Mfma<T>::kTransposed)  // A = moment tile (pair cb*16 + lane%16, k 4q + lane/16)
+              acc[r][cb] = Mfma<T>::op(bf[q][cb], ca[r][q], acc[r][cb]);
+            else
+              acc[r][cb] = Mfma<T>::op(ca[r][q], bf[q][cb], acc[r][cb]);
           }
         }
       }
@@ -593,7 +598,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
     else step(set2{}, s, std::false_type{});
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < RPW; ++h)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       if (cb >= ncb) continue;
@@ -628,24 +633,28 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   } while (w < total);
 }
 
-// Tile variants of the M2L products: (columns per tile, K step).  The variant
-// and whether the launch is persistent are chosen by timing (autotuning).
-constexpr int M2L_VARIANTS = 6;
-static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64, 32, 32};
-static const int kVariantKs[M2L_VARIANTS] = {16, 32, 16, 32, 16, 32};
+// Tile variants of the M2L products: (columns per tile, K step, row blocks per
+// wave).  The variant and whether the launch is persistent are chosen by
+// timing (autotuning).
+constexpr int M2L_VARIANTS = 9;
+static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64, 32, 32, 32, 64, 32};
+static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 2, 4, 4, 4};
 
 template <class T, bool PERS>
 static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
   switch (v) {
-    case 0: m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 0: m2l_mfma_kernel<T, 8, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     case 1:  // the FP64 tile would need 68 KB of LDS: FP64 uses the K=16 kernel here
-      if constexpr (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
-      else m2l_mfma_kernel<T, 8, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
+      if constexpr (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
+      else m2l_mfma_kernel<T, 8, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
       break;
-    case 2: m2l_mfma_kernel<T, 4, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 3: m2l_mfma_kernel<T, 4, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 4: m2l_mfma_kernel<T, 2, 16, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    default: m2l_mfma_kernel<T, 2, 32, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 2: m2l_mfma_kernel<T, 4, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 3: m2l_mfma_kernel<T, 4, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 4: m2l_mfma_kernel<T, 2, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 5: m2l_mfma_kernel<T, 2, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 6: m2l_mfma_kernel<T, 2, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 7: m2l_mfma_kernel<T, 4, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    default: m2l_mfma_kernel<T, 2, 32, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
   }
 }
 
@@ -941,7 +950,8 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
 static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   const int P = f->P, G = f->G;
   const int v = choice >> 1, persistent = choice & 1;
-  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + MB_M - 1) / MB_M;
+  const int rows = 64 * kVariantRpw[v];
+  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + rows - 1) / rows;
   const int cols = kVariantCols[v];
   M2LWork W{};
   int total = 0;
@@ -952,7 +962,7 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     Lw.ntiles = cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32;
     Lw.tiles = cols == 128 ? L.d_tiles128.p : cols == 64 ? L.d_tiles64.p : L.d_tiles32.p;
     Lw.pairs_by_slot = L.d_pairs_by_slot.p;
-    Lw.il_src = L.d_il_src.p;
+    Lw.src_by_slot = L.d_src_by_slot.p;
     Lw.mom = L.d_mom.p;
     if (f->f32) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
     else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
@@ -980,8 +990,9 @@ struct M2LKey {
 static std::mutex g_tune_mu;
 static std::map<M2LKey, int> g_tune_table;
 
-static int m2l_work_items(const Fmm* f, int n, int cols) {
-  const int nrb = (f->G * f->P + MB_M - 1) / MB_M;
+static int m2l_work_items(const Fmm* f, int n, int v) {
+  const int cols = kVariantCols[v], rows = 64 * kVariantRpw[v];
+  const int nrb = (f->G * f->P + rows - 1) / rows;
   int total = 0;
   for (int l = f->D; l > f->D - n && l >= 2; --l) {
     const FmmLevel& L = f->lev[l];
@@ -993,7 +1004,7 @@ static int m2l_work_items(const Fmm* f, int n, int cols) {
 static void autotune_m2l(Fmm* f, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   for (int n = 1; n <= f->D - 1; ++n) {
-    const int items = m2l_work_items(f, n, 64);
+    const int items = m2l_work_items(f, n, 2);
     int bucket = 0;
     while ((1 << bucket) < items) ++bucket;
     const M2LKey key{f->P, f->G, f->f32 ? 1 : 0, n, bucket};
@@ -1009,7 +1020,7 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
     float best = 1e30f;
     int bestc = 4;
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
-      if ((c & 1) && m2l_work_items(f, n, kVariantCols[c >> 1]) <= f->persistent_grid) continue;
+      if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
       launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
       for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
@@ -1121,9 +1132,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     }
     for (int l = 2; l <= f->D; ++l) {
       FmmLevel& L = f->lev[l];
-      std::vector<int32_t> ilp(L.il_ptr.begin(), L.il_ptr.end()), ils(L.il_src.begin(), L.il_src.end());
+      std::vector<int32_t> ilp(L.il_ptr.begin(), L.il_ptr.end());
       upload(L.d_il_ptr, ilp, st);
-      upload(L.d_il_src, ils, st);
       const int nslot = (int)L.slot_off.size();
       std::vector<std::vector<int32_t>> by(nslot);
       for (int64_t p = 0; p < L.npair; ++p) by[L.il_slot[p]].push_back((int32_t)p);
@@ -1147,6 +1157,9 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       upload(L.d_tiles64, tiles64, st);
       upload(L.d_tiles32, tiles32, st);
       upload(L.d_pairs_by_slot, flat, st);
+      std::vector<int32_t> flat_src(flat.size());
+      for (size_t i = 0; i < flat.size(); ++i) flat_src[i] = L.il_src[flat[i]];
+      upload(L.d_src_by_slot, flat_src, st);
       std::vector<int32_t> so;
       for (auto& v : L.slot_off) { so.push_back(v[0]); so.push_back(v[1]); so.push_back(v[2]); }
       DevBuf<int32_t> d_so;
