@@ -122,8 +122,8 @@ typedef struct {
   double setup_ms;
   int m2l_variant[16];  /* [n], n = 1..depth-1: autotuned M2L launch for the n finest levels ending an interval
                            together, 2 * tile + persistent; tile (columns x K step x operator rows per
-                           workgroup) 0 128x16x128, 1 128x32x128, 2 64x16x128, 3 64x32x128, 4 32x16x128,
-                           5 32x32x128, 6 32x16x256, 7 64x16x256, 8 32x32x256 */
+                           workgroup) 0 128x16x128, 1 64x16x128, 2 64x32x128, 3 32x16x128, 4 32x32x128,
+                           5 32x16x256, 6 64x16x256, 7 32x32x256 */
   int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
 } tdbem_info;
 

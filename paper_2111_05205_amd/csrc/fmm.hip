@@ -444,8 +444,16 @@ struct M2LWork {
   int total;                     // work items over all levels
 };
 
+// Waves per SIMD that the register allocation aims at for FP32 (without a
+// target the compiler parks values in the accumulation registers and lands a
+// wave short; FP64 and the widest tiles would spill, so they keep 1).
 template <class T, int NCB, int KS, int RPW, bool PERS>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, int KB, M2LWork W) {
+constexpr int m2l_waves() {
+  return sizeof(T) == 8 || NCB == 8 ? 1 : PERS ? (NCB == 2 ? 2 : 1) : (NCB == 2 && KS == 16) ? 3 : 2;
+}
+
+template <class T, int NCB, int KS, int RPW, bool PERS>
+__global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l_mfma_kernel(int P, int GP, int RB, int KB, M2LWork W) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int BN = NCB * 16;              // columns (interaction pairs) per tile
   constexpr int LD = BN + 4;                // LDS row stride of the moment tile
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
   // DEPTH = 1: the second set costs it occupancy.)
   // DEPTH + 1 register sets rotate so that no set is copied: step s reads set
   // s % NSET while the loads of step s + DEPTH fill set (s + DEPTH) % NSET.
-  constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+  constexpr int DEPTH = (sizeof(T) == 4 && RPW == 2) ? 2 : 1;
   constexpr int NSET = DEPTH + 1;
   T fa[NSET][RPW][QS];
   double fb[NSET][BPT];
@@ -636,24 +644,20 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int P, int GP, int RB, in
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
 // wave).  The variant and whether the launch is persistent are chosen by
 // timing (autotuning).
-constexpr int M2L_VARIANTS = 9;
-static const int kVariantCols[M2L_VARIANTS] = {128, 128, 64, 64, 32, 32, 32, 64, 32};
-static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 2, 4, 4, 4};
+constexpr int M2L_VARIANTS = 8;
+static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32};
+static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4};
 
 template <class T, bool PERS>
 static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
   switch (v) {
     case 0: m2l_mfma_kernel<T, 8, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 1:  // the FP64 tile would need 68 KB of LDS: FP64 uses the K=16 kernel here
-      if constexpr (sizeof(T) == 8) m2l_mfma_kernel<T, 8, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
-      else m2l_mfma_kernel<T, 8, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W);
-      break;
-    case 2: m2l_mfma_kernel<T, 4, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 3: m2l_mfma_kernel<T, 4, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 4: m2l_mfma_kernel<T, 2, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 5: m2l_mfma_kernel<T, 2, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 6: m2l_mfma_kernel<T, 2, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 7: m2l_mfma_kernel<T, 4, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 1: m2l_mfma_kernel<T, 4, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 2: m2l_mfma_kernel<T, 4, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 3: m2l_mfma_kernel<T, 2, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 4: m2l_mfma_kernel<T, 2, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 5: m2l_mfma_kernel<T, 2, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 6: m2l_mfma_kernel<T, 4, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     default: m2l_mfma_kernel<T, 2, 32, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
   }
 }
@@ -1004,7 +1008,7 @@ static int m2l_work_items(const Fmm* f, int n, int v) {
 static void autotune_m2l(Fmm* f, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   for (int n = 1; n <= f->D - 1; ++n) {
-    const int items = m2l_work_items(f, n, 2);
+    const int items = m2l_work_items(f, n, 1);
     int bucket = 0;
     while ((1 << bucket) < items) ++bucket;
     const M2LKey key{f->P, f->G, f->f32 ? 1 : 0, n, bucket};
@@ -1018,7 +1022,7 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
       TDBEM_HIP(hipEventCreate(&e1));
     }
     float best = 1e30f;
-    int bestc = 4;
+    int bestc = 2;  // 64 x 16 x 128, one item per workgroup
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
       if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
       launch_m2l_levels(f, n, c, st);  // warm-up
