@@ -7,7 +7,9 @@
 // (L2-resident for the sizes this kernel serves), the Hessenberg matrix,
 // Givens rotations and reduction scratch in LDS, and no host round trip is
 // needed.  Orthogonalisation is classical Gram-Schmidt applied twice (CGS2),
-// so each Arnoldi step needs two fused multi-dot reductions.
+// so each Arnoldi step needs two fused multi-dot reductions.  The products
+// A v read a copy of A padded to the longest row and stored column-major, so
+// the loads of a row are independent and consecutive rows are adjacent.
 //
 // Larger systems use the cooperative variant: NW workgroups of 256 threads,
 // guaranteed co-resident by a cooperative launch, each owning a contiguous
@@ -82,18 +84,35 @@ __device__ inline void multi_dot(int ns, int j, const double* __restrict__ V, co
   __syncthreads();
 }
 
-__device__ inline void spmv(int ns, const int32_t* __restrict__ ap, const int32_t* __restrict__ ac,
-                            const double* __restrict__ av, const double* __restrict__ v, double* __restrict__ y) {
-  for (int i = threadIdx.x; i < ns; i += GM_THREADS) {
-    double s = 0.0;
-    for (int k = ap[i]; k < ap[i + 1]; ++k) s += av[k] * v[ac[k]];
-    y[i] = s;
+// Row i of A v with A padded to W entries per row, column-major ([k][row]):
+// consecutive rows are consecutive addresses, and the loads of four entries
+// are issued together before their products.
+__device__ inline double ell_row(int i, int ns, int W, const int32_t* __restrict__ ec,
+                                 const double* __restrict__ ev, const double* __restrict__ v) {
+  double s0 = 0.0, s1 = 0.0;
+  int k = 0;
+  for (; k + 3 < W; k += 4) {
+    const int64_t o = (int64_t)k * ns + i;
+    const int c0 = ec[o], c1 = ec[o + ns], c2 = ec[o + 2 * ns], c3 = ec[o + 3 * ns];
+    const double a0 = ev[o], a1 = ev[o + ns], a2 = ev[o + 2 * ns], a3 = ev[o + 3 * ns];
+    const double v0 = v[c0], v1 = v[c1], v2 = v[c2], v3 = v[c3];
+    s0 += a0 * v0 + a2 * v2;
+    s1 += a1 * v1 + a3 * v3;
   }
+  for (; k < W; ++k) {
+    const int64_t o = (int64_t)k * ns + i;
+    s0 += ev[o] * v[ec[o]];
+  }
+  return s0 + s1;
 }
 
-__global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t* __restrict__ ap,
-                                                            const int32_t* __restrict__ ac,
-                                                            const double* __restrict__ av,
+__device__ inline void spmv(int ns, int W, const int32_t* __restrict__ ec, const double* __restrict__ ev,
+                            const double* __restrict__ v, double* __restrict__ y) {
+  for (int i = threadIdx.x; i < ns; i += GM_THREADS) y[i] = ell_row(i, ns, W, ec, ev, v);
+}
+
+__global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, int W, const int32_t* __restrict__ ec,
+                                                            const double* __restrict__ ev,
                                                             const double* __restrict__ b, double* __restrict__ x,
                                                             double* __restrict__ V, int m, int maxit, double tol,
                                                             StepStat* __restrict__ stat,
@@ -114,7 +133,7 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
     for (;;) {
       // r = b - A x  -> V_0
       double* V0 = V;
-      spmv(ns, ap, ac, av, x, V0);
+      spmv(ns, W, ec, ev, x, V0);
       double rr = 0.0;
       for (int i = tid; i < ns; i += GM_THREADS) {
         const double r = b[i] - V0[i];
@@ -125,7 +144,7 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
       if (it == 0 && xalt) {
         // a second candidate starting point: keep whichever has the smaller residual
         double* V1 = V + ns;
-        spmv(ns, ap, ac, av, xalt, V1);
+        spmv(ns, W, ec, ev, xalt, V1);
         double ra = 0.0;
         for (int i = tid; i < ns; i += GM_THREADS) {
           const double r = b[i] - V1[i];
@@ -167,24 +186,24 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, const int32_t
       int jlast = -1;
       for (int j = 0; j < m; ++j) {
         double* Vj = V + (size_t)j * ns;
-        double* W = V + (size_t)(j + 1) * ns;
-        spmv(ns, ap, ac, av, Vj, W);
+        double* Wv = V + (size_t)(j + 1) * ns;
+        spmv(ns, W, ec, ev, Vj, Wv);
         __syncthreads();
         for (int pass = 0; pass < 2; ++pass) {
-          multi_dot(ns, j, V, W, sh);
+          multi_dot(ns, j, V, Wv, sh);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
           for (int i = tid; i < ns; i += GM_THREADS) {
-            double wi = W[i];
+            double wi = Wv[i];
             for (int k = 0; k <= j; ++k) wi -= sh.hv[k] * V[(size_t)k * ns + i];
-            W[i] = wi;
+            Wv[i] = wi;
           }
           __syncthreads();
         }
         double ww = 0.0;
-        for (int i = tid; i < ns; i += GM_THREADS) ww += W[i] * W[i];
+        for (int i = tid; i < ns; i += GM_THREADS) ww += Wv[i] * Wv[i];
         const double hn = sqrt(block_sum(ww, sh));
         if (hn > 0.0)
-          for (int i = tid; i < ns; i += GM_THREADS) W[i] /= hn;
+          for (int i = tid; i < ns; i += GM_THREADS) Wv[i] /= hn;
         if (tid == 0) {
           sh.H[j + 1][j] = hn;
           for (int k = 0; k < j; ++k) {  // previous rotations
@@ -283,7 +302,7 @@ __device__ inline void grid_multi_sum(int n, const double* part, double* __restr
 }
 
 __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
-    int ns, const int32_t* __restrict__ ap, const int32_t* __restrict__ ac, const double* __restrict__ av,
+    int ns, int W, const int32_t* __restrict__ ec, const double* __restrict__ ev,
     const double* __restrict__ b, double* __restrict__ x, double* __restrict__ V, int m, int maxit, double tol,
     StepStat* __restrict__ stat, double* __restrict__ gpart, const double* __restrict__ xalt) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
@@ -308,9 +327,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
       double* V0 = V;
       part[0] = 0.0;
       for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-        double s = 0.0;
-        for (int k = ap[i]; k < ap[i + 1]; ++k) s += av[k] * x[ac[k]];
-        const double r = b[i] - s;
+        const double r = b[i] - ell_row(i, ns, W, ec, ev, x);
         V0[i] = r;
         part[0] += r * r;
       }
@@ -322,9 +339,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
         double* V1 = V + ns;
         part[0] = 0.0;
         for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-          double sa = 0.0;
-          for (int k = ap[i]; k < ap[i + 1]; ++k) sa += av[k] * xalt[ac[k]];
-          const double r = b[i] - sa;
+          const double r = b[i] - ell_row(i, ns, W, ec, ev, xalt);
           V1[i] = r;
           part[0] += r * r;
         }
@@ -364,17 +379,13 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
       int jlast = -1;
       for (int j = 0; j < m; ++j) {
         const double* Vj = V + (size_t)j * ns;
-        double* W = V + (size_t)(j + 1) * ns;
-        for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-          double s = 0.0;
-          for (int k = ap[i]; k < ap[i + 1]; ++k) s += av[k] * Vj[ac[k]];
-          W[i] = s;
-        }
+        double* Wv = V + (size_t)(j + 1) * ns;
+        for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] = ell_row(i, ns, W, ec, ev, Vj);
         for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
           for (int k = 0; k < GM_MAXM + 1; ++k) part[k] = 0.0;
           for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-            const double wi = W[i];
+            const double wi = Wv[i];
 #pragma unroll
             for (int k = 0; k < GM_MAXM; ++k)
               if (k <= j) part[k] += V[(size_t)k * ns + i] * wi;
@@ -382,17 +393,17 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
           grid_multi_sum(j + 1, part, gpart, flip, sh, grid);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
           for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-            double wi = W[i];
+            double wi = Wv[i];
             for (int k = 0; k <= j; ++k) wi -= sh.hv[k] * V[(size_t)k * ns + i];
-            W[i] = wi;
+            Wv[i] = wi;
           }
         }
         part[0] = 0.0;
-        for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += W[i] * W[i];
+        for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += Wv[i] * Wv[i];
         grid_multi_sum(1, part, gpart, flip, sh, grid);
         const double hn = sqrt(sh.hv[0]);
         if (hn > 0.0)
-          for (int i = r0 + tid; i < r1; i += GC_THREADS) W[i] /= hn;
+          for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] /= hn;
         if (tid == 0) {
           sh.H[j + 1][j] = hn;
           for (int k = 0; k < j; ++k) {
@@ -455,7 +466,7 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, co
   // solver serves captured marches
   const int nwg = ctx->capturing ? 1 : ctx->gmres_wg;
   if (nwg <= 1) {
-    gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, b, x,
+    gmres_kernel<<<1, GM_THREADS, 0, ctx->stream>>>(ctx->ns, ctx->ell_w, ctx->d_ell_col.p, ctx->d_ell_val.p, b, x,
                                                      ctx->d_V.p, m, ctx->opts.gmres_maxiter, ctx->opts.gmres_tol,
                                                      stat, xalt);
     TDBEM_HIP(hipGetLastError());
@@ -463,12 +474,12 @@ void launch_gmres(tdbem_ctx* ctx, const double* b, double* x, StepStat* stat, co
   }
   int ns = ctx->ns, maxit = ctx->opts.gmres_maxiter;
   double tol = ctx->opts.gmres_tol;
-  const int32_t* ap = ctx->d_a_ptr.p;
-  const int32_t* ac = ctx->d_a_col.p;
-  const double* av = ctx->d_a_val.p;
+  int W = ctx->ell_w;
+  const int32_t* ec = ctx->d_ell_col.p;
+  const double* ev = ctx->d_ell_val.p;
   double* V = ctx->d_V.p;
   double* gp = ctx->d_gpart.p;
-  void* args[] = {&ns, &ap, &ac, &av, &b, &x, &V, &m, &maxit, &tol, &stat, &gp, &xalt};
+  void* args[] = {&ns, &W, &ec, &ev, &b, &x, &V, &m, &maxit, &tol, &stat, &gp, &xalt};
   TDBEM_HIP(hipLaunchCooperativeKernel((const void*)gmres_coop_kernel, dim3(nwg), dim3(GC_THREADS), args, 0,
                                        ctx->stream));
 }

@@ -100,6 +100,11 @@ struct tdbem_ctx {
   int64_t a_nnz = 0;
   tdbem::DevBuf<int32_t> d_a_ptr, d_a_col;
   tdbem::DevBuf<double> d_a_val, d_u1_val, d_w1_val;
+  // the per-step matrix again for the solver, padded to ell_w entries per row and
+  // stored column-major ([k][row]; padding: column = row, value = 0)
+  int ell_w = 0;
+  tdbem::DevBuf<int32_t> d_ell_col;
+  tdbem::DevBuf<double> d_ell_val;
 
   // history [beta][element], beta = 0..nt_max-2
   int nt_max = 0;

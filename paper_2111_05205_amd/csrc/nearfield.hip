@@ -13,6 +13,8 @@
 // A = w^{0,d} (W^{(1)} phi - U^{(1)} (1 - phi)) of eq. linear.
 #include "internal.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace tdbem {
@@ -186,6 +188,17 @@ __global__ void a_fill_kernel(int ns, int bc, const int64_t* __restrict__ row_pt
   }
 }
 
+__global__ void ell_fill_kernel(int ns, int W, const int32_t* __restrict__ ap, const int32_t* __restrict__ ac,
+                                const double* __restrict__ av, int32_t* __restrict__ ec, double* __restrict__ ev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int k0 = ap[i], n = ap[i + 1] - k0;
+  for (int k = 0; k < W; ++k) {
+    ec[(int64_t)k * ns + i] = k < n ? ac[k0 + k] : i;
+    ev[(int64_t)k * ns + i] = k < n ? av[k0 + k] : 0.0;
+  }
+}
+
 void build_step_matrix(tdbem_ctx* ctx) {
   const int ns = ctx->ns;
   DevBuf<int32_t> cnt;
@@ -208,6 +221,12 @@ void build_step_matrix(tdbem_ctx* ctx) {
   a_fill_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(
       ns, ctx->bc, ctx->d_row_ptr.p, ctx->d_pair_j.p, ctx->d_pair_gw.p, ctx->d_pair_off.p, ctx->d_cu.p, ctx->d_cw.p,
       ctx->d_a_ptr.p, ctx->d_a_col.p, ctx->d_a_val.p, ctx->d_u1_val.p, ctx->d_w1_val.p);
+  TDBEM_HIP(hipGetLastError());
+  ctx->ell_w = h.empty() ? 1 : std::max(1, *std::max_element(h.begin(), h.end()));
+  ctx->d_ell_col.alloc((size_t)ctx->ell_w * ns);
+  ctx->d_ell_val.alloc((size_t)ctx->ell_w * ns);
+  ell_fill_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(ns, ctx->ell_w, ctx->d_a_ptr.p, ctx->d_a_col.p,
+                                                             ctx->d_a_val.p, ctx->d_ell_col.p, ctx->d_ell_val.p);
   TDBEM_HIP(hipGetLastError());
   TDBEM_HIP(hipStreamSynchronize(ctx->stream));
 }
