@@ -14,9 +14,11 @@
 // Larger systems use the cooperative variant: NW workgroups of 256 threads,
 // guaranteed co-resident by a cooperative launch, each owning a contiguous
 // slice of rows.  Every reduction goes through per-workgroup partial sums in
-// global memory and a grid barrier; every workgroup then sums the partials in
-// the same order, so the Hessenberg matrix, Givens rotations and stopping
-// decision are bitwise identical in all workgroups (4 barriers per step).
+// global memory and a grid barrier (the barrier orders memory at device scope);
+// every workgroup then sums the partials in the same order, so the Hessenberg
+// matrix, Givens rotations and stopping decision are bitwise identical in all
+// workgroups.  The second orthogonalisation pass also carries |W|^2, so an
+// Arnoldi step takes 3 barriers.
 #include "internal.h"
 
 #include <hip/hip_cooperative_groups.h>
@@ -40,6 +42,43 @@ struct GmresShared {
 __device__ inline double wave_sum(double v) {
   for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
   return v;
+}
+
+// Cooperative-kernel helpers.  part[k] += V_k[i] w for k <= j, and
+// sum_{k <= j} coef[k] V_k[i]: basis rows are read CH at a time with the index
+// clamped to j, so every load is issued without a branch (and lands in rows
+// already written) and a thread's loads are in flight together.
+template <int CH>
+__device__ inline void dot_rows(int ns, int j, const double* __restrict__ V, int i, double w,
+                                double (&part)[GM_MAXM + 1]) {
+#pragma unroll
+  for (int c = 0; c < GM_MAXM / CH; ++c) {
+    if (CH * c <= j) {
+      double v[CH];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) v[kk] = V[(size_t)min(CH * c + kk, j) * ns + i];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk)
+        if (CH * c + kk <= j) part[CH * c + kk] += v[kk] * w;
+    }
+  }
+}
+
+template <int CH>
+__device__ inline double comb_rows(int ns, int j, const double* __restrict__ V, int i, const double* coef) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < GM_MAXM / CH; ++c) {
+    if (CH * c <= j) {
+      double v[CH];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) v[kk] = V[(size_t)min(CH * c + kk, j) * ns + i];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk)
+        if (CH * c + kk <= j) s += coef[CH * c + kk] * v[kk];
+    }
+  }
+  return s;
 }
 
 // Sum of one value over the block, result broadcast to every thread.
@@ -291,11 +330,19 @@ __device__ inline void grid_multi_sum(int n, const double* part, double* __restr
     for (int w = 0; w < GC_THREADS / 64; ++w) s += sh.red[w][threadIdx.x];
     gpart[blockIdx.x * (GM_MAXM + 1) + threadIdx.x] = s;
   }
-  __threadfence();
-  grid.sync();
+  grid.sync();  // orders memory at device scope: the partials are visible after it
   if (threadIdx.x < n) {
+    // every workgroup's partial loaded at once, then summed in workgroup order
+    const int G = (int)gridDim.x;
     double s = 0.0;
-    for (int w = 0; w < (int)gridDim.x; ++w) s += gpart[w * (GM_MAXM + 1) + threadIdx.x];
+    for (int w0 = 0; w0 < G; w0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = gpart[min(w0 + q, G - 1) * (GM_MAXM + 1) + threadIdx.x];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (w0 + q < G) s += v[q];
+    }
     sh.hv[threadIdx.x] = s;
   }
   __syncthreads();
@@ -374,34 +421,38 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
         sh.g[0] = beta;
         for (int k = 1; k <= m; ++k) sh.g[k] = 0.0;
       }
-      __threadfence();
       grid.sync();
       int jlast = -1;
       for (int j = 0; j < m; ++j) {
         const double* Vj = V + (size_t)j * ns;
         double* Wv = V + (size_t)(j + 1) * ns;
         for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] = ell_row(i, ns, W, ec, ev, Vj);
+        double ww = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
           for (int k = 0; k < GM_MAXM + 1; ++k) part[k] = 0.0;
           for (int i = r0 + tid; i < r1; i += GC_THREADS) {
             const double wi = Wv[i];
+            dot_rows<8>(ns, j, V, i, wi, part);
+            if (pass == 1) {
 #pragma unroll
-            for (int k = 0; k < GM_MAXM; ++k)
-              if (k <= j) part[k] += V[(size_t)k * ns + i] * wi;
+              for (int k = 1; k < GM_MAXM + 1; ++k)
+                if (k == j + 1) part[k] += wi * wi;
+            }
           }
-          grid_multi_sum(j + 1, part, gpart, flip, sh, grid);
+          // the second pass carries the squared norm of W as value j+1
+          grid_multi_sum(pass == 0 ? j + 1 : j + 2, part, gpart, flip, sh, grid);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
-          for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-            double wi = Wv[i];
-            for (int k = 0; k <= j; ++k) wi -= sh.hv[k] * V[(size_t)k * ns + i];
-            Wv[i] = wi;
+          if (pass == 1) {
+            // |W - sum h_k V_k|^2 = |W|^2 - sum h_k^2 for orthonormal V_k; after the
+            // first pass the h_k are at rounding level, so nothing cancels
+            double hh = 0.0;
+            for (int k = 0; k <= j; ++k) hh += sh.hv[k] * sh.hv[k];
+            ww = sh.hv[j + 1] - hh;
           }
+          for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] -= comb_rows<8>(ns, j, V, i, sh.hv);
         }
-        part[0] = 0.0;
-        for (int i = r0 + tid; i < r1; i += GC_THREADS) part[0] += Wv[i] * Wv[i];
-        grid_multi_sum(1, part, gpart, flip, sh, grid);
-        const double hn = sqrt(sh.hv[0]);
+        const double hn = ww >= 0.0 ? sqrt(ww) : (ww < 0.0 ? 0.0 : ww);  // NaN stays NaN
         if (hn > 0.0)
           for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] /= hn;
         if (tid == 0) {
@@ -421,7 +472,6 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
           sh.g[j + 1] = -sj * sh.g[j];
           sh.g[j] = cj * sh.g[j];
         }
-        __threadfence();
         grid.sync();  // W normalised everywhere; every workgroup's Givens state updated
         ++it;
         jlast = j;
@@ -436,12 +486,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
         }
       }
       __syncthreads();
-      for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-        double xi = x[i];
-        for (int k = 0; k <= jlast; ++k) xi += sh.y[k] * V[(size_t)k * ns + i];
-        x[i] = xi;
-      }
-      __threadfence();
+      for (int i = r0 + tid; i < r1; i += GC_THREADS) x[i] += comb_rows<8>(ns, jlast, V, i, sh.y);
       grid.sync();
       if (!(rel * bnorm > target) || it >= maxit) {
         if (!(rel == rel)) flags |= 2;
