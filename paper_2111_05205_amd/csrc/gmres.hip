@@ -44,13 +44,12 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Cooperative-kernel helpers.  part[k] += V_k[i] w for k <= j, and
+// part[k] += V_k[i] w for k <= j, and
 // sum_{k <= j} coef[k] V_k[i]: basis rows are read CH at a time with the index
 // clamped to j, so every load is issued without a branch (and lands in rows
 // already written) and a thread's loads are in flight together.
-template <int CH>
-__device__ inline void dot_rows(int ns, int j, const double* __restrict__ V, int i, double w,
-                                double (&part)[GM_MAXM + 1]) {
+template <int CH, int NP>
+__device__ inline void dot_rows(int ns, int j, const double* __restrict__ V, int i, double w, double (&part)[NP]) {
 #pragma unroll
   for (int c = 0; c < GM_MAXM / CH; ++c) {
     if (CH * c <= j) {
@@ -231,11 +230,7 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, int W, const 
         for (int pass = 0; pass < 2; ++pass) {
           multi_dot(ns, j, V, Wv, sh);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
-          for (int i = tid; i < ns; i += GM_THREADS) {
-            double wi = Wv[i];
-            for (int k = 0; k <= j; ++k) wi -= sh.hv[k] * V[(size_t)k * ns + i];
-            Wv[i] = wi;
-          }
+          for (int i = tid; i < ns; i += GM_THREADS) Wv[i] -= comb_rows<4>(ns, j, V, i, sh.hv);
           __syncthreads();
         }
         double ww = 0.0;
@@ -277,11 +272,7 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, int W, const 
         }
       }
       __syncthreads();
-      for (int i = tid; i < ns; i += GM_THREADS) {
-        double xi = x[i];
-        for (int k = 0; k <= jlast; ++k) xi += sh.y[k] * V[(size_t)k * ns + i];
-        x[i] = xi;
-      }
+      for (int i = tid; i < ns; i += GM_THREADS) x[i] += comb_rows<4>(ns, jlast, V, i, sh.y);
       __syncthreads();
       if (!(rel * bnorm > target) || it >= maxit) {
         if (!(rel == rel)) flags |= 2;
