@@ -123,7 +123,9 @@ typedef struct {
   int m2l_variant[16];  /* [n], n = 1..depth-1: autotuned M2L launch for the n finest levels ending an interval
                            together, 2 * tile + persistent; tile (columns x K step x operator rows per
                            workgroup) 0 128x16x128, 1 64x16x128, 2 64x32x128, 3 32x16x128, 4 32x32x128,
-                           5 32x16x256, 6 64x16x256, 7 32x32x256 */
+                           5 32x16x256, 6 64x16x256, 7 32x32x256 (moment tile shared through LDS);
+                           8 32x16x128, 9 32x16x256, 10 64x16x128, 11 64x16x256 (each lane reads its
+                           moments directly, no LDS or barrier in the K loop) */
   int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
 } tdbem_info;
 
@@ -238,6 +240,14 @@ int tdbem_profile_read(struct tdbem_ctx *ctx, double *ms, int64_t *launches, int
 /* Like tdbem_profile(ctx, 1) but only the categories whose bit is set in mask
  * are bracketed (fewer events in the stream); mask 0 disables profiling. */
 int tdbem_profile_mask(struct tdbem_ctx *ctx, unsigned mask);
+
+/* Override the autotuned M2L launch for the n finest levels ending an interval
+ * together (n = 1 .. depth-1; tdbem_info.m2l_variant reports the current one):
+ * choice = 2 * tile + persistent, tile 0 .. 11 as listed at m2l_variant.  For
+ * tests and tuning studies; the results are the same for every choice up to
+ * summation order.  TDBEM_E_INVAL without an FMM, for n or choice out of range,
+ * or for tiles 8 .. 11 when p_s^3 p_t is not a multiple of 4. */
+int tdbem_set_m2l_variant(struct tdbem_ctx *ctx, int n, int choice);
 
 /* ------------------------------------------------------------------------
  * Learned initial guess (not part of the paper: the per-step system of eq.

@@ -195,6 +195,11 @@ class TDBEM:
         self._check(self._L.tdbem_incident_forcing(self._h, ctypes.byref(incs), int(a0), int(n), _dptr(out)))
         return out
 
+    def set_m2l_variant(self, n, choice):
+        """Override the autotuned M2L launch for the n finest levels ending together
+        (choice = 2 * tile + persistent, see tdbem_info.m2l_variant)."""
+        self._check(self._L.tdbem_set_m2l_variant(self._h, int(n), int(choice)))
+
     def profile(self, enable=True, kinds=None):
         """Start (clear) or stop per-kernel timing of this context; kinds: None (all)
         or an iterable of category names (see PROF_KINDS) to bracket only those."""

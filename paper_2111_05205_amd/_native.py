@@ -82,6 +82,7 @@ def lib():
         L.tdbem_profile.argtypes = [vp, ip]
         L.tdbem_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ip]
         L.tdbem_profile_mask.argtypes = [vp, ctypes.c_uint]
+        L.tdbem_set_m2l_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.tdbem_mlp_forward.argtypes = [vp, ip, vp, vp, vp, vp]
         L.tdbem_mlp_workspace_floats.argtypes = [ip]
         L.tdbem_mlp_workspace_floats.restype = ctypes.c_size_t

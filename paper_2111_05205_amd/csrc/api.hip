@@ -504,6 +504,11 @@ int tdbem_profile_mask(tdbem_ctx* ctx, unsigned mask) {
   });
 }
 
+int tdbem_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
+  if (!ctx || !ctx->fmm) return TDBEM_E_INVAL;
+  return fmm_set_m2l_variant(ctx, n, choice);
+}
+
 int tdbem_profile_read(tdbem_ctx* ctx, double* ms, int64_t* launches, int n) {
   if (!ctx || n < 0 || n > 16) return TDBEM_E_INVAL;
   return guarded(ctx, [&] {

@@ -404,7 +404,9 @@ template <> struct Mfma<float> {
 };
 
 // Operators in MFMA fragment order, V = 16 / sizeof(T) k blocks interleaved per lane:
-// Uf[slot][rb][kb / V][lane][kb % V] = U[16 rb + lane%16][4 kb + lane/16], rows padded to
+// Uf[slot][rb][kb / V][lane][kb % V] = U[16 rb + lane%16][16 (kb/4) + 4 (lane/16) + kb%4]: the
+// fragment of MFMA k-substep q of a 16-column block gives lane group kk = lane/16 column
+// 4 kk + q, so a lane's four substeps are four consecutive columns.  Rows padded to
 // RB = ceil(GP/16) blocks and columns to KB = m2l_kblocks(P) blocks (zeros).  A lane's A
 // fragments of V consecutive k blocks are then one 16-byte load, and a wave's load is
 // 1 KB of contiguous memory.
@@ -419,7 +421,7 @@ __global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double*
   const int e = (int)(idx % V), lane = (int)((idx / V) & 63);
   const int64_t blk = idx / (64 * V);
   const int kb = (int)(blk % (KB / V)) * V + e, rb = (int)(blk / (KB / V));
-  const int row = rb * 16 + (lane & 15), col = kb * 4 + (lane >> 4);
+  const int row = rb * 16 + (lane & 15), col = 16 * (kb >> 2) + 4 * (lane >> 4) + (kb & 3);
   const double v = (row < GP && col < P) ? U[((int64_t)slot * GP + row) * P + col] : 0.0;
   Uf[(int64_t)slot * per + idx] = (T)v;
 }
@@ -553,7 +555,8 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
 #pragma unroll
     for (int q = 0; q < QS; ++q)
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) bf[q][cb] = Bs[b][4 * q + (lane >> 4)][cb * 16 + (lane & 15)];
+      for (int cb = 0; cb < NCB; ++cb)
+        bf[q][cb] = Bs[b][16 * (q >> 2) + 4 * (lane >> 4) + (q & 3)][cb * 16 + (lane & 15)];
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
 #pragma unroll
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
         if (decltype(full)::value || cb < ncb) {
 #pragma unroll
           for (int r = 0; r < RPW; ++r) {
-            if constexpr (Mfma<T>::kTransposed)  // A = moment tile (pair cb*16 + lane%16, k 4q + lane/16)
+            if constexpr (Mfma<T>::kTransposed)  // A = moment tile (pair cb*16 + lane%16)
               acc[r][cb] = Mfma<T>::op(bf[q][cb], ca[r][q], acc[r][cb]);
             else
               acc[r][cb] = Mfma<T>::op(ca[r][q], bf[q][cb], acc[r][cb]);
@@ -641,12 +644,180 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
   } while (w < total);
 }
 
+// The same products without LDS or barriers in the K loop: every lane loads
+// its B fragments straight from the moments.  With the operator layout above,
+// lane (n = lane%16, kk = lane/16) needs moments 4 kk .. 4 kk + 3 of the 16-column
+// block for its four k-substeps, one contiguous 32-byte read per column block,
+// so each wave runs its K loop on its own (the four waves of a workgroup only
+// share the tile's pair list, read once into LDS for the epilogue).  K steps of
+// 16; P a multiple of 4.  The moment loads are clamped into the row and masked
+// (column live, k < P) when they are used.
+template <class T, int NCB, int RPW, bool PERS>
+constexpr int m2l_direct_waves() {
+  return sizeof(T) == 8 || PERS || NCB != 2 ? 1 : RPW == 2 ? 3 : 2;
+}
+
+template <class T, int NCB, int RPW, bool PERS>
+__global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void m2l_direct_kernel(
+    int P, int GP, int RB, int KB, M2LWork W) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  typedef typename Vec16<T>::type vec_t;
+  typedef double dvec2_t __attribute__((ext_vector_type(2)));
+  constexpr int V = Vec16<T>::n;
+  constexpr int QS = 4;                     // k-substeps per K step of 16
+  constexpr int BN = NCB * 16;
+  __shared__ int pid[BN];
+  const int total = W.total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk4 = 4 * (lane >> 4);
+  int w = blockIdx.x;
+  do {
+  const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
+  const int item = x8 * q8 + min(x8, r8) + w / 8;
+  int lv = 0;
+  while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
+  const M2LLevelWork& Lw = W.lev[lv];
+  const int local = item - Lw.item0;
+  const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
+  const int32_t* __restrict__ tiles = Lw.tiles;
+  const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
+  const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
+  const T* __restrict__ Uf = static_cast<const T*>(Lw.Uf);
+  const double* __restrict__ mom = Lw.mom;
+  T* __restrict__ stage = static_cast<T*>(Lw.stage);
+  const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
+  if constexpr (PERS) __syncthreads();  // the previous item's readers of pid are done
+  const int rb0 = (rowblk * 4 + wave) * RPW;
+  if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
+  // this lane's moment rows (column cb*16 + lane%16 of each column block)
+  const double* brow[NCB];
+  bool blive[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int col = cb * 16 + (lane & 15);
+    blive[cb] = col < cnt;
+    brow[cb] = mom + (int64_t)src_by_slot[first + min(col, cnt - 1)] * P;
+  }
+  const int64_t per = (int64_t)RB * KB * 64;
+  const vec_t* Ar[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+    Ar[r] = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0 + r, RB - 1) * KB) * 64) + lane;
+  const int ncb = (cnt + 15) >> 4;
+  acc_t acc[RPW][NCB];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  constexpr int DEPTH = (sizeof(T) == 4 && RPW == 2) ? 2 : 1;
+  constexpr int NSET = DEPTH + 1;
+  T fa[NSET][RPW][QS];
+  dvec2_t fb[NSET][NCB][2];
+  auto load = [&](int set, int k0) {
+    const int g0 = (k0 >> 2) / V;
+#pragma unroll
+    for (int g = 0; g < QS / V; ++g) {
+      const int kg = min(g0 + g, KB / V - 1);
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const vec_t a = Ar[r][(int64_t)kg * 64];
+#pragma unroll
+        for (int e = 0; e < V; ++e) fa[set][r][g * V + e] = a[e];
+      }
+    }
+    const int off = min(k0 + kk4, P - 4);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const dvec2_t* bp = reinterpret_cast<const dvec2_t*>(brow[cb] + off);
+      fb[set][cb][0] = bp[0];
+      fb[set][cb][1] = bp[1];
+    }
+  };
+  auto products = [&](auto full, int set, int k0) {
+    const bool kin = k0 + kk4 < P;
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        if (decltype(full)::value || cb < ncb) {
+          const double m = fb[set][cb][q >> 1][q & 1];
+          const T bv = (blive[cb] && kin) ? (T)m : T(0);
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            if constexpr (Mfma<T>::kTransposed)
+              acc[r][cb] = Mfma<T>::op(bv, fa[set][r][q], acc[r][cb]);
+            else
+              acc[r][cb] = Mfma<T>::op(fa[set][r][q], bv, acc[r][cb]);
+          }
+        }
+      }
+    }
+  };
+#pragma unroll
+  for (int h = 0; h < DEPTH; ++h) load(h, h * 16);  // in bounds past P too (clamped)
+  const int nsteps = (P + 15) / 16;
+  auto step = [&](auto hc, int s, auto steady) {
+    constexpr int h = decltype(hc)::value;
+    constexpr bool st = decltype(steady)::value;
+    if (st || s + DEPTH < nsteps) load((h + DEPTH) % NSET, (s + DEPTH) * 16);
+    if (sizeof(T) == 4 && ncb == NCB) products(std::true_type{}, h, s * 16);
+    else products(std::false_type{}, h, s * 16);
+  };
+  typedef std::integral_constant<int, 0> set0;
+  typedef std::integral_constant<int, 1> set1;
+  typedef std::integral_constant<int, 2 % NSET> set2;
+  int s = 0;
+  for (; s + NSET - 1 + DEPTH < nsteps; s += NSET) {
+    step(set0{}, s, std::true_type{});
+    step(set1{}, s + 1, std::true_type{});
+    if constexpr (NSET == 3) step(set2{}, s + 2, std::true_type{});
+  }
+  for (; s < nsteps; ++s) {
+    const int j = s % NSET;
+    if (j == 0) step(set0{}, s, std::false_type{});
+    else if (j == 1) step(set1{}, s, std::false_type{});
+    else step(set2{}, s, std::false_type{});
+  }
+  __syncthreads();  // pid written by the first BN threads
+#pragma unroll
+  for (int h = 0; h < RPW; ++h)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      if (cb >= ncb) continue;
+      if constexpr (Mfma<T>::kTransposed) {
+        const int row = (rb0 + h) * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int pr = pid[cb * 16 + 4 * r + (lane >> 4)];
+          if (pr >= 0 && row < GP) stage[(int64_t)pr * GP + row] = acc[h][cb][r];
+        }
+        continue;
+      }
+      const int p = pid[cb * 16 + (lane & 15)];
+      if constexpr (sizeof(T) == 4) {
+        const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
+        if (p >= 0 && (GP & 3) == 0 && row0 + 3 < GP) {
+          *reinterpret_cast<flt4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
+          continue;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (rb0 + h) * 16 + Mfma<T>::row(lane, r);
+        if (p >= 0 && row < GP) stage[(int64_t)p * GP + row] = acc[h][cb][r];
+      }
+    }
+    if constexpr (!PERS) break;
+    w += gridDim.x;
+  } while (w < total);
+}
+
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
 // wave).  The variant and whether the launch is persistent are chosen by
 // timing (autotuning).
-constexpr int M2L_VARIANTS = 8;
-static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32};
-static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4};
+constexpr int M2L_VARIANTS = 12;
+constexpr int M2L_FIRST_DIRECT = 8;  // variants from here on use m2l_direct_kernel (P % 4 == 0)
+static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32, 32, 32, 64, 64};
+static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4, 2, 4, 2, 4};
 
 template <class T, bool PERS>
 static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
@@ -658,7 +829,11 @@ static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int 
     case 4: m2l_mfma_kernel<T, 2, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     case 5: m2l_mfma_kernel<T, 2, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     case 6: m2l_mfma_kernel<T, 4, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    default: m2l_mfma_kernel<T, 2, 32, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 7: m2l_mfma_kernel<T, 2, 32, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 8: m2l_direct_kernel<T, 2, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 9: m2l_direct_kernel<T, 2, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 10: m2l_direct_kernel<T, 4, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    default: m2l_direct_kernel<T, 4, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
   }
 }
 
@@ -1025,6 +1200,7 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
     int bestc = 2;  // 64 x 16 x 128, one item per workgroup
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
       if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
+      if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) continue;
       launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
       for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
@@ -1381,6 +1557,14 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
     bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
   }
   info->m2l_matrix_bytes = bytes;
+}
+
+int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
+  Fmm* f = ctx->fmm;
+  if (!f || n < 1 || n > f->D - 1 || n >= 16 || choice < 0 || choice >= 2 * M2L_VARIANTS) return TDBEM_E_INVAL;
+  if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) return TDBEM_E_INVAL;
+  f->m2l_choice[n] = choice;
+  return TDBEM_OK;
 }
 
 void fmm_near_pairs(const tdbem_ctx* ctx, std::vector<int64_t>& row_ptr, std::vector<int32_t>& pair_j) {

@@ -206,6 +206,7 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out);
 // the coefficient row beta has been stored: update moments and run interval-end translations
 void fmm_advance(tdbem_ctx* ctx, int beta);
 void fmm_info(const tdbem_ctx* ctx, tdbem_info* info);
+int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice);
 void fmm_near_pairs(const tdbem_ctx* ctx, std::vector<int64_t>& row_ptr, std::vector<int32_t>& pair_j);
 // device arrays that carry FMM state from one step to the next (moments, locals, recurrence terms)
 void fmm_state_buffers(const tdbem_ctx* ctx, std::vector<std::pair<double*, size_t>>& out);

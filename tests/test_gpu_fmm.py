@@ -114,3 +114,64 @@ def test_fmm_fp32_m2l_products(s3):
     want = R.history_rhs(26, u, np.zeros_like(u))
     e = _rel(got, want)
     assert 1e-12 < e < 1e-4, e
+
+
+N_M2L_TILES = 12  # tdbem_info.m2l_variant: choice = 2 * tile + persistent
+
+
+def test_fmm_every_m2l_variant_matches_oracle():
+    """Every M2L tile shape, one item per workgroup and persistent, FP64 and FP32,
+    forced with tdbem_set_m2l_variant: the history sum against the oracle's FMM
+    (P = 256, so the LDS-free tiles 8..11 are eligible)."""
+    P = _P()
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    R = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, 4, 4)
+    ns = tri.shape[0]
+    u = synth.random_history(ns, 24, seed=3)
+    q = synth.random_history(ns, 24, seed=4)
+    want = R.history_rhs(21, u, q)
+    dev = torch.device("cuda")
+    for prec, tol in ((P.M2L_FP64, 1e-10), (P.M2L_FP32, 1e-4)):
+        g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=4, p_t=4, m2l_prec=prec, nt_max=32)
+        for choice in range(2 * N_M2L_TILES):
+            g.set_m2l_variant(1, choice)
+            assert g.info()["m2l_variant"][1] == choice
+            g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
+            e = _rel(g.fmm_eval(21).cpu().numpy(), want)
+            assert e < tol, (prec, choice, e)
+        with pytest.raises(P.TDBEMError):
+            g.set_m2l_variant(1, 2 * N_M2L_TILES)
+        with pytest.raises(P.TDBEMError):
+            g.set_m2l_variant(2, 0)  # depth 2: only n = 1
+        g.close()
+
+
+def test_fmm_m2l_variants_agree_across_levels(s3):
+    """Launches covering two levels at once (depth 3): every variant gives the
+    autotuned variant's history sum (FP64 1e-12, FP32 1e-5 relative)."""
+    P = _P()
+    xyz, tri, dt = s3
+    u = synth.random_history(tri.shape[0], 30, seed=5)
+    dev = torch.device("cuda")
+    for prec, tol in ((P.M2L_FP64, 1e-12), (P.M2L_FP32, 1e-5)):
+        g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=3, p_s=4, p_t=4, m2l_prec=prec, nt_max=40)
+        g.set_history(torch.tensor(u[:27], device=dev), None)
+        ref = g.fmm_eval(28).cpu().numpy()
+        for choice in range(2 * N_M2L_TILES):
+            for n in (1, 2):
+                g.set_m2l_variant(n, choice)
+            g.set_history(torch.tensor(u[:27], device=dev), None)
+            e = _rel(g.fmm_eval(28).cpu().numpy(), ref)
+            assert e < tol, (prec, choice, e)
+        g.close()
+
+
+def test_fmm_direct_tiles_need_p_multiple_of_4(s3):
+    P = _P()
+    xyz, tri, dt = s3
+    g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=3, p_s=3, p_t=3, nt_max=8)  # P = 81
+    g.set_m2l_variant(1, 2 * 7)
+    with pytest.raises(P.TDBEMError):
+        g.set_m2l_variant(1, 2 * 8)
+    g.close()
