@@ -63,6 +63,7 @@ struct FmmLevel {
   DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
   DevBuf<float> d_U32, d_stage32;           // FP32 operators and staging (mixed-precision M2L)
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_stage, d_dp;
+  DevBuf<float> d_mom32;                    // FP32 copy of the moments at an interval end (FP32 M2L)
 };
 
 struct Fmm {
@@ -436,6 +437,7 @@ struct M2LLevelWork {
   const int32_t* src_by_slot;
   const void* Uf;                // T operators in fragment order
   const double* mom;
+  const float* mom32;            // FP32 copy of mom (FP32 products only)
   void* stage;                   // T per-pair products
   int ntiles;
   int item0;                     // first work item of this level
@@ -647,7 +649,8 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
 // The same products without LDS or barriers in the K loop: every lane loads
 // its B fragments straight from the moments.  With the operator layout above,
 // lane (n = lane%16, kk = lane/16) needs moments 4 kk .. 4 kk + 3 of the 16-column
-// block for its four k-substeps, one contiguous 32-byte read per column block,
+// block for its four k-substeps, one contiguous read per column block (16 bytes
+// from the FP32 copy of the moments, 32 bytes in FP64),
 // so each wave runs its K loop on its own (the four waves of a workgroup only
 // share the tile's pair list, read once into LDS for the epilogue).  K steps of
 // 16; P a multiple of 4.  The moment loads are clamped into the row and masked
@@ -662,7 +665,6 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
     int P, int GP, int RB, int KB, M2LWork W) {
   typedef typename Mfma<T>::acc_t acc_t;
   typedef typename Vec16<T>::type vec_t;
-  typedef double dvec2_t __attribute__((ext_vector_type(2)));
   constexpr int V = Vec16<T>::n;
   constexpr int QS = 4;                     // k-substeps per K step of 16
   constexpr int BN = NCB * 16;
@@ -688,14 +690,18 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
   if constexpr (PERS) __syncthreads();  // the previous item's readers of pid are done
   const int rb0 = (rowblk * 4 + wave) * RPW;
   if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
-  // this lane's moment rows (column cb*16 + lane%16 of each column block)
-  const double* brow[NCB];
+  // this lane's moment rows (column cb*16 + lane%16 of each column block), in
+  // the product's precision: FP32 tiles read the FP32 copy of the moments
+  const T* mbase;
+  if constexpr (sizeof(T) == 4) mbase = Lw.mom32;
+  else mbase = mom;
+  const T* brow[NCB];
   bool blive[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) {
     const int col = cb * 16 + (lane & 15);
     blive[cb] = col < cnt;
-    brow[cb] = mom + (int64_t)src_by_slot[first + min(col, cnt - 1)] * P;
+    brow[cb] = mbase + (int64_t)src_by_slot[first + min(col, cnt - 1)] * P;
   }
   const int64_t per = (int64_t)RB * KB * 64;
   const vec_t* Ar[RPW];
@@ -710,8 +716,9 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
     for (int j = 0; j < NCB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
   constexpr int DEPTH = (sizeof(T) == 4 && RPW == 2) ? 2 : 1;
   constexpr int NSET = DEPTH + 1;
+  typedef T mvec_t __attribute__((ext_vector_type(4)));
   T fa[NSET][RPW][QS];
-  dvec2_t fb[NSET][NCB][2];
+  mvec_t fb[NSET][NCB];
   auto load = [&](int set, int k0) {
     const int g0 = (k0 >> 2) / V;
 #pragma unroll
@@ -726,11 +733,7 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
     }
     const int off = min(k0 + kk4, P - 4);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const dvec2_t* bp = reinterpret_cast<const dvec2_t*>(brow[cb] + off);
-      fb[set][cb][0] = bp[0];
-      fb[set][cb][1] = bp[1];
-    }
+    for (int cb = 0; cb < NCB; ++cb) fb[set][cb] = *reinterpret_cast<const mvec_t*>(brow[cb] + off);
   };
   auto products = [&](auto full, int set, int k0) {
     const bool kin = k0 + kk4 < P;
@@ -739,8 +742,7 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         if (decltype(full)::value || cb < ncb) {
-          const double m = fb[set][cb][q >> 1][q & 1];
-          const T bv = (blive[cb] && kin) ? (T)m : T(0);
+          const T bv = (blive[cb] && kin) ? fb[set][cb][q] : T(0);
 #pragma unroll
           for (int r = 0; r < RPW; ++r) {
             if constexpr (Mfma<T>::kTransposed)
@@ -1143,6 +1145,7 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     Lw.pairs_by_slot = L.d_pairs_by_slot.p;
     Lw.src_by_slot = L.d_src_by_slot.p;
     Lw.mom = L.d_mom.p;
+    Lw.mom32 = L.d_mom32.p;
     if (f->f32) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
     else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
     Lw.item0 = total;
@@ -1353,6 +1356,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         TDBEM_HIP(hipGetLastError());
       }
       L.d_mom.alloc((size_t)L.ncell * P);
+      if (f->f32) {
+        L.d_mom32.alloc((size_t)L.ncell * P);
+        TDBEM_HIP(hipMemsetAsync(L.d_mom32.p, 0, L.d_mom32.n * sizeof(float), st));
+      }
       L.d_ring.alloc((size_t)f->R * L.ncell * P);
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
@@ -1447,6 +1454,11 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
 static int sep_threads(int P) { return std::min(1024, ((P + 63) / 64) * 64); }
 
 void fmm_advance(tdbem_ctx* ctx, int beta) {
@@ -1497,6 +1509,17 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
       m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
                                                          L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p);
       TDBEM_HIP(hipGetLastError());
+    }
+    if (f->f32) {
+      // the FP32 moments that the LDS-free FP32 tiles read
+      ProfScope ps(ctx, K_OTHER);
+      for (int l = D; l > D - ndue && l >= 2; --l) {
+        FmmLevel& L = f->lev[l];
+        if (L.npair == 0) continue;
+        to_f32_kernel<<<(unsigned)((L.d_mom.n + 255) / 256), 256, 0, st>>>(L.d_mom.p, L.d_mom32.p,
+                                                                           (int64_t)L.d_mom.n);
+        TDBEM_HIP(hipGetLastError());
+      }
     }
     {
       ProfScope ps(ctx, K_M2L_GEMM);
