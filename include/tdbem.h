@@ -289,6 +289,13 @@ int tdbem_set_m2l_variant(struct tdbem_ctx *ctx, int n, int choice);
 int tdbem_mlp_forward(const float *dev_params, int n, const float *dev_feat, float *dev_y,
                       uint16_t *dev_act, void *hip_stream);
 
+/* The same forward pass with the network installed in ctx by tdbem_mlp_load
+ * (or tdbem_restore), through the march's kernel, which reads the hidden
+ * layers' weights pre-rounded to bf16 in matrix-core fragment order: dev_y (n)
+ * equals tdbem_mlp_forward of the installed parameters bit for bit.  Runs on
+ * the context's stream.  TDBEM_E_INVAL if no network is installed. */
+int tdbem_mlp_forward_loaded(struct tdbem_ctx *ctx, int n, const float *dev_feat, float *dev_y);
+
 /* FP32 floats of workspace tdbem_mlp_backward needs for n rows. */
 size_t tdbem_mlp_workspace_floats(int n);
 

@@ -237,6 +237,18 @@ class TDBEM:
         from .mlp import _fptr
         self._check(self._L.tdbem_mlp_load(self._h, _fptr(params, N.MLP_NPARAM, "params")))
 
+    def mlp_forward_loaded(self, feat):
+        """y (n) of the installed network for feat (n x 16 float32 CUDA tensor), through the
+        march's kernel (pre-packed bf16 fragments); equals mlp.forward of the same parameters."""
+        import torch
+        from .mlp import _fptr
+        n = feat.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=feat.device)
+        torch.cuda.synchronize()
+        self._check(self._L.tdbem_mlp_forward_loaded(self._h, int(n), _fptr(feat, n * N.MLP_IN_PAD, "feat"),
+                                                     _fptr(y)))
+        return y
+
     def mlp_record(self, feat=None, target=None):
         """Record features (nt_max x Ns x 16) and targets (nt_max x Ns), float32 CUDA tensors, during
         later steps (rows beta >= 4); no arguments stops recording."""

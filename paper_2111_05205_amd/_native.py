@@ -84,6 +84,7 @@ def lib():
         L.tdbem_profile_mask.argtypes = [vp, ctypes.c_uint]
         L.tdbem_set_m2l_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.tdbem_mlp_forward.argtypes = [vp, ip, vp, vp, vp, vp]
+        L.tdbem_mlp_forward_loaded.argtypes = [vp, ip, vp, vp]
         L.tdbem_mlp_workspace_floats.argtypes = [ip]
         L.tdbem_mlp_workspace_floats.restype = ctypes.c_size_t
         L.tdbem_mlp_backward.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]

@@ -794,6 +794,7 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
       ctx->d_mlp_params.alloc(TDBEM_MLP_NPARAM);
       TDBEM_HIP(hipMemcpyAsync(ctx->d_mlp_params.p, p, TDBEM_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice,
                                ctx->stream));
+      mlp_pack(ctx);
       ctx->mlp_loaded = true;
     }
     TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));

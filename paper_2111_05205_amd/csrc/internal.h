@@ -123,6 +123,7 @@ struct tdbem_ctx {
   // learned initial guess
   bool mlp_loaded = false;
   tdbem::DevBuf<float> d_mlp_params;   // packed FP32 parameters
+  tdbem::DevBuf<uint16_t> d_mlp_wpk;   // hidden-layer weights as bf16 matrix-core fragments (march forward)
   tdbem::DevBuf<float> d_mlp_feat, d_mlp_y;
   tdbem::DevBuf<double> d_x_alt;       // extrapolated starting point offered beside the network's
   tdbem::DevBuf<double> d_mlp_diag, d_mlp_s, d_area;
@@ -190,6 +191,7 @@ void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc, int a0, int n, do
 
 // mlp.hip
 void mlp_prepare(tdbem_ctx* ctx);  // per-context buffers of the guess (diagonal of A, areas)
+void mlp_pack(tdbem_ctx* ctx);     // refresh d_mlp_wpk from d_mlp_params (stream-ordered)
 // features of unknown row beta (>= 4) from the stored history and b into feat (Ns x 16); scale into d_mlp_s
 void launch_mlp_features(tdbem_ctx* ctx, int beta, const double* b, float* feat);
 // x = quadratic extrapolation of the last three rows + s * network(feat); xe = the extrapolation

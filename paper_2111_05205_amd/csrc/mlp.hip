@@ -60,10 +60,15 @@ __device__ inline float round_bf16(float f) { return from_bf16(to_bf16(f)); }
 // weight fragments of the next K step are loaded while the current one is
 // multiplied.
 
-template <int FR>
+// PK: the hidden layers' weights come pre-rounded in matrix-core fragment
+// order (wpk, see mlp_pack_kernel): a wave fetches all of a layer's fragments
+// for its 64 neurons at once (32 x 16 bytes per lane), the next layer's while
+// the current one is multiplied, so the weight stream costs one memory
+// latency per layer instead of one per K step.
+template <int FR, bool PK>
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ P, int n,
                                                       const float* __restrict__ feat, float* __restrict__ y,
-                                                      uint16_t* __restrict__ act) {
+                                                      uint16_t* __restrict__ act, const uint4* __restrict__ wpk) {
   constexpr int RT = FR / 16;     // row tiles per wave
   constexpr int TPR = 256 / FR;   // threads per row in the output layer
   __shared__ __align__(16) uint16_t H[2][FR * HS];
@@ -79,6 +84,18 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
   }
   for (int k = tid; k < WID; k += 256) w4s[k] = round_bf16(P[OFF_W4 + k]);
   const float b4 = P[OFF_B4];
+  // packed fragments of hidden layer 1 or 2: [layer][tile 16][kstep 8][lane 64]
+  uint4 wq[8][4];
+  auto fetch = [&](int hl) {
+    if constexpr (PK) {
+      const uint4* base = wpk + (size_t)hl * 16 * 8 * 64;
+#pragma unroll
+      for (int st = 0; st < 8; ++st)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) wq[st][t] = base[((w * 4 + t) * 8 + st) * 64 + lane];
+    }
+  };
+  fetch(0);
   __syncthreads();
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? NINP : WID;
@@ -102,6 +119,22 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
         bv[b] = __builtin_bit_cast(s4, *reinterpret_cast<const uint2*>(Hin + (b * 16 + li) * HS + 4 * lk));
       for (int a = 0; a < 4; ++a)
         for (int b = 0; b < RT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+    } else if (PK) {
+      // K = 256 in 8 steps of v_mfma_f32_16x16x32_bf16 on the fetched fragments
+#pragma unroll
+      for (int st = 0; st < 8; ++st) {
+        b8 av[4], bv[RT];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[t] = __builtin_bit_cast(b8, wq[st][t]);
+#pragma unroll
+        for (int b = 0; b < RT; ++b)
+          bv[b] = __builtin_bit_cast(b8, *reinterpret_cast<const uint4*>(Hin + (b * 16 + li) * HS + 32 * st + 8 * lk));
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < RT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+      if (layer == 1) fetch(1);  // the last hidden layer's fragments, while this layer finishes
     } else {
       // K = 256 in 8 steps of v_mfma_f32_16x16x32_bf16: A[i][k] at lane i + 16 (k / 8), element k % 8
       float4 wn[4][2];
@@ -409,10 +442,28 @@ __global__ void mlp_target_kernel(int ns, int beta, const double* __restrict__ h
   t[i] = (float)((h[(int64_t)beta * ns + i] - extrapolated(h, beta, ns, i)) * inv);
 }
 
-void launch_fwd(const float* P, int n, const float* feat, float* y, uint16_t* act, hipStream_t st) {
+void launch_fwd(const float* P, int n, const float* feat, float* y, uint16_t* act, hipStream_t st,
+                const uint4* wpk = nullptr) {
   if (n <= 0) return;
-  mlp_fwd_kernel<FFR><<<(n + FFR - 1) / FFR, 256, 0, st>>>(P, n, feat, y, act);
+  if (wpk)
+    mlp_fwd_kernel<FFR, true><<<(n + FFR - 1) / FFR, 256, 0, st>>>(P, n, feat, y, act, wpk);
+  else
+    mlp_fwd_kernel<FFR, false><<<(n + FFR - 1) / FFR, 256, 0, st>>>(P, n, feat, y, act, nullptr);
   TDBEM_HIP(hipGetLastError());
+}
+
+// Hidden-layer weights W2, W3 rounded to bf16 in the fragment order of
+// v_mfma_f32_16x16x32_bf16 (A[i][k] at lane i + 16 (k / 8), element k % 8):
+// wpk[layer][tile t][kstep s][lane] holds W[16 t + lane%16][32 s + 8 (lane/16) + e], e = 0..7.
+__global__ void mlp_pack_kernel(const float* __restrict__ P, uint4* __restrict__ wpk) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (layer, t, s, lane)
+  if (idx >= 2 * 16 * 8 * 64) return;
+  const int lane = idx & 63, s = (idx >> 6) & 7, t = (idx >> 9) & 15, layer = idx >> 13;
+  const float* W = P + (layer == 0 ? OFF_W2 : OFF_W3) + (int64_t)(16 * t + (lane & 15)) * WID + 32 * s + 8 * (lane >> 4);
+  uint32_t h[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) h[e] = to_bf16(W[e]);
+  wpk[idx] = uint4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
 }
 
 }  // namespace
@@ -476,7 +527,8 @@ void launch_mlp_guess(tdbem_ctx* ctx, int beta, const float* feat, double* x, do
   ProfScope ps(ctx, K_MLP);
   const int ns = ctx->ns;
   const double* h = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
-  launch_fwd(ctx->d_mlp_params.p, ns, feat, ctx->d_mlp_y.p, nullptr, ctx->stream);
+  launch_fwd(ctx->d_mlp_params.p, ns, feat, ctx->d_mlp_y.p, nullptr, ctx->stream,
+             reinterpret_cast<const uint4*>(ctx->d_mlp_wpk.p));
   mlp_guess_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(ns, beta, h, ctx->d_mlp_s.p, ctx->d_mlp_y.p, x,
                                                                xe);
   TDBEM_HIP(hipGetLastError());
@@ -487,6 +539,13 @@ void launch_mlp_target(tdbem_ctx* ctx, int beta, float* target) {
   const int ns = ctx->ns;
   const double* h = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
   mlp_target_kernel<<<(ns + 255) / 256, 256, 0, ctx->stream>>>(ns, beta, h, ctx->d_mlp_s.p, target);
+  TDBEM_HIP(hipGetLastError());
+}
+
+void mlp_pack(tdbem_ctx* ctx) {
+  ctx->d_mlp_wpk.alloc((size_t)2 * WID * WID);
+  mlp_pack_kernel<<<(2 * 16 * 8 * 64 + 255) / 256, 256, 0, ctx->stream>>>(
+      ctx->d_mlp_params.p, reinterpret_cast<uint4*>(ctx->d_mlp_wpk.p));
   TDBEM_HIP(hipGetLastError());
 }
 
@@ -518,6 +577,23 @@ int tdbem_mlp_forward(const float* dev_params, int n, const float* dev_feat, flo
     launch_fwd(dev_params, n, dev_feat, dev_y, dev_act, st);
     TDBEM_HIP(hipStreamSynchronize(st));
   });
+}
+
+int tdbem_mlp_forward_loaded(tdbem_ctx* ctx, int n, const float* dev_feat, float* dev_y) {
+  if (!ctx) return TDBEM_E_INVAL;
+  try {
+    if (!ctx->mlp_loaded) throw Error(TDBEM_E_INVAL, "mlp_forward_loaded: no network installed");
+    if (n < 0 || (n > 0 && (!dev_feat || !dev_y))) throw Error(TDBEM_E_INVAL, "mlp_forward_loaded: bad arguments");
+    if (reinterpret_cast<uintptr_t>(dev_feat) & 15)
+      throw Error(TDBEM_E_INVAL, "mlp_forward_loaded: features must be 16-byte aligned");
+    launch_fwd(ctx->d_mlp_params.p, n, dev_feat, dev_y, nullptr, ctx->stream,
+               reinterpret_cast<const uint4*>(ctx->d_mlp_wpk.p));
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+    return TDBEM_OK;
+  } catch (const Error& e) {
+    ctx->err = e.msg;
+    return e.code;
+  }
 }
 
 size_t tdbem_mlp_workspace_floats(int n) {
@@ -581,6 +657,7 @@ int tdbem_mlp_load(tdbem_ctx* ctx, const float* dev_params) {
     ctx->d_mlp_params.alloc(NPARAM);
     TDBEM_HIP(hipMemcpyAsync(ctx->d_mlp_params.p, dev_params, NPARAM * sizeof(float), hipMemcpyDeviceToDevice,
                              ctx->stream));
+    mlp_pack(ctx);
     TDBEM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->mlp_loaded = true;
     return TDBEM_OK;

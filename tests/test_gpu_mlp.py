@@ -73,6 +73,25 @@ def test_forward_matches_oracle(n):
         assert np.all(np.abs(a[k] - ref)[diff] <= 2.0 ** -7 * np.abs(ref)[diff] + 1e-30)
 
 
+@pytest.mark.parametrize("n", [1, 300, 5120])
+def test_loaded_forward_equals_api_forward(n):
+    """The march's forward (hidden-layer weights pre-packed as bf16 fragments at
+    mlp_load) gives the API forward's outputs bit for bit."""
+    M = _M()
+    P = _P()
+    xyz, tri = synth.icosphere(1)
+    s = P.TDBEM(xyz, tri, 1.0, synth.mean_edge_length(xyz, tri), 2, P.BMBIE, P.NEUMANN, nt_max=8,
+                guess=P.GUESS_MLP)
+    p, f = _params(7), _feat(n, 8)
+    with pytest.raises(P.TDBEMError):
+        s.mlp_forward_loaded(_dev(f))  # nothing installed yet
+    s.mlp_load(_dev(p))
+    y_api = M.forward(_dev(p), _dev(f))
+    y_loaded = s.mlp_forward_loaded(_dev(f))
+    assert torch.equal(y_api, y_loaded)
+    s.close()
+
+
 def test_forward_ragged_rows_only_written():
     M = _M()
     n = 100
