@@ -290,6 +290,90 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, int W, const 
 
 constexpr int GC_THREADS = 256;
 
+// Two rows per call (i0, i1) so that both rows' loads are in flight together.
+__device__ inline void ell_row2(int i0, int i1, int ns, int W, const int32_t* __restrict__ ec,
+                                const double* __restrict__ ev, const double* __restrict__ v, double& y0,
+                                double& y1) {
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+  int k = 0;
+  for (; k + 3 < W; k += 4) {
+    const int64_t o = (int64_t)k * ns;
+    int c0[4], c1[4];
+    double e0[4], e1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c0[q] = ec[o + q * ns + i0];
+      c1[q] = ec[o + q * ns + i1];
+      e0[q] = ev[o + q * ns + i0];
+      e1[q] = ev[o + q * ns + i1];
+    }
+    double x0[4], x1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x0[q] = v[c0[q]];
+      x1[q] = v[c1[q]];
+    }
+    a0 += e0[0] * x0[0] + e0[2] * x0[2];
+    b0 += e0[1] * x0[1] + e0[3] * x0[3];
+    a1 += e1[0] * x1[0] + e1[2] * x1[2];
+    b1 += e1[1] * x1[1] + e1[3] * x1[3];
+  }
+  for (; k < W; ++k) {
+    const int64_t o = (int64_t)k * ns;
+    a0 += ev[o + i0] * v[ec[o + i0]];
+    a1 += ev[o + i1] * v[ec[o + i1]];
+  }
+  y0 = a0 + b0;
+  y1 = a1 + b1;
+}
+
+template <int CH>
+__device__ inline void dot_rows2(int ns, int j, const double* __restrict__ V, int i0, int i1, double w0, double w1,
+                                 double (&part)[GM_MAXM + 1]) {
+#pragma unroll
+  for (int c = 0; c < GM_MAXM / CH; ++c) {
+    if (CH * c <= j) {
+      double v0[CH], v1[CH];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) {
+        const size_t r = (size_t)min(CH * c + kk, j) * ns;
+        v0[kk] = V[r + i0];
+        v1[kk] = V[r + i1];
+      }
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk)
+        if (CH * c + kk <= j) part[CH * c + kk] += v0[kk] * w0 + v1[kk] * w1;
+    }
+  }
+}
+
+template <int CH>
+__device__ inline void comb_rows2(int ns, int j, const double* __restrict__ V, int i0, int i1, const double* coef,
+                                  double& s0, double& s1) {
+  s0 = 0.0;
+  s1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < GM_MAXM / CH; ++c) {
+    if (CH * c <= j) {
+      double v0[CH], v1[CH];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) {
+        const size_t r = (size_t)min(CH * c + kk, j) * ns;
+        v0[kk] = V[r + i0];
+        v1[kk] = V[r + i1];
+      }
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk)
+        if (CH * c + kk <= j) {
+          s0 += coef[CH * c + kk] * v0[kk];
+          s1 += coef[CH * c + kk] * v1[kk];
+        }
+    }
+  }
+}
+
+
+
 struct CoopShared {
   double H[GM_MAXM + 1][GM_MAXM];
   double cs[GM_MAXM], sn[GM_MAXM], g[GM_MAXM + 1], y[GM_MAXM];
@@ -417,18 +501,28 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
       for (int j = 0; j < m; ++j) {
         const double* Vj = V + (size_t)j * ns;
         double* Wv = V + (size_t)(j + 1) * ns;
-        for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] = ell_row(i, ns, W, ec, ev, Vj);
+        // rows two at a time (i1 clamped to i0 past the slice end, its result dropped)
+        for (int i0 = r0 + tid; i0 < r1; i0 += 2 * GC_THREADS) {
+          const bool has1 = i0 + GC_THREADS < r1;
+          const int i1 = has1 ? i0 + GC_THREADS : i0;
+          double y0, y1;
+          ell_row2(i0, i1, ns, W, ec, ev, Vj, y0, y1);
+          Wv[i0] = y0;
+          if (has1) Wv[i1] = y1;
+        }
         double ww = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
           for (int k = 0; k < GM_MAXM + 1; ++k) part[k] = 0.0;
-          for (int i = r0 + tid; i < r1; i += GC_THREADS) {
-            const double wi = Wv[i];
-            dot_rows<8>(ns, j, V, i, wi, part);
+          for (int i0 = r0 + tid; i0 < r1; i0 += 2 * GC_THREADS) {
+            const bool has1 = i0 + GC_THREADS < r1;
+            const int i1 = has1 ? i0 + GC_THREADS : i0;
+            const double w0 = Wv[i0], w1 = has1 ? Wv[i1] : 0.0;
+            dot_rows2<8>(ns, j, V, i0, i1, w0, w1, part);
             if (pass == 1) {
 #pragma unroll
               for (int k = 1; k < GM_MAXM + 1; ++k)
-                if (k == j + 1) part[k] += wi * wi;
+                if (k == j + 1) part[k] += w0 * w0 + w1 * w1;
             }
           }
           // the second pass carries the squared norm of W as value j+1
@@ -441,7 +535,14 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
             for (int k = 0; k <= j; ++k) hh += sh.hv[k] * sh.hv[k];
             ww = sh.hv[j + 1] - hh;
           }
-          for (int i = r0 + tid; i < r1; i += GC_THREADS) Wv[i] -= comb_rows<8>(ns, j, V, i, sh.hv);
+          for (int i0 = r0 + tid; i0 < r1; i0 += 2 * GC_THREADS) {
+            const bool has1 = i0 + GC_THREADS < r1;
+            const int i1 = has1 ? i0 + GC_THREADS : i0;
+            double c0, c1;
+            comb_rows2<8>(ns, j, V, i0, i1, sh.hv, c0, c1);
+            Wv[i0] -= c0;
+            if (has1) Wv[i1] -= c1;
+          }
         }
         const double hn = ww >= 0.0 ? sqrt(ww) : (ww < 0.0 ? 0.0 : ww);  // NaN stays NaN
         if (hn > 0.0)
