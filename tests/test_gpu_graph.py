@@ -26,10 +26,17 @@ def _rel(a, b):
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
-@pytest.mark.parametrize("case", ["direct_l2", "fmm_l3", "fmm_geo11"])
+@pytest.mark.parametrize("case", ["direct_l2", "fmm_l3", "fmm_geo11", "fmm_l3_f32_direct"])
 def test_graph_replay_matches_eager(case):
     P = _P()
-    if case == "direct_l2":
+    force = None
+    if case == "fmm_l3_f32_direct":
+        # FP32 products on an LDS-free tile (P = 256): the moment conversion and
+        # the tile are captured too
+        xyz, tri = synth.icosphere(3)
+        kw, d, bc, nt = dict(use_fmm=1, depth=3, p_s=4, p_t=4, m2l_prec=P.M2L_FP32), 2, P.NEUMANN, 40
+        force = 2 * 9
+    elif case == "direct_l2":
         xyz, tri = synth.icosphere(2)
         kw, d, bc, nt = dict(use_fmm=0), 1, P.DIRICHLET, 40
     elif case == "fmm_l3":
@@ -41,8 +48,12 @@ def test_graph_replay_matches_eager(case):
     dt = synth.mean_edge_length(xyz, tri)
     inc = synth.incident_params(xyz, seed=4)
     eager = P.TDBEM(xyz, tri, 1.0, dt, d, P.BMBIE, bc, nt_max=nt, **kw)
-    xe, re_ = eager.run(nt, inc=inc)
     g = P.TDBEM(xyz, tri, 1.0, dt, d, P.BMBIE, bc, nt_max=nt, graph=True, stream=torch.cuda.Stream(), **kw)
+    if force is not None:
+        for n in (1, 2):
+            eager.set_m2l_variant(n, force)
+            g.set_m2l_variant(n, force)
+    xe, re_ = eager.run(nt, inc=inc)
     tol = 1e-9 if case == "fmm_geo11" else 0.0
     for rep in range(3):
         g.reset()
