@@ -264,7 +264,7 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 5}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(value is the single-GPU throughput); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
