@@ -17,14 +17,17 @@
 //
 // Per sample beta (after the solve of step beta+1):
 //   P2M        leaf moments of the current source interval       (HBM-bound, small)
-//   at the end of a level's source interval k:
+//   at the end of a level's source interval k (every level ending then together):
+//     M2M      child -> parent re-interpolation (parent-centric, no atomics), first:
+//              it only reads the children's moments
 //     M2L      offset-batched dense products: for every interaction pair,
 //              [U_{k+1,k}; ...; U_{k+mu+1,k}; U^{(1)}; ...; U^{(d)}] M_k(S)
-//              written to a per-pair staging buffer                   (dense contraction)
-//     reduce   per target cell: near-future locals L_{k+l} += ..., then the
-//              recurrence of Algorithm 1 (eqs. m2l_expand_rec1, m2l_rec,
-//              m2l_expand_rec2) fused in the same pass                  (HBM-bound)
-//     M2M      child -> parent re-interpolation (parent-centric, no atomics)
+//              written to a per-pair staging buffer, one launch for all those
+//              levels (FP32 contexts convert the moments to FP32 first) (dense contraction)
+//     reduce   per target cell: near-future locals L_{k+l} += ..., and the
+//              derivative products                                      (HBM-bound)
+//     recurrence of Algorithm 1 (eqs. m2l_expand_rec1, m2l_rec, m2l_expand_rec2)
+//              per (cell, coefficient)
 //   L2L        at the start of a parent's target interval, parent -> child
 //   L2P        at each target step: field or Burton-Miller operator of it
 #include "internal.h"
