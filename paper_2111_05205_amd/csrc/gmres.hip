@@ -17,8 +17,9 @@
 // global memory and a grid barrier (the barrier orders memory at device scope);
 // every workgroup then sums the partials in the same order, so the Hessenberg
 // matrix, Givens rotations and stopping decision are bitwise identical in all
-// workgroups.  The second orthogonalisation pass also carries |W|^2, so an
-// Arnoldi step takes 3 barriers.
+// workgroups.  Each orthogonalisation pass also carries |W|^2, and a second
+// pass runs only when the first removes more than 99% of |W|^2, so an Arnoldi
+// step usually takes 2 barriers.
 #include "internal.h"
 
 #include <hip/hip_cooperative_groups.h>
@@ -510,6 +511,14 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
           Wv[i0] = y0;
           if (has1) Wv[i1] = y1;
         }
+        // Classical Gram-Schmidt, repeated only when the first pass cancels
+        // badly (the test of Daniel, Gragg, Kaufman and Stewart with eta = 0.1):
+        // each pass's reduction also carries |W|^2 (value j+1), and
+        // |W - sum h_k V_k|^2 = |W|^2 - sum h_k^2 for orthonormal V_k.  If a pass
+        // keeps more than eta^2 of |W|^2, the orthogonality it leaves is within
+        // ~eps / eta and the difference is accurate to ~eps / eta^2; otherwise a
+        // second pass (whose h_k are at rounding level) follows.  Every workgroup
+        // holds the same sums, so all take the same branch.
         double ww = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
@@ -519,22 +528,16 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
             const int i1 = has1 ? i0 + GC_THREADS : i0;
             const double w0 = Wv[i0], w1 = has1 ? Wv[i1] : 0.0;
             dot_rows2<8>(ns, j, V, i0, i1, w0, w1, part);
-            if (pass == 1) {
 #pragma unroll
-              for (int k = 1; k < GM_MAXM + 1; ++k)
-                if (k == j + 1) part[k] += w0 * w0 + w1 * w1;
-            }
+            for (int k = 1; k < GM_MAXM + 1; ++k)
+              if (k == j + 1) part[k] += w0 * w0 + w1 * w1;
           }
-          // the second pass carries the squared norm of W as value j+1
-          grid_multi_sum(pass == 0 ? j + 1 : j + 2, part, gpart, flip, sh, grid);
+          grid_multi_sum(j + 2, part, gpart, flip, sh, grid);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
-          if (pass == 1) {
-            // |W - sum h_k V_k|^2 = |W|^2 - sum h_k^2 for orthonormal V_k; after the
-            // first pass the h_k are at rounding level, so nothing cancels
-            double hh = 0.0;
-            for (int k = 0; k <= j; ++k) hh += sh.hv[k] * sh.hv[k];
-            ww = sh.hv[j + 1] - hh;
-          }
+          double hh = 0.0;
+          for (int k = 0; k <= j; ++k) hh += sh.hv[k] * sh.hv[k];
+          const double w2 = sh.hv[j + 1];
+          ww = w2 - hh;
           for (int i0 = r0 + tid; i0 < r1; i0 += 2 * GC_THREADS) {
             const bool has1 = i0 + GC_THREADS < r1;
             const int i1 = has1 ? i0 + GC_THREADS : i0;
@@ -543,6 +546,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
             Wv[i0] -= c0;
             if (has1) Wv[i1] -= c1;
           }
+          if (ww >= 0.01 * w2) break;
         }
         const double hn = ww >= 0.0 ? sqrt(ww) : (ww < 0.0 ? 0.0 : ww);  // NaN stays NaN
         if (hn > 0.0)
