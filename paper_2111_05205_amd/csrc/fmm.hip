@@ -23,7 +23,7 @@
 //     M2L      offset-batched dense products: for every interaction pair,
 //              [U_{k+1,k}; ...; U_{k+mu+1,k}; U^{(1)}; ...; U^{(d)}] M_k(S)
 //              written to a per-pair staging buffer, one launch for all those
-//              levels (FP32 contexts convert the moments to FP32 first) (dense contraction)
+//              levels (FP32 contexts: P2M and M2M also keep an FP32 copy of the moments)
 //     reduce   per target cell: near-future locals L_{k+l} += ..., and the
 //              derivative products                                      (HBM-bound)
 //     recurrence of Algorithm 1 (eqs. m2l_expand_rec1, m2l_rec, m2l_expand_rec2)
@@ -66,7 +66,7 @@ struct FmmLevel {
   DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
   DevBuf<float> d_U32, d_stage32;           // FP32 operators and staging (mixed-precision M2L)
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_stage, d_dp;
-  DevBuf<float> d_mom32;                    // FP32 copy of the moments at an interval end (FP32 M2L)
+  DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
 };
 
 struct Fmm {
@@ -259,7 +259,8 @@ struct TimeWeights { double w[MAXP]; double dw[MAXP]; };
 __global__ void p2m_kernel(int Ps, int pt, double Cd, TimeWeights tw, const int32_t* __restrict__ leaf_ptr,
                            const int32_t* __restrict__ leaf_elems, const double* __restrict__ A,
                            const double* __restrict__ B, const double* __restrict__ tau,
-                           const double* __restrict__ sig, double* __restrict__ mom) {
+                           const double* __restrict__ sig, double* __restrict__ mom,
+                           float* __restrict__ mom32) {
   const int S = blockIdx.x;
   const int P = Ps * pt;
   for (int b = threadIdx.x; b < Ps; b += blockDim.x) {
@@ -269,7 +270,12 @@ __global__ void p2m_kernel(int Ps, int pt, double Cd, TimeWeights tw, const int3
       acc += A[(int64_t)e * Ps + b] * tau[e] - B[(int64_t)e * Ps + b] * sig[e];
     }
     acc *= Cd;
-    for (int n = 0; n < pt; ++n) mom[(int64_t)S * P + b + Ps * n] += acc * tw.w[n];
+    for (int n = 0; n < pt; ++n) {
+      const int64_t ix = (int64_t)S * P + b + Ps * n;
+      const double v = mom[ix] + acc * tw.w[n];
+      mom[ix] = v;
+      if (mom32) mom32[ix] = (float)v;  // FP32 products read this copy; the last write of an interval is final
+    }
   }
 }
 
@@ -303,7 +309,8 @@ __device__ double* apply_sep(double* buf0, double* buf1, int ps, int pt, const d
 __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__ child_ptr,
                            const int32_t* __restrict__ child, const int32_t* __restrict__ octant,
                            const double* __restrict__ S, const double* __restrict__ T,
-                           const double* __restrict__ mom_c, double* __restrict__ mom_p) {
+                           const double* __restrict__ mom_c, double* __restrict__ mom_p,
+                           float* __restrict__ mom32_p) {
   extern __shared__ double sm[];
   const int Ps = ps * ps * ps, P = Ps * pt;
   double* b0 = sm;
@@ -329,7 +336,11 @@ __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__
   }
   for (int q = 0; q < per; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    if (idx < P) mom_p[(int64_t)p * P + idx] += acc[q];
+    if (idx < P) {
+      const double v = mom_p[(int64_t)p * P + idx] + acc[q];
+      mom_p[(int64_t)p * P + idx] = v;
+      if (mom32_p) mom32_p[(int64_t)p * P + idx] = (float)v;
+    }
   }
 }
 
@@ -1457,10 +1468,6 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
-}
 
 static int sep_threads(int P) { return std::min(1024, ((P + 63) / 64) * 64); }
 
@@ -1483,7 +1490,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     FmmLevel& L = f->lev[D];
     p2m_kernel<<<L.ncell, ((f->Ps + 63) / 64) * 64, 0, st>>>(f->Ps, f->pt, f->Cd, tw, f->d_leaf_ptr.p,
                                                               f->d_leaf_elems.p, f->d_A.p, f->d_B.p, f->d_tau.p,
-                                                              f->d_sig.p, L.d_mom.p);
+                                                              f->d_sig.p, L.d_mom.p, L.d_mom32.p);
     TDBEM_HIP(hipGetLastError());
   }
   delete p2m_scope;
@@ -1510,19 +1517,8 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
       FmmLevel& Pl = f->lev[l - 1];
       ProfScope ps(ctx, K_M2M);
       m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
-                                                         L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p);
+                                                         L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p, Pl.d_mom32.p);
       TDBEM_HIP(hipGetLastError());
-    }
-    if (f->f32) {
-      // the FP32 moments that the LDS-free FP32 tiles read
-      ProfScope ps(ctx, K_OTHER);
-      for (int l = D; l > D - ndue && l >= 2; --l) {
-        FmmLevel& L = f->lev[l];
-        if (L.npair == 0) continue;
-        to_f32_kernel<<<(unsigned)((L.d_mom.n + 255) / 256), 256, 0, st>>>(L.d_mom.p, L.d_mom32.p,
-                                                                           (int64_t)L.d_mom.n);
-        TDBEM_HIP(hipGetLastError());
-      }
     }
     {
       ProfScope ps(ctx, K_M2L_GEMM);
