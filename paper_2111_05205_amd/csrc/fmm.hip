@@ -256,7 +256,9 @@ __global__ void densities_kernel(int ns, int beta, int d, BWeights bw, const dou
 struct TimeWeights { double w[MAXP]; double dw[MAXP]; };
 
 // P2M of one sample into the leaf moments: one block per leaf, thread per spatial node.
-__global__ void p2m_kernel(int Ps, int pt, double Cd, TimeWeights tw, const int32_t* __restrict__ leaf_ptr,
+// first: this sample opens the leaf's source interval, so the moments are
+// assigned rather than accumulated (no clearing pass between intervals).
+__global__ void p2m_kernel(int Ps, int pt, int first, double Cd, TimeWeights tw, const int32_t* __restrict__ leaf_ptr,
                            const int32_t* __restrict__ leaf_elems, const double* __restrict__ A,
                            const double* __restrict__ B, const double* __restrict__ tau,
                            const double* __restrict__ sig, double* __restrict__ mom,
@@ -272,7 +274,7 @@ __global__ void p2m_kernel(int Ps, int pt, double Cd, TimeWeights tw, const int3
     acc *= Cd;
     for (int n = 0; n < pt; ++n) {
       const int64_t ix = (int64_t)S * P + b + Ps * n;
-      const double v = mom[ix] + acc * tw.w[n];
+      const double v = (first ? 0.0 : mom[ix]) + acc * tw.w[n];
       mom[ix] = v;
       if (mom32) mom32[ix] = (float)v;  // FP32 products read this copy; the last write of an interval is final
     }
@@ -306,6 +308,7 @@ __device__ double* apply_sep(double* buf0, double* buf1, int ps, int pt, const d
 
 // M2M: one block per parent cell; sums its children's re-interpolated moments.
 // S[side][parent a][child b] (side 0: lower half, 1: upper), T likewise for time.
+// half 0 (the first child interval of the parent's) assigns, half 1 accumulates.
 __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__ child_ptr,
                            const int32_t* __restrict__ child, const int32_t* __restrict__ octant,
                            const double* __restrict__ S, const double* __restrict__ T,
@@ -337,7 +340,7 @@ __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__
   for (int q = 0; q < per; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
     if (idx < P) {
-      const double v = mom_p[(int64_t)p * P + idx] + acc[q];
+      const double v = (half == 0 ? 0.0 : mom_p[(int64_t)p * P + idx]) + acc[q];
       mom_p[(int64_t)p * P + idx] = v;
       if (mom32_p) mom32_p[(int64_t)p * P + idx] = (float)v;
     }
@@ -1463,10 +1466,6 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out) {
   TDBEM_HIP(hipGetLastError());
 }
 
-__global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
 
 
 static int sep_threads(int P) { return std::min(1024, ((P + 63) / 64) * 64); }
@@ -1488,7 +1487,8 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     const double center = (k * (double)Ml - 1.0 + (Ml - 1) / 2.0) * ctx->dt;
     TimeWeights tw = time_weights(f, (beta * ctx->dt - center) / ht, ht);
     FmmLevel& L = f->lev[D];
-    p2m_kernel<<<L.ncell, ((f->Ps + 63) / 64) * 64, 0, st>>>(f->Ps, f->pt, f->Cd, tw, f->d_leaf_ptr.p,
+    const int first = (beta + 1) % Ml == 0;
+    p2m_kernel<<<L.ncell, ((f->Ps + 63) / 64) * 64, 0, st>>>(f->Ps, f->pt, first, f->Cd, tw, f->d_leaf_ptr.p,
                                                               f->d_leaf_elems.p, f->d_A.p, f->d_B.p, f->d_tau.p,
                                                               f->d_sig.p, L.d_mom.p, L.d_mom32.p);
     TDBEM_HIP(hipGetLastError());
@@ -1546,9 +1546,6 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
                                                                                L.d_aux.p);
         TDBEM_HIP(hipGetLastError());
       }
-      // a kernel, not a memset node, so that a captured march replays correctly
-      fill_zero_kernel<<<(unsigned)((L.d_mom.n + 255) / 256), 256, 0, st>>>(L.d_mom.p, (int64_t)L.d_mom.n);
-      TDBEM_HIP(hipGetLastError());
     }
   }
   // L2L for the target intervals that start at the next step, top-down
