@@ -370,10 +370,11 @@ __global__ void diag_kernel(int ns, const int32_t* __restrict__ ap, const int32_
 __global__ __launch_bounds__(1024) void mlp_scale_kernel(int ns, int beta, const double* __restrict__ h,
                                                          const double* __restrict__ b,
                                                          const double* __restrict__ diag, double* __restrict__ s) {
-  __shared__ double sh[1024];
+  __shared__ double sh[16];
   const int tid = threadIdx.x;
   double acc = 0.0;
-  for (int i = tid; i < ns; i += 1024) {
+#pragma unroll 4
+  for (int i = tid; i < ns; i += 1024) {  // unrolled: several rows' loads in flight
     for (int k = 1; k <= 4; ++k) {
       const double x = h[(int64_t)(beta - k) * ns + i];
       acc += x * x;
@@ -381,13 +382,14 @@ __global__ __launch_bounds__(1024) void mlp_scale_kernel(int ns, int beta, const
     const double bj = b[i] / diag[i];
     acc += bj * bj;
   }
-  sh[tid] = acc;
+  for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if ((tid & 63) == 0) sh[tid >> 6] = acc;
   __syncthreads();
-  for (int st = 512; st > 0; st >>= 1) {
-    if (tid < st) sh[tid] += sh[tid + st];
-    __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += sh[w];
+    s[0] = sqrt(t / (5.0 * ns));
   }
-  if (tid == 0) s[0] = sqrt(sh[0] / (5.0 * ns));
 }
 
 struct FeatGeo { double inv_h2, cen[3], inv_r; };
