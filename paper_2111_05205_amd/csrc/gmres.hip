@@ -6,8 +6,8 @@
 // threads (16 wavefronts) per step: the Krylov basis lives in global memory
 // (L2-resident for the sizes this kernel serves), the Hessenberg matrix,
 // Givens rotations and reduction scratch in LDS, and no host round trip is
-// needed.  Orthogonalisation is classical Gram-Schmidt applied twice (CGS2),
-// so each Arnoldi step needs two fused multi-dot reductions.  The products
+// needed.  Orthogonalisation is classical Gram-Schmidt, applied a second time
+// only when the first pass removes more than 99% of |W|^2.  The products
 // A v read a copy of A padded to the longest row and stored column-major, so
 // the loads of a row are independent and consecutive rows are adjacent.
 //
@@ -228,15 +228,33 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, int W, const 
         double* Wv = V + (size_t)(j + 1) * ns;
         spmv(ns, W, ec, ev, Vj, Wv);
         __syncthreads();
+        // classical Gram-Schmidt with a second pass only when the first removes
+        // more than 99% of |W|^2 (as in the cooperative kernel)
+        {
+          double w2 = 0.0;
+          for (int i = tid; i < ns; i += GM_THREADS) w2 += Wv[i] * Wv[i];
+          w2 = block_sum(w2, sh);
+          if (tid == 0) sh.scal[3] = w2;  // |W|^2, read by thread 0 below
+        }
         for (int pass = 0; pass < 2; ++pass) {
           multi_dot(ns, j, V, Wv, sh);
           if (tid <= j) sh.H[tid][j] = (pass == 0 ? 0.0 : sh.H[tid][j]) + sh.hv[tid];
+          if (tid == 0) {
+            double hh = 0.0;
+            for (int k = 0; k <= j; ++k) hh += sh.hv[k] * sh.hv[k];
+            const double ww = sh.scal[3] - hh;
+            sh.scal[2] = (pass == 0 && ww >= 0.01 * sh.scal[3]) ? sqrt(ww) : -1.0;
+          }
           for (int i = tid; i < ns; i += GM_THREADS) Wv[i] -= comb_rows<4>(ns, j, V, i, sh.hv);
           __syncthreads();
+          if (sh.scal[2] >= 0.0) break;
         }
-        double ww = 0.0;
-        for (int i = tid; i < ns; i += GM_THREADS) ww += Wv[i] * Wv[i];
-        const double hn = sqrt(block_sum(ww, sh));
+        double hn = sh.scal[2];
+        if (!(hn >= 0.0)) {
+          double ww = 0.0;
+          for (int i = tid; i < ns; i += GM_THREADS) ww += Wv[i] * Wv[i];
+          hn = sqrt(block_sum(ww, sh));
+        }
         if (hn > 0.0)
           for (int i = tid; i < ns; i += GM_THREADS) Wv[i] /= hn;
         if (tid == 0) {
