@@ -354,8 +354,7 @@ class ReferenceFMM:
                 self.mom_done[lev][kk] = Mk.copy()
                 self.local_cache = {}
             if lev > 2:
-                half = -1 if kk % 2 == 0 else 1
-                self._m2m(lev, Mk, half)
+                self._m2m(lev, Mk, kk)
             self.mom_cur[lev] = np.zeros_like(Mk)
 
     def _reinterp(self, lev, X, half, transpose):
@@ -382,7 +381,10 @@ class ReferenceFMM:
                     out[sel] = T.reshape(sel.size, -1)
         return out
 
-    def _m2m(self, lev, Mk, half):
+    def _m2m(self, lev, Mk, k):
+        """Moments of source interval k at level lev, re-interpolated into the parents' moments of
+        interval k // 2 (k even: the first half of the parent interval)."""
+        half = -1 if k % 2 == 0 else 1
         np.add.at(self.mom_cur[lev - 1], self.parent[lev], self._reinterp(lev, Mk, half, False))
 
     def _algorithm1(self, lev, k, Mk):

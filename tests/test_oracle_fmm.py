@@ -146,17 +146,25 @@ def test_algorithm1_equals_naive_m2l(fmm3, d, bie):
     assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
 
 
-def test_fmm_approximates_direct_history_sum(fmm3):
-    """Near + far approximates the direct history sum of a physical (marched) history.
-    The interpolation error is dominated by the time gaps in which the wavefront crosses a
-    cluster pair, so only a loose bound holds at p = 3 (the paper's own FMM differs from its
-    conventional solution by >= 1e-2)."""
-    xyz, tri, dt, R = fmm3
+@pytest.fixture(scope="module")
+def marched(fmm3):
+    """A physical history: 40 steps of the direct BMBIE march (d = 2, Neumann) on the fixture's
+    mesh, and the direct history sum at step 32."""
+    xyz, tri, dt, _ = fmm3
     nt = 40
     m = mot.DirectMOT(xyz, tri, 1.0, dt, 2, 1, 1)
     inc = synth.incident_params(xyz, seed=0)
     u, q = m.run(nt, mot.incident(m.geom, inc, 1.0, dt, nt, 1))
-    ref = m.history_rhs(32, u, q)
+    return u, q, m.history_rhs(32, u, q)
+
+
+def test_fmm_approximates_direct_history_sum(fmm3, marched):
+    """Near + far approximates the direct history sum of a physical (marched) history.
+    The interpolation error is dominated by the time gaps in which the wavefront crosses a
+    cluster pair, so only a loose bound holds at p = 3 (the paper's own FMM differs from its
+    conventional solution by >= 1e-2)."""
+    R = fmm3[3]
+    u, q, ref = marched
     err = np.linalg.norm(R.history_rhs(32, u, q) - ref) / np.linalg.norm(ref)
     assert err < 0.1, err
 
@@ -197,3 +205,163 @@ def test_kernel_interpolation_converges_after_the_wavefront():
     for o in [(3, 1, 0), (2, 2, 2)]:
         e = [_interp_error(o, 13, p) for p in (3, 4, 5)]
         assert e[0] > 5 * e[1] > 25 * e[2], (o, e)
+
+
+def _basis_at(R, lev, center, half_side, t_center, y, s):
+    """Basis functions of a space-time box evaluated at one point (y, s): the moments of a unit
+    point source there, or the weights that evaluate a local at a target point.  Index
+    a1 + p_s (a2 + p_s a3) + P_s m, a1 along x."""
+    l = [F.lagrange(R.om_s, [(y[q] - center[q]) / half_side])[0] for q in range(3)]
+    space = np.einsum("k,j,i->kji", l[2], l[1], l[0]).reshape(-1)
+    lt = F.lagrange(R.om_t, [(s - t_center) / R.ht(lev)])[0]
+    return (lt[:, None] * space[None, :]).reshape(-1)
+
+
+def _m2m_error(R, seed=3):
+    """M2M (Section 4) re-interpolates polynomials of degree < p exactly, so the moments of a
+    point source in a child box and interval k become the parent box's basis at that point, in
+    the parent interval k // 2.  Returns the largest deviation."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for lev in range(3, R.D + 1):
+        for ci in rng.choice(len(R.cells[lev]), 4, replace=False):
+            pi = R.parent[lev][ci]
+            cc = R.cell_center(lev, R.cells[lev][ci])
+            pc = R.cell_center(lev - 1, R.cells[lev - 1][pi])
+            for k in (6, 7):
+                y = cc + R.hb(lev) * rng.uniform(-1, 1, 3)
+                s = R.src_center(lev, k) + R.ht(lev) * rng.uniform(-1, 1)
+                X = np.zeros((len(R.cells[lev]), R.P))
+                X[ci] = _basis_at(R, lev, cc, R.hb(lev), R.src_center(lev, k), y, s)
+                R.reset()
+                R._m2m(lev, X, k)
+                want = _basis_at(R, lev - 1, pc, R.hb(lev - 1), R.src_center(lev - 1, k // 2), y, s)
+                worst = max(worst, np.abs(R.mom_cur[lev - 1][pi] - want).max())
+    return worst
+
+
+def _l2l_error(R, seed=4):
+    """L2L (Section 4): a parent's local, re-interpolated onto a child cell's two target
+    intervals, takes the same value at every point of the child box (exact for the polynomial
+    the local represents).  Returns the largest deviation relative to the local's size."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for lev in range(3, R.D + 1):
+        G = rng.standard_normal((len(R.cells[lev - 1]), R.P))
+        for kp in (5, 6):
+            child = R._l2l_apply(lev - 1, G, kp)
+            for ci in rng.choice(len(R.cells[lev]), 4, replace=False):
+                pi = R.parent[lev][ci]
+                cc = R.cell_center(lev, R.cells[lev][ci])
+                pc = R.cell_center(lev - 1, R.cells[lev - 1][pi])
+                for kc in (2 * kp, 2 * kp + 1):
+                    x = cc + R.hs(lev) * rng.uniform(-1, 1, 3)
+                    t = R.tgt_center(lev, kc) + R.ht(lev) * rng.uniform(-1, 1)
+                    got = child[kc][ci] @ _basis_at(R, lev, cc, R.hs(lev), R.tgt_center(lev, kc), x, t)
+                    want = G[pi] @ _basis_at(R, lev - 1, pc, R.hs(lev - 1), R.tgt_center(lev - 1, kp), x, t)
+                    worst = max(worst, abs(got - want) / np.abs(G[pi]).max())
+    return worst
+
+
+def test_m2m_maps_point_moments_to_parent_basis(fmm3):
+    assert _m2m_error(fmm3[3]) < 1e-12
+
+
+def test_m2m_exact_with_grown_source_boxes():
+    xyz, tri = synth.icosphere(2)
+    R = F.ReferenceFMM(xyz, tri, 1.0, 0.02, 1, 0, 3, 3, 2, src_ext=0.03)
+    assert R.hb(3) > R.hs(3)
+    assert _m2m_error(R, seed=8) < 1e-12
+
+
+def test_l2l_preserves_the_local_field(fmm3):
+    assert _l2l_error(fmm3[3]) < 1e-12
+
+
+# Planted mistakes: each must make one of the pins above fail.
+def _recurrence_error(mu=2, d=3):
+    rng = np.random.default_rng(11)
+    T, K = 0.61, 10
+    near, D, snap = _abstract_alg1(mu, d, T, K, rng)
+    worst = 0.0
+    for k in range(K):
+        for l in range(k + 1, k + mu + 3):
+            want = np.zeros(near.shape[2])
+            for kk in range(0, k + 1):
+                if l <= kk + mu + 1:
+                    want += near[kk, l - kk]
+                else:
+                    want += sum(D[kk, p] * (l - kk - mu - 1) ** p * T ** p for p in range(d + 1))
+            worst = max(worst, np.abs(snap[(k, l)] - want).max() / np.abs(want).max())
+    return worst
+
+
+def _plant_cmp_sign(mp):
+    orig = F.cmp_coef
+    mp.setattr(F, "cmp_coef", lambda p, m, k: orig(p, m, k) * (-1) ** m)
+
+
+def _plant_cmp_index(mp):
+    orig = F.cmp_coef
+    mp.setattr(F, "cmp_coef", lambda p, m, k: orig(p, m, k - 1))
+
+
+def _plant_aux_not_updated(mp):
+    orig = F.recurrence
+
+    def rec(k, mu, d, T, ring, R, Lp, aux, Dp):
+        keep = aux.copy()
+        orig(k, mu, d, T, ring, R, Lp, aux, Dp)
+        aux[...] = keep
+    mp.setattr(F, "recurrence", rec)
+
+
+def _plant_top_derivative_dropped(mp):
+    orig = F.recurrence
+
+    def rec(k, mu, d, T, ring, R, Lp, aux, Dp):
+        Dp = Dp.copy()
+        Dp[d] = 0.0
+        orig(k, mu, d, T, ring, R, Lp, aux, Dp)
+    mp.setattr(F, "recurrence", rec)
+
+
+@pytest.mark.parametrize("plant", [_plant_cmp_sign, _plant_cmp_index, _plant_aux_not_updated,
+                                   _plant_top_derivative_dropped])
+def test_planted_recurrence_mistakes_fail_the_naive_sum_pin(monkeypatch, plant):
+    assert _recurrence_error() < 1e-11
+    plant(monkeypatch)
+    assert _recurrence_error() > 1e-3
+
+
+def test_planted_translation_mistakes_fail_their_pins(fmm3, monkeypatch):
+    R = fmm3[3]
+    orig_m2m, orig_l2l = F.ReferenceFMM._m2m, F.ReferenceFMM._l2l_apply
+    # M2M into the wrong half of the parent interval
+    monkeypatch.setattr(F.ReferenceFMM, "_m2m", lambda self, lev, Mk, k: orig_m2m(self, lev, Mk, k + 1))
+    assert _m2m_error(R) > 1e-3
+    monkeypatch.setattr(F.ReferenceFMM, "_m2m", orig_m2m)
+    # transposed spatial re-interpolation operator
+    saved = {lev: dict(m) for lev, m in R.Msp.items()}
+    for lev in R.Msp:
+        R.Msp[lev] = {sd: m.T.copy() for sd, m in R.Msp[lev].items()}
+    try:
+        assert _m2m_error(R) > 1e-3
+    finally:
+        R.Msp.update(saved)
+    assert _m2m_error(R) < 1e-12
+    # L2L results handed to the wrong child interval
+    monkeypatch.setattr(F.ReferenceFMM, "_l2l_apply",
+                        lambda self, lp, G, kp: {k ^ 1: v for k, v in orig_l2l(self, lp, G, kp).items()})
+    assert _l2l_error(R) > 1e-3
+
+
+def test_planted_transposed_m2l_operator_fails_the_direct_pin(fmm3, marched, monkeypatch):
+    R = fmm3[3]
+    u, q, ref = marched
+    orig = F.ReferenceFMM.m2l_matrix
+    monkeypatch.setattr(F.ReferenceFMM, "m2l_matrix", lambda self, *a, **kw: orig(self, *a, **kw).T)
+    R._mats = {}
+    err = np.linalg.norm(R.history_rhs(32, u, q) - ref) / np.linalg.norm(ref)
+    R._mats = {}
+    assert err > 0.1, err
