@@ -126,11 +126,42 @@ def _extinction_residual(level, d, bie):
     return np.linalg.norm(res) / np.linalg.norm(F)
 
 
+def _extinction_converges(d, bie):
+    r1, r2, r3 = (_extinction_residual(level, d, bie) for level in (1, 2, 3))
+    return r2 < r1 and r3 < r2 and r3 < 0.5 and r2 / r3 > 1.5, (r1, r2, r3)
+
+
 @pytest.mark.parametrize("d,bie", [(1, 0), (1, 1), (2, 1)])
 def test_extinction_consistency(d, bie):
     """Traces of a field regular inside the scatterer satisfy the discrete equation
     up to a discretisation residual that shrinks under refinement."""
-    r1 = _extinction_residual(1, d, bie)
-    r2 = _extinction_residual(2, d, bie)
-    r3 = _extinction_residual(3, d, bie)
-    assert r2 < r1 and r3 < r2 and r3 < 0.5 and r2 / r3 > 1.5, (r1, r2, r3)
+    ok, r = _extinction_converges(d, bie)
+    assert ok, r
+
+
+def _plant_w_sign(m):
+    m.CW = {g: -X for g, X in m.CW.items()}
+
+
+def _plant_gap_shift(m):
+    for name in ("CU", "CW"):
+        C = getattr(m, name)
+        setattr(m, name, {g: C.get(g + 1, 0 * C[g]) for g in C})
+
+
+def _plant_u_w_swapped(m):
+    m.CU, m.CW = m.CW, m.CU
+
+
+@pytest.mark.parametrize("plant", [_plant_w_sign, _plant_gap_shift, _plant_u_w_swapped])
+def test_planted_march_mistakes_fail_the_extinction_pin(monkeypatch, plant):
+    """A sign error on the double-layer terms, coefficients taken one time gap late, or
+    the two families exchanged each stop the residual from converging."""
+    orig = mot.DirectMOT.__init__
+
+    def init(self, *a, **kw):
+        orig(self, *a, **kw)
+        plant(self)
+    monkeypatch.setattr(mot.DirectMOT, "__init__", init)
+    ok, r = _extinction_converges(2, mot.BMBIE)
+    assert not ok, r
