@@ -187,3 +187,71 @@ def test_extrapolation_exact_on_quadratics_only():
     cub = t ** 3 * np.ones(5)
     # third difference of t^3 is 6: the parabola through three points misses by exactly 6
     assert np.allclose(cub[6] - mlp.extrapolate(cub, 6), 6.0)
+
+
+# Planted mistakes: each must make one of the pins above fail.
+def _plant_bf16_truncates(mp):
+    def trunc(x):
+        m, e = np.frexp(np.asarray(x, dtype=np.float64))
+        return np.ldexp(np.trunc(m * 256.0), e - 8)
+    mp.setattr(mlp, "bf16", trunc)
+
+
+def _plant_bf16_ties_away(mp):
+    def away(x):
+        m, e = np.frexp(np.asarray(x, dtype=np.float64))
+        return np.ldexp(np.sign(m) * np.floor(np.abs(m) * 256.0 + 0.5), e - 8)
+    mp.setattr(mlp, "bf16", away)
+
+
+def _plant_backward_untransposed(mp):
+    orig = mlp.backward
+
+    def bwd(cache, dy):
+        r = cache["r"]
+        flip = lambda v: r(v).T if np.ndim(v) == 2 and v.shape[0] == v.shape[1] else r(v)
+        return orig({**cache, "r": flip}, dy)
+    mp.setattr(mlp, "backward", bwd)
+
+
+def _plant_backward_without_relu_masks(mp):
+    orig = mlp.backward
+
+    def bwd(cache, dy):
+        return orig({**cache, **{k: np.ones_like(cache[k]) for k in ("z1", "z2", "z3")}}, dy)
+    mp.setattr(mlp, "backward", bwd)
+
+
+def _plant_output_bias_dropped(mp):
+    orig = mlp.forward
+
+    def fwd(p, feat, rounding=True):
+        y, cache = orig(p, feat, rounding)
+        return y - mlp.unpack(np.asarray(p, dtype=np.float64))["b4"][0], cache
+    mp.setattr(mlp, "forward", fwd)
+
+
+def _plant_mse_half_derivative(mp):
+    orig = mlp.mse
+    mp.setattr(mlp, "mse", lambda y, t: (orig(y, t)[0], orig(y, t)[1] / 2))
+
+
+def _plant_adam_without_bias_correction(mp):
+    orig = mlp.adam
+    mp.setattr(mlp, "adam", lambda p, g, m, v, t, lr, **kw: orig(p, g, m, v, 10 ** 9, lr, **kw))
+
+
+@pytest.mark.parametrize("plant,pin", [
+    (_plant_bf16_truncates, test_bf16_matches_torch_conversion),
+    (_plant_bf16_ties_away, test_bf16_ties_to_even),
+    (_plant_backward_untransposed, test_backward_matches_finite_differences),
+    (_plant_backward_without_relu_masks, test_backward_matches_finite_differences),
+    (_plant_output_bias_dropped, test_one_hidden_layer_special_case_by_loops),
+    (_plant_mse_half_derivative, test_mse_derivative),
+    (_plant_adam_without_bias_correction, test_adam_first_step_closed_form_and_convergence),
+])
+def test_planted_mistakes_fail_a_pin(monkeypatch, plant, pin):
+    pin()
+    plant(monkeypatch)
+    with pytest.raises(AssertionError):
+        pin()
