@@ -31,3 +31,28 @@ def test_traffic_record_matches_the_m2l_source():
     else:
         assert bench.measured_traffic(1) is None
     assert bench.measured_traffic(0) is None  # FP64 products: no counter record
+
+
+def test_m2l_flop_count_equals_the_products_the_oracle_makes(monkeypatch):
+    """The roofline's numerator: bench.py's algorithmic M2L flops of a march (2 G P^2 per
+    interaction pair per completed source interval) equal the flops of the matrix products
+    the oracle's Algorithm 1 actually performs over the same march."""
+    import synth
+    from oracle import fmm as F
+    xyz, tri = synth.icosphere(2)
+    R = F.ReferenceFMM(xyz, tri, 1.0, 0.02, 2, 1, 3, 2, 2)
+    made = []
+    orig = F.ReferenceFMM.m2l_matrix
+
+    def counted(self, lev, o, gap=None, deriv=0):
+        made.append((lev, o))
+        return orig(self, lev, o, gap=gap, deriv=deriv)
+    monkeypatch.setattr(F.ReferenceFMM, "m2l_matrix", counted)
+    nt = 2 * R.M[2] + 3
+    u = synth.random_history(R.geom.ns, nt, seed=1)
+    q = synth.random_history(R.geom.ns, nt, seed=2)
+    R.history_rhs(nt, u, q)       # samples 0 .. nt-2, as in a march of nt steps
+    flops = sum(2 * R.P ** 2 * len(R.il_by_off[lev][o][0]) for lev, o in made)
+    info = {"il_pairs": {lev: len(R.il[lev]) for lev in range(2, R.D + 1)}}
+    want = bench.m2l_flops_per_march(info, nt, R.m_leaf, R.D, R.mu + 1 + R.d, R.P)
+    assert flops > 0 and flops == want, (flops, want)
