@@ -41,6 +41,9 @@
 extern "C" {
 #endif
 
+/* Opaque handle of one solver instance (created by tdbem_create, freed by tdbem_destroy). */
+struct tdbem_ctx;
+
 enum {
   TDBEM_OK = 0,
   TDBEM_E_INVAL = -1,         /* bad argument or mesh */

@@ -59,3 +59,41 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         assert "missing" in str(e)
     else:
         raise AssertionError("expected a RuntimeError")
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/tdbem.h compiles as C99 with warnings as errors, and a C program links
+    libtdbem.so and calls it (argument checks only; no device work)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        import pytest
+        pytest.skip("no C compiler")
+    from paper_2111_05205_amd import _native
+    lib = os.path.abspath(_native.LIB_PATH)
+    src = tmp_path / "use.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "tdbem.h"
+int main(void) {
+  tdbem_mesh m;
+  struct tdbem_ctx *ctx = 0;
+  memset(&m, 0, sizeof m);
+  int rc = tdbem_create(&m, 1.0, 0.1, 2, TDBEM_BMBIE, TDBEM_NEUMANN, NULL, NULL, &ctx);
+  printf("%d %s\n", rc, tdbem_last_error(NULL));
+  rc = tdbem_create(&m, 1.0, 0.1, 2, TDBEM_BMBIE, TDBEM_NEUMANN, NULL, NULL, NULL);
+  printf("%d\n", rc);
+  tdbem_destroy(NULL);
+  return ctx != 0;
+}
+''')
+    exe = tmp_path / "use"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", inc, str(src), lib,
+                    "-Wl,-rpath," + os.path.dirname(lib), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.splitlines()
+    assert lines[0].startswith(str(_native.E_INVAL) + " ") and "NULL" in lines[0]
+    assert lines[1] == str(_native.E_INVAL)
