@@ -97,3 +97,24 @@ int main(void) {
     lines = out.stdout.splitlines()
     assert lines[0].startswith(str(_native.E_INVAL) + " ") and "NULL" in lines[0]
     assert lines[1] == str(_native.E_INVAL)
+
+
+def test_binding_signatures_match_the_header():
+    """Every ctypes declaration in the binding has the header's parameter count, with a
+    pointer exactly where the prototype has one (a missing or integer-typed pointer
+    argument would truncate addresses)."""
+    from paper_2111_05205_amd import _native
+    L = _native.lib()
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "tdbem.h")).read(), flags=re.S)
+    protos = re.findall(r"\b(tdbem_[a-z_]+)\s*\(([^)]*)\)\s*;", src)
+    assert len(protos) == len(_declared())
+
+    def is_ptr(t):
+        return t in (ctypes.c_void_p, ctypes.c_char_p) or (isinstance(t, type) and issubclass(t, ctypes._Pointer))
+    for name, params in protos:
+        params = params.strip()
+        ps = [] if params in ("", "void") else [p.strip() for p in params.split(",")]
+        at = getattr(L, name).argtypes
+        assert at is not None, name
+        assert len(at) == len(ps), name
+        assert ["*" in p for p in ps] == [is_ptr(t) for t in at], name
