@@ -16,25 +16,29 @@ from . import build as _build
 _lib = None
 
 
+def configure(L):
+    """Declare the argument types of the oracle's C entry points on a loaded library."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lp = ctypes.POINTER(ctypes.c_long)
+    L.oracle_face_terms.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp]
+    L.oracle_elem.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
+    L.oracle_dist_range.argtypes = [dp, dp, dp, dp]
+    L.oracle_windows.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip]
+    L.oracle_fill.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip, lp, dp]
+    L.oracle_windows_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double,
+                                      ip, ip]
+    L.oracle_fill_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                                   ip, ip, lp, dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_build.OUT):
             _build.build()
-        L = ctypes.CDLL(_build.OUT)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int)
-        lp = ctypes.POINTER(ctypes.c_long)
-        L.oracle_face_terms.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp]
-        L.oracle_elem.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
-        L.oracle_dist_range.argtypes = [dp, dp, dp, dp]
-        L.oracle_windows.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip]
-        L.oracle_fill.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip, lp, dp]
-        L.oracle_windows_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double,
-                                          ip, ip]
-        L.oracle_fill_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, ctypes.c_int, ctypes.c_double,
-                                       ip, ip, lp, dp]
-        _lib = L
+        _lib = configure(ctypes.CDLL(_build.OUT))
     return _lib
 
 

@@ -6,6 +6,7 @@ derivatives, and exact identities of a closed polyhedron (solid angle 4 pi,
 divergence theorem).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -192,3 +193,58 @@ def test_gauss_identities_closed_surface():
         assert abs(tot2[1] - ((s / cdt) ** 2 - C2 * vol)) < 1e-9 * (s / cdt) ** 2
         ref = 2 * C2 * grad - 8 * math.pi * C2 * s
         assert abs(tot2[3] - ref) < 1e-9 * abs(8 * math.pi * C2 * s)
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each compiles a copy of the oracle's C source with one
+# plausible slip and checks that at least one of the pins above fails on it.
+
+_PLANTS = {
+    # App. B's local y taken with the opposite sign (the bracket is odd in y)
+    "edge_y_sign": ("double yl = -h;", "double yl = h;"),
+    # the foot-point term I_0 of the polar integral dropped
+    "no_foot_term": ("out[0] += theta * pospow(s - az, d + 1) / (d + 1);", "out[0] += 0.0;"),
+    # edges not clipped to the wavefront r <= s
+    "no_clip": ("double lo = x1 > -X ? x1 : -X, hi = x2 < X ? x2 : X;", "double lo = x1, hi = x2;"),
+    # double layer with the wrong sign (W = +C dPhi/dz)
+    "w_sign": ("out[1] = -C * f[1];", "out[1] = C * f[1];"),
+    # Burton-Miller time derivative with the wrong sign (+(1/c) d/dt)
+    "bm_time_sign": ("out[2] = C * (nn * f[1] + f[5] - f[3]);", "out[2] = C * (nn * f[1] + f[5] + f[3]);"),
+    # in-plane part of the adjoint double layer (tangential divergence theorem) dropped
+    "no_tangential_gradient": ("out[3] = -C * (nn * f[2] + f[6] - f[4]);", "out[3] = -C * (nn * f[2] - f[4]);"),
+}
+
+
+def _pins_d2():
+    """The fast pins at d = 2 (and d = 1 for the closed-surface identities)."""
+    test_U_bruteforce_no_clip(2)
+    test_U_bruteforce_clipped(2)
+    test_U_self_polar_bruteforce(2)
+    test_derivative_families_by_finite_differences(2)
+    test_self_pair_is_one_sided_limit(2)
+    test_gauss_identities_closed_surface()
+
+
+def _planted_lib(tmp_path, name):
+    import ctypes
+    import subprocess
+    from oracle import build as obuild
+    src = open(os.path.join(os.path.dirname(obuild.OUT), "..", "elemint.c")).read()
+    old, new = _PLANTS[name]
+    assert src.count(old) == 1, name
+    path = tmp_path / f"plant_{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"plant_{name}.so"
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", str(path), "-lm", "-o", str(so)], check=True)
+    return elemint.configure(ctypes.CDLL(str(so)))
+
+
+def test_unplanted_pins_pass():
+    _pins_d2()
+
+
+@pytest.mark.parametrize("name", sorted(_PLANTS))
+def test_planted_element_integral_mistakes_fail_a_pin(tmp_path, monkeypatch, name):
+    monkeypatch.setattr(elemint, "_lib", _planted_lib(tmp_path, name))
+    with pytest.raises(AssertionError):
+        _pins_d2()

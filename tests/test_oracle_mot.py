@@ -165,3 +165,105 @@ def test_planted_march_mistakes_fail_the_extinction_pin(monkeypatch, plant):
     monkeypatch.setattr(mot.DirectMOT, "__init__", init)
     ok, r = _extinction_converges(2, mot.BMBIE)
     assert not ok, r
+
+
+class _Pts:
+    """Stand-in for a Geometry: collocation points and paper normals only."""
+
+    def __init__(self, x, n):
+        self.x, self.n = np.ascontiguousarray(x), np.ascontiguousarray(n)
+
+
+def _seeded_points(seed=11, m=40):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, size=(m, 3))
+    n = rng.standard_normal((m, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return x, n
+
+
+@pytest.mark.parametrize("kind", ["raised_cos", "gauss_mod"])
+def test_bm_forcing_is_the_bm_operator_of_the_incident_field(kind):
+    """(d/dn - (1/c) d/dt) u_in by central differences of the OBIE forcing: in x along the
+    paper normal, and in t through the arrival shift rb (u_in depends on c t - k.x - rb)."""
+    x, n = _seeded_points()
+    c, dt, nt, h = 1.3, 0.05, 120, 1e-6
+    inc = {"kind": kind, "dir": np.array([0.6, -0.48, 0.64]), "f0": 1.0, "sigma": 0.5, "t0": 1.5, "rb": 0.2}
+    if kind == "raised_cos":
+        inc["sigma"] = 0.5       # pulse length Lambda
+    bm = mot.incident(_Pts(x, n), inc, c, dt, nt, mot.BMBIE)
+    up = mot.incident(_Pts(x + h * n, n), inc, c, dt, nt, mot.OBIE)
+    um = mot.incident(_Pts(x - h * n, n), inc, c, dt, nt, mot.OBIE)
+    early = dict(inc, rb=inc["rb"] - c * h)      # u_in(x, t + h)
+    late = dict(inc, rb=inc["rb"] + c * h)       # u_in(x, t - h)
+    ut = (mot.incident(_Pts(x, n), early, c, dt, nt, mot.OBIE)
+          - mot.incident(_Pts(x, n), late, c, dt, nt, mot.OBIE)) / (2 * h)
+    fd = (up - um) / (2 * h) - ut / c
+    scale = np.abs(bm).max()
+    assert scale > 1.0
+    # the raised cosine is C^1 only: skip samples within 2h of its two kinks
+    ok = np.ones_like(bm, dtype=bool)
+    if kind == "raised_cos":
+        t = dt * np.arange(1, nt)[:, None]
+        ph = c * t - (x @ inc["dir"])[None, :] - inc["rb"]
+        ok = (np.abs(ph) > 4 * h) & (np.abs(ph - inc["sigma"]) > 4 * h)
+    assert np.all(np.abs(bm - fd)[ok] <= 1e-6 * scale)
+
+
+def test_raised_cosine_pulse_shape():
+    """Plane pulse of eq. uin: zero before arrival and after one pulse length, peak 1 at half
+    the pulse length, time integral Lambda / (2 c) at every point, and invariant under the
+    plane-wave translation (x, t) -> (x + v, t + k.v / c) and under shifts across k."""
+    x, n = _seeded_points(5, 25)
+    c, lam = 1.7, 0.5
+    k = np.array([1.0, 0.0, 0.0])
+    inc = {"kind": "raised_cos", "dir": k, "f0": 1.0, "sigma": lam, "t0": 0.0, "rb": 1.5}
+    dt, nt = 1e-4, 2 * int(3.0 / 1e-4)
+    u = mot.incident(_Pts(x, n), inc, c, dt, nt, mot.OBIE)
+    t = dt * np.arange(1, nt)[:, None]
+    ph = c * t - (x @ k)[None, :] - inc["rb"]
+    assert np.all(u[(ph < 0) | (ph > lam)] == 0.0)
+    assert np.all((u >= 0.0) & (u <= 1.0))
+    assert np.allclose(u.sum(axis=0) * dt, lam / (2 * c), rtol=1e-6)
+    # peak: ph = lam / 2 at t = (x1 + rb + lam / 2) / c
+    tp = (x[:, 0] + inc["rb"] + lam / 2) / c
+    j = np.rint(tp / dt).astype(int) - 1
+    assert np.allclose(u[j, np.arange(len(x))], 1.0, atol=1e-6)
+    # plane-wave invariance: a shift v with k.v = 0.3 delays the pulse by 0.3 / c
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal(3)
+    v += (0.3 - v @ k) * k
+    shift = int(round(0.3 / c / dt))
+    dt2 = 0.3 / c / shift
+    u0 = mot.incident(_Pts(x, n), inc, c, dt2, 4000, mot.OBIE)
+    u1 = mot.incident(_Pts(x + v, n), inc, c, dt2, 4000 + shift, mot.OBIE)
+    assert np.allclose(u1[shift:], u0, atol=1e-12)
+
+
+_FORCING_PLANTS = [
+    # time derivative of the BM operator with the wrong sign
+    ("(-kn[None, :] - 1.0)", "(-kn[None, :] + 1.0)"),
+    # pulse travelling against its direction
+    ("(c * t - kx[None, :] - inc[\"rb\"])", "(c * t + kx[None, :] - inc[\"rb\"])"),
+    # pulse length used as a wavenumber
+    ("/ lam\n", "* lam\n"),
+]
+
+
+@pytest.mark.parametrize("old,new", _FORCING_PLANTS)
+def test_planted_forcing_mistakes_fail_a_pin(monkeypatch, old, new):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(mot.incident))
+    assert src.count(old) == 1, old
+    ns = dict(vars(mot))
+    exec(compile(src.replace(old, new), "planted_incident", "exec"), ns)
+    monkeypatch.setattr(mot, "incident", ns["incident"])
+    failed = 0
+    for pin in (lambda: test_bm_forcing_is_the_bm_operator_of_the_incident_field("raised_cos"),
+                test_raised_cosine_pulse_shape):
+        try:
+            pin()
+        except AssertionError:
+            failed += 1
+    assert failed >= 1
