@@ -39,7 +39,8 @@ WORKLOAD_TEXT = {
 
 def m2l_flops_per_march(info, nt, m_leaf, depth, G, P):
     """Algorithmic M2L flops of one march: 2 G P^2 per interaction pair per completed
-    source interval (G = mu+1+d operator blocks of P x P)."""
+    source interval (G operator blocks of P x P: mu+1+d for the whole product, mu+1 for
+    the near-future pass of a mixed-precision context)."""
     tot = 0
     for lev in range(2, depth + 1):
         Ml = m_leaf * 2 ** (depth - lev)
@@ -142,12 +143,16 @@ def run_form(P, w, args, prec, guess, params=None):
            "gmres_iters_per_march": iters // args.steps, "setup_ms": round(info["setup_ms"], 1)}
     if use_fmm:
         Pn = info["p_s"] ** 3 * info["p_t"]
-        G = info["mu"] + 1 + info["d"]
+        mixed = prec != P.M2L_FP64
+        # the dominant kernel: the products of every block (FP64), or of the mu+1
+        # near-future blocks in the context's low precision (mixed)
+        G = info["mu"] + 1 + (0 if mixed else info["d"])
         flops = m2l_flops_per_march(info, nt, info["m_leaf"], info["depth"], G, Pn) * args.steps
         ms, n = prof["m2l_gemm"]
         peak = PEAK_FP32_TFLOPS if prec == P.M2L_FP32 else PEAK_FP64_TFLOPS
         achieved = flops / (ms * 1e-3) / 1e12
-        roof = {"kernel": "m2l_gemm", "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+        roof = {"kernel": "m2l_gemm" + (" (near-future blocks, FP32)" if mixed else " (all blocks, FP64)"),
+                "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(prec) if args.workload == "sphere5k" else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",

@@ -11,11 +11,11 @@ import ctypes
 import numpy as np
 
 from . import _native as N
-from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
+from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_MLP_ONLY, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
                       INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
 
 __all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
-           "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP"]
+           "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP", "GUESS_MLP_ONLY"]
 
 
 class TDBEMError(RuntimeError):
@@ -149,6 +149,7 @@ class TDBEM:
         out = {k: getattr(i, k) for k, _ in N.Info._fields_}
         out["il_pairs"] = list(i.il_pairs)
         out["m2l_variant"] = list(i.m2l_variant)
+        out["m2l_variant_fp64"] = list(i.m2l_variant_fp64)
         return out
 
     def reset(self):

@@ -9,7 +9,7 @@ OBIE, BMBIE = 0, 1
 DIRICHLET, NEUMANN = 0, 1
 M2L_FP64, M2L_FP32 = 0, 1
 INC_GAUSS_MOD, INC_RAISED_COS = 0, 1
-GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP = 0, 1, 2, 3
+GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP, GUESS_MLP_ONLY = 0, 1, 2, 3, 4
 MLP_IN, MLP_IN_PAD, MLP_WIDTH, MLP_NPARAM = 12, 16, 256, 136193
 
 
@@ -46,10 +46,12 @@ class Info(ctypes.Structure):
                 ("p_s", ctypes.c_int), ("p_t", ctypes.c_int), ("mu", ctypes.c_int), ("m_leaf", ctypes.c_int),
                 ("near_pairs", ctypes.c_int64), ("near_coefs", ctypes.c_int64), ("a_nnz", ctypes.c_int64),
                 ("il_pairs", ctypes.c_int64 * 16), ("m2l_matrix_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
-                ("m2l_variant", ctypes.c_int * 16), ("gmres_workgroups", ctypes.c_int)]
+                ("m2l_variant", ctypes.c_int * 16), ("gmres_workgroups", ctypes.c_int),
+                ("m2l_variant_fp64", ctypes.c_int * 16)]
 
 
-PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other", "mlp"]
+PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other", "mlp",
+              "m2l_gemm_fp64"]
 
 _lib = None
 

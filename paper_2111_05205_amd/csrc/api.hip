@@ -232,7 +232,8 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
     if (ctx->bc == TDBEM_DIRICHLET) launch_spmv_add(ctx, ctx->d_w1_val.p, -1.0, bcv, ctx->d_b.p);
     else launch_spmv_add(ctx, ctx->d_u1_val.p, 1.0, bcv, ctx->d_b.p);
   }
-  const bool use_mlp = ctx->opts.guess == TDBEM_GUESS_MLP && ctx->mlp_loaded && beta >= 4;
+  const bool use_mlp = (ctx->opts.guess == TDBEM_GUESS_MLP || ctx->opts.guess == TDBEM_GUESS_MLP_ONLY) &&
+                       ctx->mlp_loaded && beta >= 4;
   float* feat = nullptr;
   if (beta >= 4 && (use_mlp || ctx->rec_feat)) {
     feat = ctx->rec_feat ? ctx->rec_feat + (size_t)beta * ctx->ns * TDBEM_MLP_IN_PAD : ctx->d_mlp_feat.p;
@@ -241,7 +242,7 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   const double* xalt = nullptr;
   if (use_mlp) {
     launch_mlp_guess(ctx, beta, feat, ctx->d_x.p, ctx->d_x_alt.p);
-    xalt = ctx->d_x_alt.p;
+    if (ctx->opts.guess == TDBEM_GUESS_MLP) xalt = ctx->d_x_alt.p;
   } else {
     ProfScope pg(ctx, K_OTHER);
     guess_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
@@ -284,15 +285,19 @@ static void march_steps(tdbem_ctx* ctx, int nt, const double* forc) {
     do_step(ctx, forc ? forc + (size_t)(alpha - 1) * ctx->ns : ctx->d_zero.p, nullptr, ctx->d_stat.p + (alpha - 1));
 }
 
+void tdbem::invalidate_graph(tdbem_ctx* ctx) {
+  if (ctx->g_exec) (void)hipGraphExecDestroy(ctx->g_exec);
+  ctx->g_exec = nullptr;
+  ctx->g_nt = 0;
+  ctx->g_forc = nullptr;
+}
+
 // Capture the march from alpha = 1 to nt-1 into a graph (host work only: the
 // launches are recorded, not run) unless one for (nt, forcing) exists.  The
 // host-side state a march leaves behind is kept for the replays.
 static void ensure_graph(tdbem_ctx* ctx, int nt, const double* forc) {
   if (ctx->g_exec && ctx->g_nt == nt && ctx->g_forc == forc) return;
-  if (ctx->g_exec) {
-    (void)hipGraphExecDestroy(ctx->g_exec);
-    ctx->g_exec = nullptr;
-  }
+  invalidate_graph(ctx);
   if (!ctx->cap_stream) TDBEM_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   const hipStream_t user = ctx->stream;
   const int a0 = ctx->alpha;
@@ -406,7 +411,7 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     if (o.gmres_restart <= 0) o.gmres_restart = 30;
     if (o.gmres_maxiter <= 0) o.gmres_maxiter = 300;
     if (o.nt_max <= 1) o.nt_max = 4096;
-    if (o.guess < TDBEM_GUESS_EXTRAP || o.guess > TDBEM_GUESS_MLP) fail(TDBEM_E_INVAL, "guess must be 0..3");
+    if (o.guess < TDBEM_GUESS_EXTRAP || o.guess > TDBEM_GUESS_MLP_ONLY) fail(TDBEM_E_INVAL, "guess must be 0..4");
     ctx->stream = (hipStream_t)hip_stream;
     ctx->c = c;
     ctx->dt = dt;
@@ -506,7 +511,9 @@ int tdbem_profile_mask(tdbem_ctx* ctx, unsigned mask) {
 
 int tdbem_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
   if (!ctx || !ctx->fmm) return TDBEM_E_INVAL;
-  return fmm_set_m2l_variant(ctx, n, choice);
+  const int rc = fmm_set_m2l_variant(ctx, n, choice);
+  if (rc == TDBEM_OK) invalidate_graph(ctx);
+  return rc;
 }
 
 int tdbem_profile_read(tdbem_ctx* ctx, double* ms, int64_t* launches, int n) {
@@ -705,7 +712,32 @@ struct CkptHeader {
   int32_t version, ns, d, bie, bc, use_fmm, depth, p_s, p_t, nstate;
   int32_t alpha, hist_u, hist_q, mlp;
   int64_t state_doubles;
+  double c, dt;
+  int32_t mu, m_leaf, m2l_prec, pad;
+  uint64_t mesh_hash;  // FNV-1a over the face vertex coordinates in face order
 };
+
+static uint64_t mesh_hash(const tdbem_ctx* ctx) {
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(ctx->geo.tris.data());
+  const size_t n = ctx->geo.tris.size() * sizeof(double);
+  for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+static void ckpt_fill_config(const tdbem_ctx* ctx, CkptHeader& h) {
+  h.ns = ctx->ns; h.d = ctx->d; h.bie = ctx->bie; h.bc = ctx->bc;
+  h.use_fmm = ctx->fmm ? 1 : 0;
+  h.depth = ctx->fmm ? ctx->opts.depth : 0;
+  h.p_s = ctx->fmm ? ctx->opts.p_s : 0;
+  h.p_t = ctx->fmm ? ctx->opts.p_t : 0;
+  h.c = ctx->c; h.dt = ctx->dt;
+  tdbem_info info{};
+  if (ctx->fmm) fmm_info(ctx, &info);
+  h.mu = info.mu; h.m_leaf = info.m_leaf;
+  h.m2l_prec = ctx->fmm ? ctx->opts.m2l_prec : 0;
+  h.mesh_hash = mesh_hash(ctx);
+}
 
 static size_t ckpt_bytes(const tdbem_ctx* ctx, const std::vector<std::pair<double*, size_t>>& st) {
   size_t n = sizeof(CkptHeader) + (size_t)2 * (ctx->alpha - 1) * ctx->ns * sizeof(double);
@@ -727,10 +759,8 @@ int tdbem_checkpoint(tdbem_ctx* ctx, void* host_buf, size_t* bytes) {
     }
     CkptHeader h{};
     std::memcpy(h.magic, "TDBEMCK1", 8);
-    h.version = 1;
-    h.ns = ctx->ns; h.d = ctx->d; h.bie = ctx->bie; h.bc = ctx->bc;
-    h.use_fmm = ctx->fmm ? 1 : 0;
-    h.depth = ctx->opts.depth; h.p_s = ctx->opts.p_s; h.p_t = ctx->opts.p_t;
+    h.version = 2;
+    ckpt_fill_config(ctx, h);
     h.nstate = (int32_t)st.size();
     h.alpha = ctx->alpha; h.hist_u = ctx->hist_u; h.hist_q = ctx->hist_q; h.mlp = ctx->mlp_loaded;
     for (const auto& b : st) h.state_doubles += (int64_t)b.second;
@@ -762,15 +792,19 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
     if (bytes < sizeof(CkptHeader)) fail(TDBEM_E_INVAL, "restore: buffer smaller than a checkpoint header");
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof(h));
-    if (std::memcmp(h.magic, "TDBEMCK1", 8) != 0 || h.version != 1) fail(TDBEM_E_INVAL, "restore: not a checkpoint");
+    if (std::memcmp(h.magic, "TDBEMCK1", 8) != 0 || h.version != 2) fail(TDBEM_E_INVAL, "restore: not a checkpoint");
     std::vector<std::pair<double*, size_t>> st;
     if (ctx->fmm) fmm_state_buffers(ctx, st);
     int64_t sd = 0;
     for (const auto& b : st) sd += (int64_t)b.second;
-    if (h.ns != ctx->ns || h.d != ctx->d || h.bie != ctx->bie || h.bc != ctx->bc || h.use_fmm != (ctx->fmm ? 1 : 0) ||
-        (h.use_fmm && (h.depth != ctx->opts.depth || h.p_s != ctx->opts.p_s || h.p_t != ctx->opts.p_t)) ||
+    CkptHeader mine{};
+    ckpt_fill_config(ctx, mine);
+    if (h.ns != mine.ns || h.d != mine.d || h.bie != mine.bie || h.bc != mine.bc || h.use_fmm != mine.use_fmm ||
+        h.depth != mine.depth || h.p_s != mine.p_s || h.p_t != mine.p_t || h.mu != mine.mu ||
+        h.m_leaf != mine.m_leaf || h.m2l_prec != mine.m2l_prec || h.c != mine.c || h.dt != mine.dt ||
         h.nstate != (int32_t)st.size() || h.state_doubles != sd)
       fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a context with a different configuration");
+    if (h.mesh_hash != mine.mesh_hash) fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a different mesh");
     if (h.alpha < 1 || h.alpha > ctx->nt_max) fail(TDBEM_E_INVAL, "restore: step beyond this context's nt_max");
     const size_t rows = (size_t)(h.alpha - 1) * ctx->ns * sizeof(double);
     size_t need = sizeof(CkptHeader) + 2 * rows + (size_t)sd * sizeof(double) +
@@ -789,9 +823,10 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
       TDBEM_HIP(hipMemcpyAsync(b.first, p, b.second * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
       p += b.second * sizeof(double);
     }
+    invalidate_graph(ctx);
     if (h.mlp) {
       mlp_prepare(ctx);
-      ctx->d_mlp_params.alloc(TDBEM_MLP_NPARAM);
+      if (!ctx->d_mlp_params.p) ctx->d_mlp_params.alloc(TDBEM_MLP_NPARAM);
       TDBEM_HIP(hipMemcpyAsync(ctx->d_mlp_params.p, p, TDBEM_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice,
                                ctx->stream));
       mlp_pack(ctx);

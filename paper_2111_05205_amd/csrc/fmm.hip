@@ -63,15 +63,22 @@ struct FmmLevel {
   DevBuf<int32_t> d_src_by_slot;            // their source cells (so the two loads are independent)
   int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
   DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
-  DevBuf<double> d_Uf;                      // FP64 operators in MFMA fragment order
-  DevBuf<float> d_U32, d_stage32;           // FP32 operators and staging (mixed-precision M2L)
-  DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_stage, d_dp;
+  // FP64 operators in MFMA fragment order: all G blocks (FP64 contexts) or only
+  // the d derivative blocks U^{(p)} (mixed contexts), and their per-pair products
+  DevBuf<double> d_Uf, d_stage;
+  DevBuf<float> d_U32, d_stage32;           // mixed FP32: near-future blocks l = 1..mu+1 and their products
+  DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_dp;
   DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
 };
 
 struct Fmm {
   int D = 0, ps = 0, pt = 0, Ps = 0, P = 0, G = 0, mu = 0, R = 0, m_leaf = 1;
-  bool f32 = false;
+  // M2L precision: 0 FP64, every block in one pass; 1 the mu+1 near-future blocks
+  // in FP32 (FP32 accumulation) and the d derivative blocks, which feed the
+  // recurrence, in a second FP64 pass
+  int prec = 0;
+  bool split() const { return prec != 0; }
+  int g_lo() const { return split() ? mu + 1 : G; }  // blocks of the first (low-precision) pass
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
   double om_s[MAXP], om_t[MAXP];
   std::vector<FmmLevel> lev;               // 0..D
@@ -82,7 +89,7 @@ struct Fmm {
   DevBuf<double> d_tau, d_sig;
   DevBuf<double> d_S, d_T;                 // 1-D re-interpolation matrices [side][parent][child]
   double Cd = 0;
-  int m2l_choice[16] = {0};                // per number of levels in a launch: 2 * tile variant + persistent
+  int m2l_choice[2][16] = {};              // [pass][levels in a launch]: 2 * tile variant + persistent
   int persistent_grid = 0;                 // workgroups of a persistent M2L launch
 };
 
@@ -428,9 +435,11 @@ template <> struct Mfma<float> {
 // RB = ceil(GP/16) blocks and columns to KB = m2l_kblocks(P) blocks (zeros).  A lane's A
 // fragments of V consecutive k blocks are then one 16-byte load, and a wave's load is
 // 1 KB of contiguous memory.
+// row0, GP: the rows row0 .. row0+GP-1 of each slot's G P x P operator stack
+// (GPsrc rows) are converted.
 template <class T>
-__global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double* __restrict__ U,
-                                    T* __restrict__ Uf) {
+__global__ void to_fragments_kernel(int P, int GPsrc, int row0, int GP, int RB, int KB,
+                                    const double* __restrict__ U, T* __restrict__ Uf) {
   constexpr int V = Vec16<T>::n;
   const int slot = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -440,7 +449,7 @@ __global__ void to_fragments_kernel(int P, int GP, int RB, int KB, const double*
   const int64_t blk = idx / (64 * V);
   const int kb = (int)(blk % (KB / V)) * V + e, rb = (int)(blk / (KB / V));
   const int row = rb * 16 + (lane & 15), col = 16 * (kb >> 2) + 4 * (lane >> 4) + (kb & 3);
-  const double v = (row < GP && col < P) ? U[((int64_t)slot * GP + row) * P + col] : 0.0;
+  const double v = (row < GP && col < P) ? U[((int64_t)slot * GPsrc + row0 + row) * P + col] : 0.0;
   Uf[(int64_t)slot * per + idx] = (T)v;
 }
 
@@ -863,31 +872,40 @@ static void launch_m2l_variant(int v, bool persistent, int grid, hipStream_t st,
   else launch_m2l_tile<T, false>(v, grid, st, P, GP, RB, KB, W);
 }
 
-// Reduce the staged products per target cell: grid (ncell, G, ceil(P/256)).
-// Block g < mu+1 adds its sum into the near-future local L_{k+g+1}; block
-// g = mu+p writes L^{(p)}_{k+mu+1,k} to dp[p-1].  Each thread sums one
-// coefficient over the cell's interaction pairs (independent loads).
+// Sum of one staged coefficient over pairs p0..p1-1 (row stride ld), four
+// independent partial sums.
 template <class ST>
-__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int G, int mu, int R, int k,
+__device__ inline double sum_pairs(const ST* __restrict__ sp, int64_t ld, int p0, int p1) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int p = p0;
+  for (; p + 3 < p1; p += 4) {
+    s0 += (double)sp[(int64_t)p * ld];
+    s1 += (double)sp[(int64_t)(p + 1) * ld];
+    s2 += (double)sp[(int64_t)(p + 2) * ld];
+    s3 += (double)sp[(int64_t)(p + 3) * ld];
+  }
+  for (; p < p1; ++p) s0 += (double)sp[(int64_t)p * ld];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Reduce the staged products per target cell: grid (ncell, G, ceil(P/256)).
+// Block g < mu+1 adds its sum into the near-future local L_{k+g+1} (products
+// in stage_lo: ST, row stride ld_lo); block g = mu+p writes L^{(p)}_{k+mu+1,k}
+// to dp[p-1] (products in stage_d, FP64, row stride ld_d, derivative p at
+// column (p-1) P).  Each thread sums one coefficient over the cell's
+// interaction pairs (independent loads).
+template <class ST>
+__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int mu, int R, int k,
                                                          const int32_t* __restrict__ il_ptr,
-                                                         const ST* __restrict__ stage, int ncell,
+                                                         const ST* __restrict__ stage_lo, int64_t ld_lo,
+                                                         const double* __restrict__ stage_d, int64_t ld_d, int ncell,
                                                          double* __restrict__ ring, double* __restrict__ dp) {
   const int O = blockIdx.x, g = blockIdx.y;
   const int a = blockIdx.z * blockDim.x + threadIdx.x;
   if (a >= P) return;
-  const int64_t GP = (int64_t)G * P;
   const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
-  const ST* sp = stage + (int64_t)g * P + a;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int p = p0;
-  for (; p + 3 < p1; p += 4) {
-    s0 += (double)sp[(int64_t)p * GP];
-    s1 += (double)sp[(int64_t)(p + 1) * GP];
-    s2 += (double)sp[(int64_t)(p + 2) * GP];
-    s3 += (double)sp[(int64_t)(p + 3) * GP];
-  }
-  for (; p < p1; ++p) s0 += (double)sp[(int64_t)p * GP];
-  const double s = (s0 + s1) + (s2 + s3);
+  const double s = g <= mu ? sum_pairs(stage_lo + (int64_t)g * P + a, ld_lo, p0, p1)
+                           : sum_pairs(stage_d + (int64_t)(g - mu - 1) * P + a, ld_d, p0, p1);
   if (g <= mu) ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s;
   else dp[((int64_t)(g - mu - 1) * ncell + O) * P + a] = s;
 }
@@ -1143,10 +1161,18 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
   if (!v.empty()) TDBEM_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Operator blocks of pass `part`: 0 the first pass (every block of an FP64
+// context, the near-future blocks of a mixed one), 1 the FP64 derivative pass
+// of a mixed context.
+static int pass_blocks(const Fmm* f, int part) { return part == 0 ? f->g_lo() : f->G - f->g_lo(); }
+static bool pass_fp32(const Fmm* f, int part) { return part == 0 && f->prec == 1; }
+
 // Levels D, D-1, ..., D-n+1 end a source interval together (n = 1..D-1): one
-// launch does their products.  choice = 2 * variant + persistent.
-static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
-  const int P = f->P, G = f->G;
+// launch does their products for pass `part`.  choice = 2 * variant + persistent.
+static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st, int part) {
+  const int P = f->P, G = pass_blocks(f, part);
+  if (G == 0) return;
+  const bool lo = pass_fp32(f, part);
   const int v = choice >> 1, persistent = choice & 1;
   const int rows = 64 * kVariantRpw[v];
   const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + rows - 1) / rows;
@@ -1163,7 +1189,7 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     Lw.src_by_slot = L.d_src_by_slot.p;
     Lw.mom = L.d_mom.p;
     Lw.mom32 = L.d_mom32.p;
-    if (f->f32) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
+    if (lo) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
     else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
     Lw.item0 = total;
     total += Lw.ntiles * nrb;
@@ -1172,14 +1198,14 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   if (total == 0) return;
   const bool pers = persistent && total > f->persistent_grid;
   const int grid = pers ? f->persistent_grid : total;
-  if (f->f32) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
+  if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
   else launch_m2l_variant<double>(v, pers, grid, st, P, G * P, RB, KB, W);
   TDBEM_HIP(hipGetLastError());
 }
 
 // Autotuner table shared by all contexts of the process: the fastest
-// (tile variant, persistent) for a launch, keyed by operator size P, blocks G,
-// precision, levels in the launch and the work size in powers of two.
+// (tile variant, persistent) for a launch, keyed by operator size P, blocks G of
+// the pass, its precision, levels in the launch and the work size in powers of two.
 struct M2LKey {
   int P, G, f32, nlev, bucket;
   bool operator<(const M2LKey& o) const {
@@ -1189,9 +1215,9 @@ struct M2LKey {
 static std::mutex g_tune_mu;
 static std::map<M2LKey, int> g_tune_table;
 
-static int m2l_work_items(const Fmm* f, int n, int v) {
+static int m2l_work_items(const Fmm* f, int n, int v, int part) {
   const int cols = kVariantCols[v], rows = 64 * kVariantRpw[v];
-  const int nrb = (f->G * f->P + rows - 1) / rows;
+  const int nrb = (pass_blocks(f, part) * f->P + rows - 1) / rows;
   int total = 0;
   for (int l = f->D; l > f->D - n && l >= 2; --l) {
     const FmmLevel& L = f->lev[l];
@@ -1202,15 +1228,17 @@ static int m2l_work_items(const Fmm* f, int n, int v) {
 
 static void autotune_m2l(Fmm* f, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (int part = 0; part < 2; ++part)
   for (int n = 1; n <= f->D - 1; ++n) {
-    const int items = m2l_work_items(f, n, 1);
+    if (pass_blocks(f, part) == 0) continue;
+    const int items = m2l_work_items(f, n, 1, part);
     int bucket = 0;
     while ((1 << bucket) < items) ++bucket;
-    const M2LKey key{f->P, f->G, f->f32 ? 1 : 0, n, bucket};
+    const M2LKey key{f->P, pass_blocks(f, part), pass_fp32(f, part) ? 1 : 0, n, bucket};
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune_table.find(key);
-      if (it != g_tune_table.end()) { f->m2l_choice[n] = it->second; continue; }
+      if (it != g_tune_table.end()) { f->m2l_choice[part][n] = it->second; continue; }
     }
     if (!e0) {
       TDBEM_HIP(hipEventCreate(&e0));
@@ -1219,18 +1247,18 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
     float best = 1e30f;
     int bestc = 2;  // 64 x 16 x 128, one item per workgroup
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
-      if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
+      if ((c & 1) && m2l_work_items(f, n, c >> 1, part) <= f->persistent_grid) continue;
       if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) continue;
-      launch_m2l_levels(f, n, c, st);  // warm-up
+      launch_m2l_levels(f, n, c, st, part);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
-      for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
+      for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st, part);
       TDBEM_HIP(hipEventRecord(e1, st));
       TDBEM_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) { best = ms; bestc = c; }
     }
-    f->m2l_choice[n] = bestc;
+    f->m2l_choice[part][n] = bestc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_table[key] = bestc;
   }
@@ -1249,7 +1277,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
   Fmm* f = new Fmm();
   try {
     f->D = o.depth;
-    f->f32 = o.m2l_prec == TDBEM_M2L_FP32;
+    f->prec = o.m2l_prec;
     f->ps = o.p_s;
     f->pt = o.p_t;
     f->Ps = f->ps * f->ps * f->ps;
@@ -1373,7 +1401,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         TDBEM_HIP(hipGetLastError());
       }
       L.d_mom.alloc((size_t)L.ncell * P);
-      if (f->f32) {
+      if (f->prec == 1) {
         L.d_mom32.alloc((size_t)L.ncell * P);
         TDBEM_HIP(hipMemsetAsync(L.d_mom32.p, 0, L.d_mom32.n * sizeof(float), st));
       }
@@ -1381,20 +1409,27 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
-      {
-        const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
+      for (int part = 0; part < 2; ++part) {
+        const int Gp = pass_blocks(f, part);
+        if (Gp == 0) continue;
+        const int row0 = part == 0 ? 0 : f->g_lo() * P;
+        const int RB = (Gp * P + 15) / 16, KB = m2l_kblocks(P);
         const int64_t per = (int64_t)RB * KB * 64;
         dim3 gf((unsigned)((per + 255) / 256), std::max(nslot, 1));
-        if (f->f32) {
+        if (pass_fp32(f, part)) {
           L.d_U32.alloc((size_t)std::max(nslot, 1) * per);
-          if (nslot > 0) to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, RB, KB, L.d_U.p, L.d_U32.p);
-          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+          if (nslot > 0)
+            to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, row0, Gp * P, RB, KB, L.d_U.p, L.d_U32.p);
+          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * Gp * P);
         } else {
           L.d_Uf.alloc((size_t)std::max(nslot, 1) * per);
-          if (nslot > 0) to_fragments_kernel<double><<<gf, 256, 0, st>>>(P, G * P, RB, KB, L.d_U.p, L.d_Uf.p);
-          L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+          if (nslot > 0)
+            to_fragments_kernel<double><<<gf, 256, 0, st>>>(P, G * P, row0, Gp * P, RB, KB, L.d_U.p, L.d_Uf.p);
+          L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * Gp * P);
         }
         TDBEM_HIP(hipGetLastError());
+      }
+      {
         TDBEM_HIP(hipStreamSynchronize(st));
         L.d_U.release();  // row-major master no longer needed
       }
@@ -1522,7 +1557,11 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     }
     {
       ProfScope ps(ctx, K_M2L_GEMM);
-      launch_m2l_levels(f, ndue, f->m2l_choice[ndue], st);
+      launch_m2l_levels(f, ndue, f->m2l_choice[0][ndue], st, 0);
+    }
+    if (f->split()) {
+      ProfScope ps(ctx, K_M2L_GEMM64);
+      launch_m2l_levels(f, ndue, f->m2l_choice[1][ndue], st, 1);
     }
     for (int l = D; l > D - ndue; --l) {
       const int Ml = f->m_leaf * (1 << (D - l));
@@ -1532,11 +1571,14 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
         ProfScope ps(ctx, K_M2L_RED);
         dim3 g2(L.ncell, G, (P + 255) / 256);
         const int bs = std::min(256, ((P + 63) / 64) * 64);
-        if (f->f32)
-          m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
+        const int64_t GPlo = (int64_t)f->g_lo() * P;
+        if (f->prec == 1)
+          m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage32.p, GPlo,
+                                                       L.d_stage.p, (int64_t)(G - f->g_lo()) * P, L.ncell,
                                                        L.d_ring.p, L.d_dp.p);
         else
-          m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, G, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage.p, L.ncell,
+          m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage.p, GPlo,
+                                                        L.d_stage.p + (int64_t)(f->mu + 1) * P, GPlo, L.ncell,
                                                         L.d_ring.p, L.d_dp.p);
         TDBEM_HIP(hipGetLastError());
         const int64_t nrec = (int64_t)L.ncell * P;
@@ -1570,7 +1612,10 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   info->mu = f->mu;
   info->m_leaf = f->m_leaf;
   int64_t bytes = 0;
-  for (int n = 1; n < f->D && n < 16; ++n) info->m2l_variant[n] = f->m2l_choice[n];
+  for (int n = 1; n < f->D && n < 16; ++n) {
+    info->m2l_variant[n] = f->m2l_choice[0][n];
+    info->m2l_variant_fp64[n] = f->split() ? f->m2l_choice[1][n] : -1;
+  }
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
     bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
@@ -1580,9 +1625,12 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
 
 int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
   Fmm* f = ctx->fmm;
+  const int part = n >= 16 ? 1 : 0;
+  if (part) n -= 16;
   if (!f || n < 1 || n > f->D - 1 || n >= 16 || choice < 0 || choice >= 2 * M2L_VARIANTS) return TDBEM_E_INVAL;
+  if (part && !f->split()) return TDBEM_E_INVAL;
   if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) return TDBEM_E_INVAL;
-  f->m2l_choice[n] = choice;
+  f->m2l_choice[part][n] = choice;
   return TDBEM_OK;
 }
 

@@ -151,7 +151,7 @@ struct tdbem_ctx {
 namespace tdbem {
 
 enum ProfKind { K_NEAR = 0, K_GMRES = 1, K_L2P = 2, K_P2M = 3, K_M2L_GEMM = 4, K_M2L_RED = 5, K_M2M = 6, K_L2L = 7,
-                K_OTHER = 8, K_MLP = 9 };
+                K_OTHER = 8, K_MLP = 9, K_M2L_GEMM64 = 10 };
 
 // Brackets the launches in its scope with events when profiling is enabled.
 struct ProfScope {
@@ -188,6 +188,10 @@ void autotune_gmres(tdbem_ctx* ctx);  // pick the solver's workgroup count by ti
 // api.hip
 void set_global_error(const std::string& msg);  // message for tdbem_last_error(NULL)
 void launch_forcing(tdbem_ctx* ctx, const tdbem_incident& inc, int a0, int n, double* out);
+
+// the captured march (if any) refers to buffers and choices that are about to
+// change: drop it so the next graph run records the march again
+void invalidate_graph(tdbem_ctx* ctx);
 
 // mlp.hip
 void mlp_prepare(tdbem_ctx* ctx);  // per-context buffers of the guess (diagonal of A, areas)

@@ -17,6 +17,8 @@
 #include "internal.h"
 
 #include <cmath>
+#include <mutex>
+#include <string>
 
 namespace tdbem {
 namespace {
@@ -545,7 +547,7 @@ void launch_mlp_target(tdbem_ctx* ctx, int beta, float* target) {
 }
 
 void mlp_pack(tdbem_ctx* ctx) {
-  ctx->d_mlp_wpk.alloc((size_t)2 * WID * WID);
+  if (!ctx->d_mlp_wpk.p) ctx->d_mlp_wpk.alloc((size_t)2 * WID * WID);
   mlp_pack_kernel<<<(2 * 16 * 8 * 64 + 255) / 256, 256, 0, ctx->stream>>>(
       ctx->d_mlp_params.p, reinterpret_cast<uint4*>(ctx->d_mlp_wpk.p));
   TDBEM_HIP(hipGetLastError());
@@ -656,7 +658,8 @@ int tdbem_mlp_load(tdbem_ctx* ctx, const float* dev_params) {
   try {
     if (!dev_params) throw Error(TDBEM_E_INVAL, "mlp_load: parameters are NULL");
     mlp_prepare(ctx);
-    ctx->d_mlp_params.alloc(NPARAM);
+    invalidate_graph(ctx);  // a captured march may predate the network
+    if (!ctx->d_mlp_params.p) ctx->d_mlp_params.alloc(NPARAM);  // reloads copy in place
     TDBEM_HIP(hipMemcpyAsync(ctx->d_mlp_params.p, dev_params, NPARAM * sizeof(float), hipMemcpyDeviceToDevice,
                              ctx->stream));
     mlp_pack(ctx);

@@ -212,7 +212,7 @@ def evaluate(params, xyz, tri, nt, inc, modes=("ZERO", "PREV", "EXTRAP", "MLP"),
     ref = None
     for mode in modes:
         solver, _ = make_solver(xyz, tri, nt=nt, guess=getattr(N, "GUESS_" + mode), **solver_kw)
-        if mode == "MLP":
+        if mode in ("MLP", "MLP_ONLY"):
             solver.mlp_load(params)
         x, ri = solver.run(nt, inc=inc)
         it = ri["total_iters"]

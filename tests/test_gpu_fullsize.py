@@ -79,7 +79,8 @@ def test_fmm_march_accuracy_and_fp32_products(w5k, direct_march):
     s32 = _ctx(w5k, m2l_prec=P.M2L_FP32)
     x32, _ = s32.run(w5k["nt"], inc=w5k["inc"])
     d = np.linalg.norm(x32.cpu().numpy() - x64) / np.linalg.norm(x64)
-    assert d < 1e-2, d
+    # near-future blocks in FP32, derivative blocks (fed to the recurrence) in FP64: measured 1.1e-4
+    assert d < 3e-4, d
     # the solution decays after the pulse has passed (stable BMBIE, Neumann)
     peak = np.abs(x64).max()
     assert np.abs(x64[-10:]).max() < 0.05 * peak

@@ -145,3 +145,31 @@ def test_batch_errors():
     s = P.TDBEM(xyz, tri, 1.0, dt, 1, P.BMBIE, P.NEUMANN, nt_max=10)
     with pytest.raises(P.TDBEMError):
         P.run_batch([s], [11], None)  # beyond nt_max
+
+
+def test_graph_rerecorded_after_network_reload():
+    """A march captured with network A, then network B loaded into the same
+    context: the next graph run equals an eager march with B (bitwise: same
+    kernels), so the replay cannot read A's freed or stale parameters."""
+    P = _P()
+    from paper_2111_05205_amd import mlp
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    inc = synth.incident_params(xyz, seed=5)
+    nt = 30
+    pa = mlp.init_params(1)
+    pb = mlp.init_params(2)
+    eager = P.TDBEM(xyz, tri, 1.0, dt, 2, P.BMBIE, P.NEUMANN, nt_max=nt, guess=P.GUESS_MLP_ONLY)
+    eager.mlp_load(pb)
+    xe, re_ = eager.run(nt, inc=inc)
+    g = P.TDBEM(xyz, tri, 1.0, dt, 2, P.BMBIE, P.NEUMANN, nt_max=nt, guess=P.GUESS_MLP_ONLY, graph=True,
+                stream=torch.cuda.Stream())
+    g.mlp_load(pa)
+    xa, ra = g.run(nt, inc=inc)
+    for rep in range(2):
+        g.mlp_load(pb)
+        g.reset()
+        xg, rg = g.run(nt, inc=inc)
+        torch.cuda.synchronize()
+        assert rg["total_iters"] == re_["total_iters"], (rep, rg["total_iters"], re_["total_iters"], ra["total_iters"])
+        assert torch.equal(xg, xe), rep

@@ -279,9 +279,14 @@ def test_trained_network_saves_iterations():
     params = M.load(path)
     xyz, tri = synth.icosphere(4)
     inc = synth.incident_params(xyz, seed=0)
-    res = M.evaluate(params, xyz, tri, 256, inc, modes=("ZERO", "PREV", "EXTRAP", "MLP"), gmres_tol=1e-8)
+    res = M.evaluate(params, xyz, tri, 256, inc, modes=("ZERO", "PREV", "EXTRAP", "MLP_ONLY", "MLP"),
+                     gmres_tol=1e-8)
     it = {k: v["total"] for k, v in res.items()}
-    print("GMRES iterations per march:", it)
+    ms = {k: v["march_ms"] for k, v in res.items()}
+    print("GMRES iterations per march:", it, "march ms:", ms)
+    # the network's own proposal (no comparison with the extrapolation) against
+    # zero and previous-row starts, and the guarded start against all three
+    assert it["MLP_ONLY"] < 0.97 * min(it["ZERO"], it["PREV"])
     assert it["MLP"] < 0.97 * min(it["ZERO"], it["PREV"])
     assert it["MLP"] < it["EXTRAP"]
     assert all(v.get("rel_diff_vs_first", 0.0) < 1e-6 for v in res.values())
