@@ -324,6 +324,22 @@ int tdbem_mlp_backward(const float *dev_params, int n, const float *dev_feat, co
                        const float *dev_dy, float *dev_grad, float *dev_work, size_t work_floats,
                        void *hip_stream);
 
+/* Largest n accepted by tdbem_mlp_backward_noalloc. */
+#define TDBEM_MLP_NOALLOC_MAX_ROWS 8192
+
+/* tdbem_mlp_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc): no workspace argument, and no allocation of any kind in
+ * the call.  The intermediate results (activation gradients, per-split weight
+ * gradient partials) live in one library-owned device array of fixed size
+ * (29.6 MB per GPU, held from the first call on that GPU until the process
+ * ends), shared by every call on that GPU: calls that overlap on one GPU race
+ * and must be serialised by the caller.  Arguments and results as for
+ * tdbem_mlp_backward (bit for bit the same gradient).
+ * Errors: TDBEM_E_INVAL for n > TDBEM_MLP_NOALLOC_MAX_ROWS or bad pointers. */
+int tdbem_mlp_backward_noalloc(const float *dev_params, int n, const float *dev_feat, const uint16_t *dev_act,
+                               const float *dev_dy, float *dev_grad, void *hip_stream);
+
 /* Mean squared error over n rows: dev_loss[0] = mean (y - t)^2 and
  * dev_dy = 2 (y - t) / n.  Deterministic. */
 int tdbem_mlp_mse(int n, const float *dev_y, const float *dev_t, float *dev_dy, float *dev_loss,

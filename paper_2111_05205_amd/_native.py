@@ -11,6 +11,7 @@ M2L_FP64, M2L_FP32 = 0, 1
 INC_GAUSS_MOD, INC_RAISED_COS = 0, 1
 GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP, GUESS_MLP_ONLY = 0, 1, 2, 3, 4
 MLP_IN, MLP_IN_PAD, MLP_WIDTH, MLP_NPARAM = 12, 16, 256, 136193
+MLP_NOALLOC_MAX_ROWS = 8192
 
 
 class Mesh(ctypes.Structure):
@@ -90,6 +91,7 @@ def lib():
         L.tdbem_mlp_workspace_floats.argtypes = [ip]
         L.tdbem_mlp_workspace_floats.restype = ctypes.c_size_t
         L.tdbem_mlp_backward.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tdbem_mlp_backward_noalloc.argtypes = [vp, ip, vp, vp, vp, vp, vp]
         L.tdbem_mlp_mse.argtypes = [ip, vp, vp, vp, vp, vp]
         L.tdbem_mlp_adam_step.argtypes = [vp, vp, vp, vp, ip, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                           ctypes.c_float, vp]

@@ -553,6 +553,34 @@ void mlp_pack(tdbem_ctx* ctx) {
   TDBEM_HIP(hipGetLastError());
 }
 
+// Scratch of tdbem_mlp_backward_noalloc: dz (3 x n x 256) followed by the
+// WG_SPLIT x NPARAM weight-gradient partials, sized for the row maximum
+// (29.6 MB).  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code the name is not a device address: kernels get the
+// per-device address from hipGetSymbolAddress.
+constexpr size_t NOALLOC_FLOATS = (size_t)3 * TDBEM_MLP_NOALLOC_MAX_ROWS * WID + (size_t)WG_SPLIT * NPARAM;
+__device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch, looked up once per device with that device current.
+float* noalloc_scratch() {
+  int dev = 0;
+  TDBEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) throw Error(TDBEM_E_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(TDBEM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace tdbem
 
 using namespace tdbem;
@@ -615,6 +643,36 @@ int tdbem_mlp_backward(const float* dev_params, int n, const float* dev_feat, co
     hipStream_t st = (hipStream_t)hip_stream;
     float* dz = dev_work;
     float* part = dev_work + (size_t)3 * n * WID;
+    if (n > 0) {
+      mlp_bwd_data_kernel<<<(n + FR - 1) / FR, 256, 0, st>>>(dev_params, n, dev_act, dev_dy, dz);
+      TDBEM_HIP(hipGetLastError());
+    }
+    mlp_wgrad_kernel<<<dim3(WG_TASKS, WG_SPLIT), 256, 0, st>>>(n, dev_feat, dev_act, dz, dev_dy, part);
+    TDBEM_HIP(hipGetLastError());
+    mlp_reduce_kernel<<<(NPARAM + 255) / 256, 256, 0, st>>>(part, dev_grad);
+    TDBEM_HIP(hipGetLastError());
+    TDBEM_HIP(hipStreamSynchronize(st));
+  });
+}
+
+// Backward pass without allocation: the activation gradients and the per-split
+// weight-gradient partials live in one file-scope device array (the same kernels
+// as tdbem_mlp_backward, which takes them in a caller workspace).  Every launch
+// writes every element it later reads, so nothing needs clearing between calls.
+int tdbem_mlp_backward_noalloc(const float* dev_params, int n, const float* dev_feat, const uint16_t* dev_act,
+                               const float* dev_dy, float* dev_grad, void* hip_stream) {
+  return mlp_guarded([&] {
+    if (!dev_params || !dev_grad || n < 0 || (n > 0 && (!dev_feat || !dev_act || !dev_dy)))
+      throw Error(TDBEM_E_INVAL, "mlp_backward_noalloc: bad arguments");
+    if (n > TDBEM_MLP_NOALLOC_MAX_ROWS)
+      throw Error(TDBEM_E_INVAL, "mlp_backward_noalloc: n = " + std::to_string(n) + " exceeds the maximum of " +
+                                     std::to_string(TDBEM_MLP_NOALLOC_MAX_ROWS) + " rows");
+    if (reinterpret_cast<uintptr_t>(dev_act) & 15)
+      throw Error(TDBEM_E_INVAL, "mlp_backward_noalloc: act must be 16-byte aligned");
+    float* work = noalloc_scratch();
+    hipStream_t st = (hipStream_t)hip_stream;
+    float* dz = work;
+    float* part = work + (size_t)3 * n * WID;
     if (n > 0) {
       mlp_bwd_data_kernel<<<(n + FR - 1) / FR, 256, 0, st>>>(dev_params, n, dev_act, dev_dy, dz);
       TDBEM_HIP(hipGetLastError());

@@ -94,6 +94,19 @@ def backward(params, feat, act, dy, work=None):
     return grad
 
 
+def backward_noalloc(params, feat, act, dy, grad=None):
+    """The same gradient through the entry point that allocates nothing (library scratch)."""
+    torch = _torch()
+    n = feat.shape[0]
+    if grad is None:
+        grad = torch.empty(NPARAM, dtype=torch.float32, device=feat.device)
+    _check(N.lib().tdbem_mlp_backward_noalloc(_fptr(params, NPARAM, "params"), int(n),
+                                              _fptr(feat, n * IN_PAD, "feat"),
+                                              _fptr(act, 3 * n * WIDTH, "act", torch.int16), _fptr(dy, n, "dy"),
+                                              _fptr(grad, NPARAM, "grad"), _stream(feat)))
+    return grad
+
+
 def mse(y, t):
     """(loss tensor of 1 element, dy)."""
     torch = _torch()
