@@ -99,7 +99,7 @@ def m2l_kernel_source():
     """Text of the M2L product kernel and its launch code (what the HBM counters describe)."""
     src = open(os.path.join(ROOT, "paper_2111_05205_amd", "csrc", "fmm.hip"), "rb").read()
     a = src.index(b"constexpr int M2L_MAXLEV")
-    b = src.index(b"// Reduce the staged products per target cell")
+    b = src.index(b"// Sum of one staged coefficient over pairs")
     return src[a:b]
 
 
@@ -144,14 +144,14 @@ def run_form(P, w, args, prec, guess, params=None):
     if use_fmm:
         Pn = info["p_s"] ** 3 * info["p_t"]
         mixed = prec != P.M2L_FP64
-        # the dominant kernel: the products of every block (FP64), or of the mu+1
-        # near-future blocks in the context's low precision (mixed)
-        G = info["mu"] + 1 + (0 if mixed else info["d"])
+        # the dominant kernel: the dense products of the mu+1 near-future blocks (the
+        # derivative products go through their separable form, a separate small kernel)
+        G = info["mu"] + 1
         flops = m2l_flops_per_march(info, nt, info["m_leaf"], info["depth"], G, Pn) * args.steps
         ms, n = prof["m2l_gemm"]
         peak = PEAK_FP32_TFLOPS if prec == P.M2L_FP32 else PEAK_FP64_TFLOPS
         achieved = flops / (ms * 1e-3) / 1e12
-        roof = {"kernel": "m2l_gemm" + (" (near-future blocks, FP32)" if mixed else " (all blocks, FP64)"),
+        roof = {"kernel": "m2l_gemm (near-future blocks, " + ("FP32)" if mixed else "FP64)"),
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(prec) if args.workload == "sphere5k" else None,

@@ -56,12 +56,11 @@ enum {
 
 typedef enum { TDBEM_OBIE = 0, TDBEM_BMBIE = 1 } tdbem_bie;          /* eq. bie / eq. bmbie */
 typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1 } tdbem_bc;    /* u given (q unknown) / q given (u unknown) */
-/* Precision of the M2L products (Section 4: eq. m2l_near for the near-future
- * blocks l = 1..mu+1, eq. L_l,k for the d derivative blocks U^{(p)}):
- * FP64: every block in FP64.  FP32: the near-future blocks in FP32 with FP32
- * accumulation; the derivative blocks, whose products feed the recurrence of
- * Formula 1 over every later interval, stay FP64 (second pass).  Moments,
- * locals, recurrence, near field and solve are FP64 in every case. */
+/* Precision of the near-future M2L products (Section 4, eq. m2l_near, blocks
+ * l = 1..mu+1): FP64, or FP32 with FP32 accumulation.  The derivative products
+ * U^{(p)} M (eq. L_l,k), which feed the recurrence of Formula 1 over every later
+ * interval, are FP64 in both (evaluated exactly through the separable form of
+ * U^{(p)}); moments, locals, recurrence, near field and solve are FP64. */
 typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1 } tdbem_m2l_prec;
 typedef enum { TDBEM_INC_GAUSS_MOD = 0, TDBEM_INC_RAISED_COS = 1 } tdbem_inc_kind;
 /* Starting point of the per-step GMRES solve (the paper names no solver):
@@ -140,7 +139,6 @@ typedef struct {
                            8 32x16x128, 9 32x16x256, 10 64x16x128, 11 64x16x256 (each lane reads its
                            moments directly, no LDS or barrier in the K loop) */
   int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
-  int m2l_variant_fp64[16]; /* mixed precision: the launch of the FP64 derivative pass, coded as m2l_variant (-1 without) */
 } tdbem_info;
 
 /* Build a context: copies and validates the mesh (closed, consistently
@@ -244,9 +242,9 @@ int tdbem_near_row(struct tdbem_ctx *ctx, int i, int cap, int32_t *j_out, int32_
  * bracketed by HIP events on the context stream and attributed to a category:
  * 0 near-field history sum, 1 GMRES solve, 2 L2P, 3 P2M (with densities),
  * 4 M2L products, 5 M2L reduction + recurrence, 6 M2M, 7 L2L, 8 other,
- * 9 learned guess (scale, features, network, proposal), 10 M2L products of the
- * FP64 derivative pass of a mixed-precision context (4 then holds the
- * near-future pass only).
+ * 9 learned guess (scale, features, network, proposal), 10 M2L derivative
+ * products (time moments and the separable U^{(p)} products; 4 holds the
+ * near-future products).
  * tdbem_profile(ctx, 1) clears the accumulators; tdbem_profile_read() waits
  * for the stream and writes per-category total milliseconds and launch counts
  * (arrays of n <= 16 entries). */
@@ -258,8 +256,7 @@ int tdbem_profile_read(struct tdbem_ctx *ctx, double *ms, int64_t *launches, int
 int tdbem_profile_mask(struct tdbem_ctx *ctx, unsigned mask);
 
 /* Override the autotuned M2L launch for the n finest levels ending an interval
- * together (n = 1 .. depth-1; tdbem_info.m2l_variant reports the current one;
- * n + 16 selects the FP64 derivative pass of a mixed-precision context instead):
+ * together (n = 1 .. depth-1; tdbem_info.m2l_variant reports the current one):
  * choice = 2 * tile + persistent, tile 0 .. 11 as listed at m2l_variant.  For
  * tests and tuning studies; the results are the same for every choice up to
  * summation order.  TDBEM_E_INVAL without an FMM, for n or choice out of range,

@@ -149,7 +149,6 @@ class TDBEM:
         out = {k: getattr(i, k) for k, _ in N.Info._fields_}
         out["il_pairs"] = list(i.il_pairs)
         out["m2l_variant"] = list(i.m2l_variant)
-        out["m2l_variant_fp64"] = list(i.m2l_variant_fp64)
         return out
 
     def reset(self):

@@ -46,6 +46,8 @@ namespace tdbem {
 
 constexpr int MAXP = 8;  // nodes per axis
 
+struct NodeSet { double s[MAXP], t[MAXP]; };  // Chebyshev nodes in space and time
+
 struct FmmLevel {
   int ncell = 0;
   std::vector<std::array<int, 3>> key;      // integer cell coordinates
@@ -58,29 +60,30 @@ struct FmmLevel {
   std::vector<std::array<int, 3>> slot_off; // offset vector of each matrix slot present at this level
   // device
   DevBuf<int32_t> d_il_ptr, d_parent, d_octant, d_child_ptr, d_child;
+  DevBuf<int32_t> d_il_src;                 // source cell of each interaction pair (sorted by target cell)
   DevBuf<int32_t> d_tiles128, d_tiles64, d_tiles32;  // GEMM column tiles (slot, first, count) by width
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
   DevBuf<int32_t> d_src_by_slot;            // their source cells (so the two loads are independent)
   int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
-  DevBuf<double> d_U;                       // [slot][G*P][P] (set-up only)
-  // FP64 operators in MFMA fragment order: all G blocks (FP64 contexts) or only
-  // the d derivative blocks U^{(p)} (mixed contexts), and their per-pair products
-  DevBuf<double> d_Uf, d_stage;
-  DevBuf<float> d_U32, d_stage32;           // mixed FP32: near-future blocks l = 1..mu+1 and their products
+  DevBuf<double> d_U;                       // [slot][(mu+1) P][P] near-future operators (set-up only)
+  DevBuf<double> d_Uf, d_stage;             // FP64: operators in MFMA fragment order, per-pair products
+  DevBuf<float> d_U32, d_stage32;           // FP32 (mixed precision): the same
+  DevBuf<double> d_Ktf;                     // derivative products' spatial kernels r^{-1} (and r, d = 3), fragment order
+  DevBuf<double> d_tm, d_tsum;              // time moments [j][cell][b] and their node sums [j][cell]
+  DevBuf<double> d_V;                       // derivative pair products [product][pair][Ps]
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_dp;
   DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
 };
 
 struct Fmm {
   int D = 0, ps = 0, pt = 0, Ps = 0, P = 0, G = 0, mu = 0, R = 0, m_leaf = 1;
-  // M2L precision: 0 FP64, every block in one pass; 1 the mu+1 near-future blocks
-  // in FP32 (FP32 accumulation) and the d derivative blocks, which feed the
-  // recurrence, in a second FP64 pass
+  // precision of the near-future products: 0 FP64, 1 FP32 (FP32 accumulation);
+  // the derivative products are FP64 in both
   int prec = 0;
-  bool split() const { return prec != 0; }
-  int g_lo() const { return split() ? mu + 1 : G; }  // blocks of the first (low-precision) pass
+  int Gn = 0;                              // near-future operator blocks, mu + 1
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
   double om_s[MAXP], om_t[MAXP];
+  NodeSet nodes{};                         // the same, as a kernel argument
   std::vector<FmmLevel> lev;               // 0..D
   std::vector<int> leaf_of;                // element -> leaf cell
   std::vector<int> leaf_ptr, leaf_elems;   // leaf -> elements (CSR)
@@ -89,7 +92,7 @@ struct Fmm {
   DevBuf<double> d_tau, d_sig;
   DevBuf<double> d_S, d_T;                 // 1-D re-interpolation matrices [side][parent][child]
   double Cd = 0;
-  int m2l_choice[2][16] = {};              // [pass][levels in a launch]: 2 * tile variant + persistent
+  int m2l_choice[16] = {0};                // per number of levels in a launch: 2 * tile variant + persistent
   int persistent_grid = 0;                 // workgroups of a persistent M2L launch
 };
 
@@ -136,7 +139,6 @@ static double hs_of(const Fmm* f, int l) { return f->H / (double)(1 << l); }
 // ---------------------------------------------------------------------------
 // Device kernels
 
-struct NodeSet { double s[MAXP], t[MAXP]; };
 
 // U[slot][g*P + row][col] for one level.  row = a1 + ps(a2 + ps(a3 + ps m)), col likewise (b, n).
 __global__ void m2l_matrix_kernel(int ps, int pt, int P, int G, int mu, int d, double c, double hs, double ht,
@@ -157,21 +159,33 @@ __global__ void m2l_matrix_kernel(int ps, int pt, int P, int G, int mu, int d, d
   const double dy = 2.0 * hs * oy + hs * (nodes.s[b2] - nodes.s[a2]);
   const double dz = 2.0 * hs * oz + hs * (nodes.s[b3] - nodes.s[a3]);
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  double val;
-  if (g <= mu) {  // near future, target interval k + (g+1)
-    const double tds = ((g + 1) * (double)Ml + 1.0) * dt + ht * (nodes.t[m] - nodes.t[n]);
-    double arg = c * tds - r;
-    if (arg < 0.0) arg = 0.0;
-    val = ipow(arg, d) / r;
-  } else {        // derivative p of eq. U_expand at the expansion interval k + mu + 1
-    const int p = g - mu;
-    const double tds = ((mu + 1) * (double)Ml + 1.0) * dt + ht * (nodes.t[m] - nodes.t[n]);
-    const double arg = c * tds - r;
-    double bin = 1.0;
-    for (int q = 0; q < p; ++q) bin = bin * (d - q) / (q + 1);
-    val = bin * ipow(arg, d - p) / r;
-  }
-  U[((int64_t)slot * G + g) * P * P + idx] = val;
+  // near future, target interval k + (g+1) (eq. Uabmn)
+  const double tds = ((g + 1) * (double)Ml + 1.0) * dt + ht * (nodes.t[m] - nodes.t[n]);
+  double arg = c * tds - r;
+  if (arg < 0.0) arg = 0.0;
+  U[((int64_t)slot * G + g) * P * P + idx] = ipow(arg, d) / r;
+}
+
+// Spatial kernels of the derivative products between target node a and source
+// node b of a cell pair at offset `slot` (cell half side hs): K[0] = 1/r and,
+// for d = 3, K[1] = r; row-major [kernel][slot][a][b] (converted to MFMA
+// fragment order afterwards).
+__global__ void m2l_spatial_kernel(int ps, int nk, double hs, NodeSet nodes, const int32_t* __restrict__ slot_off,
+                                   int nslot, double* __restrict__ Kt) {
+  const int Ps = ps * ps * ps;
+  const int slot = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Ps * Ps) return;
+  const int a = idx / Ps, b = idx % Ps;
+  const int a1 = a % ps, a2 = (a / ps) % ps, a3 = a / (ps * ps);
+  const int b1 = b % ps, b2 = (b / ps) % ps, b3 = b / (ps * ps);
+  const int ox = slot_off[3 * slot], oy = slot_off[3 * slot + 1], oz = slot_off[3 * slot + 2];
+  const double dx = 2.0 * hs * ox + hs * (nodes.s[b1] - nodes.s[a1]);
+  const double dy = 2.0 * hs * oy + hs * (nodes.s[b2] - nodes.s[a2]);
+  const double dz = 2.0 * hs * oz + hs * (nodes.s[b3] - nodes.s[a3]);
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  Kt[(int64_t)slot * Ps * Ps + idx] = 1.0 / r;
+  if (nk > 1) Kt[((int64_t)nslot + slot) * Ps * Ps + idx] = r;
 }
 
 // P2M / L2P element tables on the device.  Triangle quadrature: collapsed
@@ -888,26 +902,104 @@ __device__ inline double sum_pairs(const ST* __restrict__ sp, int64_t ld, int p0
   return (s0 + s1) + (s2 + s3);
 }
 
-// Reduce the staged products per target cell: grid (ncell, G, ceil(P/256)).
-// Block g < mu+1 adds its sum into the near-future local L_{k+g+1} (products
-// in stage_lo: ST, row stride ld_lo); block g = mu+p writes L^{(p)}_{k+mu+1,k}
-// to dp[p-1] (products in stage_d, FP64, row stride ld_d, derivative p at
-// column (p-1) P).  Each thread sums one coefficient over the cell's
-// interaction pairs (independent loads).
+// Reduce the staged near-future products per target cell: grid (ncell, mu+1,
+// ceil(P/256)); block g adds its sum into the local L_{k+g+1}.  Each thread
+// sums one coefficient over the cell's interaction pairs (independent loads).
 template <class ST>
-__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int mu, int R, int k,
+__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Gn, int R, int k,
                                                          const int32_t* __restrict__ il_ptr,
-                                                         const ST* __restrict__ stage_lo, int64_t ld_lo,
-                                                         const double* __restrict__ stage_d, int64_t ld_d, int ncell,
-                                                         double* __restrict__ ring, double* __restrict__ dp) {
+                                                         const ST* __restrict__ stage, int ncell,
+                                                         double* __restrict__ ring) {
   const int O = blockIdx.x, g = blockIdx.y;
   const int a = blockIdx.z * blockDim.x + threadIdx.x;
   if (a >= P) return;
   const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
-  const double s = g <= mu ? sum_pairs(stage_lo + (int64_t)g * P + a, ld_lo, p0, p1)
-                           : sum_pairs(stage_d + (int64_t)(g - mu - 1) * P + a, ld_d, p0, p1);
-  if (g <= mu) ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s;
-  else dp[((int64_t)(g - mu - 1) * ncell + O) * P + a] = s;
+  const double s = sum_pairs(stage + (int64_t)g * P + a, (int64_t)Gn * P, p0, p1);
+  ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s;
+}
+
+// Time moments of the completed source interval's moments, per cell:
+// S[j][cell][b] = sum_n (ht w_n)^j M[cell][b + Ps n], j = 0..d-1 (ht w_n: the
+// source node's time from the interval centre), and their node sums
+// Ssum[j][cell] = sum_b S[j][cell][b].  One 64-lane wave per cell.
+__global__ __launch_bounds__(64) void m2l_time_moments_kernel(int Ps, int pt, int d, double ht, NodeSet nodes,
+                                                              int ncell, const double* __restrict__ mom,
+                                                              double* __restrict__ S, double* __restrict__ Ssum) {
+  const int cell = blockIdx.x, lane = threadIdx.x;
+  double part[3] = {0.0, 0.0, 0.0};
+  for (int b = lane; b < Ps; b += 64) {
+    const double* M = mom + (int64_t)cell * Ps * pt + b;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int n = 0; n < pt; ++n) {
+      const double v = M[(int64_t)Ps * n], tn = ht * nodes.t[n];
+      double tp = 1.0;
+      for (int j = 0; j < d; ++j) { acc[j] += tp * v; tp *= tn; }
+    }
+    for (int j = 0; j < d; ++j) {
+      S[((int64_t)j * ncell + cell) * Ps + b] = acc[j];
+      part[j] += acc[j];
+    }
+  }
+  for (int j = 0; j < d; ++j) {
+    double v = part[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) Ssum[(int64_t)j * ncell + cell] = v;
+  }
+}
+
+// Derivative products of Algorithm 1, L^{(p)}_{k+mu+1,k} = sum over the cell's
+// interaction pairs of U^{(p)} M (eq. L_l,k), p = 1..d, in FP64, through the
+// separable form of the operator: its entries are C(d,p) (c (A_m - B_n) - r_ab)^q / r_ab
+// with q = d - p, A_m = T0 + ht w_m (target node time), B_n = ht w_n (source
+// node time), T0 = the centre distance of the expansion interval, so by the
+// trinomial expansion
+//   (U^{(p)} M)[a, m] = C(d,p) sum_{i+j+k=q} q!/(i! j! k!) (c A_m)^i (-c)^j (-1)^k V_{k,j}[a],
+//   V_{k,j}[a] = sum_b r_ab^{k-1} S_j[b],   S_j[b] = sum_n B_n^j M[b, n].
+// Exact (no approximation): the pair products are P_s x P_s spatial kernels
+// times d time moments (matrix cores, FP64, per offset like the near-future
+// products) instead of P x P blocks.  V_{1,j} (kernel r^0) is the node sum of
+// S_j.  This kernel sums the pair products per target cell and expands them
+// in time: one workgroup per cell, thread per target node a.
+// V: [product][pair][Ps], products (k, j) = (0, 0) .. (0, d-1), then (2, 0) for d = 3.
+__global__ void m2l_deriv_expand_kernel(int Ps, int pt, int d, double c, double T0, double ht, NodeSet nodes,
+                                        int ncell, int64_t npair, const int32_t* __restrict__ il_ptr,
+                                        const int32_t* __restrict__ il_src, const double* __restrict__ V,
+                                        const double* __restrict__ Ssum, double* __restrict__ dp) {
+  const int O = blockIdx.x;
+  const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
+  const int P = Ps * pt;
+  double vc[3] = {0.0, 0.0, 0.0};  // V_{1,j}: node sums, the same for every a
+  for (int p = p0; p < p1; ++p)
+    for (int j = 0; j + 1 < d; ++j) vc[j] += Ssum[(int64_t)j * ncell + il_src[p]];
+  for (int a = threadIdx.x; a < Ps; a += blockDim.x) {
+    double W[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int j = 0; j < d; ++j) W[0][j] = sum_pairs(V + (int64_t)j * npair * Ps + a, Ps, p0, p1);
+    if (d >= 3) W[2][0] = sum_pairs(V + (int64_t)d * npair * Ps + a, Ps, p0, p1);
+    for (int j = 0; j + 1 < d; ++j) W[1][j] = vc[j];
+    for (int pp = 1; pp <= d; ++pp) {
+      const int q = d - pp;
+      double binom = 1.0;
+      for (int t = 0; t < pp; ++t) binom = binom * (d - t) / (t + 1);
+      for (int m = 0; m < pt; ++m) {
+        const double cA = c * (T0 + ht * nodes.t[m]);
+        double val = 0.0;
+        for (int k = 0; k <= q; ++k)
+          for (int j = 0; j + k <= q; ++j) {
+            const int i = q - j - k;
+            double coef = 1.0;  // q! / (i! j! k!)
+            for (int t = 2; t <= q; ++t) coef *= t;
+            for (int t = 2; t <= i; ++t) coef /= t;
+            for (int t = 2; t <= j; ++t) coef /= t;
+            for (int t = 2; t <= k; ++t) coef /= t;
+            double term = coef * ((j + k) & 1 ? -1.0 : 1.0);
+            for (int t = 0; t < i; ++t) term *= cA;
+            for (int t = 0; t < j; ++t) term *= c;
+            val += term * W[k][j];
+          }
+        dp[((int64_t)(pp - 1) * ncell + O) * P + a + (int64_t)Ps * m] = binom * val;
+      }
+    }
+  }
 }
 
 // Recurrence of Algorithm 1 for source interval k, per (cell, coefficient):
@@ -1122,6 +1214,7 @@ static void build_hierarchy(tdbem_ctx* ctx, Fmm* f) {
     throw Error(TDBEM_E_INVAL, "mu too small for this hierarchy (need " + std::to_string(need) + ")");
   f->mu = ctx->opts.mu > 0 ? ctx->opts.mu : need;
   f->G = f->mu + 1 + ctx->d;
+  f->Gn = f->mu + 1;
   f->R = f->mu + 3;
 }
 
@@ -1161,18 +1254,11 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
   if (!v.empty()) TDBEM_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-// Operator blocks of pass `part`: 0 the first pass (every block of an FP64
-// context, the near-future blocks of a mixed one), 1 the FP64 derivative pass
-// of a mixed context.
-static int pass_blocks(const Fmm* f, int part) { return part == 0 ? f->g_lo() : f->G - f->g_lo(); }
-static bool pass_fp32(const Fmm* f, int part) { return part == 0 && f->prec == 1; }
-
 // Levels D, D-1, ..., D-n+1 end a source interval together (n = 1..D-1): one
-// launch does their products for pass `part`.  choice = 2 * variant + persistent.
-static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st, int part) {
-  const int P = f->P, G = pass_blocks(f, part);
-  if (G == 0) return;
-  const bool lo = pass_fp32(f, part);
+// launch does their near-future products.  choice = 2 * variant + persistent.
+static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
+  const int P = f->P, G = f->Gn;
+  const bool lo = f->prec == 1;
   const int v = choice >> 1, persistent = choice & 1;
   const int rows = 64 * kVariantRpw[v];
   const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + rows - 1) / rows;
@@ -1203,9 +1289,41 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st, i
   TDBEM_HIP(hipGetLastError());
 }
 
+// Derivative pair products of one level (see m2l_deriv_expand_kernel):
+// V_{0,j} = K_{1/r} S_j (j = 0..d-1) and, for d = 3, V_{2,0} = K_r S_0, FP64 on
+// the matrix cores with the near-future products' tiles (32 pairs of one offset,
+// LDS-staged time moments), each product a "level" of one launch.
+static void launch_deriv_products(const Fmm* f, const FmmLevel& L, int d, hipStream_t st) {
+  const int Ps = f->Ps, nslot = (int)L.slot_off.size();
+  const int RBk = (Ps + 15) / 16, KBk = m2l_kblocks(Ps);
+  const int64_t perk = (int64_t)RBk * KBk * 64;
+  const int nv = d + (d >= 3 ? 1 : 0);
+  const int nrb = (Ps + 127) / 128;  // 128 operator rows per workgroup (tile 32 x 16 x 128)
+  M2LWork W{};
+  int total = 0;
+  for (int v = 0; v < nv; ++v) {
+    M2LLevelWork& Lw = W.lev[W.nlev++];
+    const int j = v < d ? v : 0, kern = v < d ? 0 : 1;
+    Lw.ntiles = L.ntiles32;
+    Lw.tiles = L.d_tiles32.p;
+    Lw.pairs_by_slot = L.d_pairs_by_slot.p;
+    Lw.src_by_slot = L.d_src_by_slot.p;
+    Lw.mom = L.d_tm.p + (int64_t)j * L.ncell * Ps;
+    Lw.mom32 = nullptr;
+    Lw.Uf = L.d_Ktf.p + (int64_t)kern * nslot * perk;
+    Lw.stage = L.d_V.p + (int64_t)v * L.npair * Ps;
+    Lw.item0 = total;
+    total += Lw.ntiles * nrb;
+  }
+  W.total = total;
+  if (total == 0) return;
+  m2l_mfma_kernel<double, 2, 16, 2, false><<<total, 256, 0, st>>>(Ps, Ps, RBk, KBk, W);
+  TDBEM_HIP(hipGetLastError());
+}
+
 // Autotuner table shared by all contexts of the process: the fastest
-// (tile variant, persistent) for a launch, keyed by operator size P, blocks G of
-// the pass, its precision, levels in the launch and the work size in powers of two.
+// (tile variant, persistent) for a launch, keyed by operator size P, blocks G,
+// precision, levels in the launch and the work size in powers of two.
 struct M2LKey {
   int P, G, f32, nlev, bucket;
   bool operator<(const M2LKey& o) const {
@@ -1215,9 +1333,9 @@ struct M2LKey {
 static std::mutex g_tune_mu;
 static std::map<M2LKey, int> g_tune_table;
 
-static int m2l_work_items(const Fmm* f, int n, int v, int part) {
+static int m2l_work_items(const Fmm* f, int n, int v) {
   const int cols = kVariantCols[v], rows = 64 * kVariantRpw[v];
-  const int nrb = (pass_blocks(f, part) * f->P + rows - 1) / rows;
+  const int nrb = (f->Gn * f->P + rows - 1) / rows;
   int total = 0;
   for (int l = f->D; l > f->D - n && l >= 2; --l) {
     const FmmLevel& L = f->lev[l];
@@ -1228,17 +1346,15 @@ static int m2l_work_items(const Fmm* f, int n, int v, int part) {
 
 static void autotune_m2l(Fmm* f, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  for (int part = 0; part < 2; ++part)
   for (int n = 1; n <= f->D - 1; ++n) {
-    if (pass_blocks(f, part) == 0) continue;
-    const int items = m2l_work_items(f, n, 1, part);
+    const int items = m2l_work_items(f, n, 1);
     int bucket = 0;
     while ((1 << bucket) < items) ++bucket;
-    const M2LKey key{f->P, pass_blocks(f, part), pass_fp32(f, part) ? 1 : 0, n, bucket};
+    const M2LKey key{f->P, f->Gn, f->prec, n, bucket};
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune_table.find(key);
-      if (it != g_tune_table.end()) { f->m2l_choice[part][n] = it->second; continue; }
+      if (it != g_tune_table.end()) { f->m2l_choice[n] = it->second; continue; }
     }
     if (!e0) {
       TDBEM_HIP(hipEventCreate(&e0));
@@ -1247,18 +1363,18 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
     float best = 1e30f;
     int bestc = 2;  // 64 x 16 x 128, one item per workgroup
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
-      if ((c & 1) && m2l_work_items(f, n, c >> 1, part) <= f->persistent_grid) continue;
+      if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
       if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) continue;
-      launch_m2l_levels(f, n, c, st, part);  // warm-up
+      launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
-      for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st, part);
+      for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
       TDBEM_HIP(hipEventRecord(e1, st));
       TDBEM_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       TDBEM_HIP(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) { best = ms; bestc = c; }
     }
-    f->m2l_choice[part][n] = bestc;
+    f->m2l_choice[n] = bestc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_table[key] = bestc;
   }
@@ -1288,8 +1404,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     build_tree(ctx, f);
     build_hierarchy(ctx, f);
     hipStream_t st = ctx->stream;
-    const int ns = ctx->ns, P = f->P, G = f->G;
-    NodeSet nodes{};
+    const int ns = ctx->ns, P = f->P, G = f->Gn;
+    NodeSet& nodes = f->nodes;
     for (int a = 0; a < f->ps; ++a) nodes.s[a] = f->om_s[a];
     for (int a = 0; a < f->pt; ++a) nodes.t[a] = f->om_t[a];
     // element tables
@@ -1362,6 +1478,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       FmmLevel& L = f->lev[l];
       std::vector<int32_t> ilp(L.il_ptr.begin(), L.il_ptr.end());
       upload(L.d_il_ptr, ilp, st);
+      std::vector<int32_t> ils(L.il_src.begin(), L.il_src.end());
+      upload(L.d_il_src, ils, st);
       const int nslot = (int)L.slot_off.size();
       std::vector<std::vector<int32_t>> by(nslot);
       for (int64_t p = 0; p < L.npair; ++p) by[L.il_slot[p]].push_back((int32_t)p);
@@ -1393,13 +1511,29 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       DevBuf<int32_t> d_so;
       upload(d_so, so, st);
       L.d_U.alloc((size_t)std::max(nslot, 1) * G * P * P);
+      const int nk = ctx->d >= 3 ? 2 : 1;
+      DevBuf<double> d_K;  // row-major spatial kernels (set-up only)
+      d_K.alloc((size_t)std::max(nslot, 1) * nk * f->Ps * f->Ps);
       if (nslot > 0) {
         const double Ml = (double)f->m_leaf * (1 << (f->D - l));
         dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, nslot);
         m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, ctx->c, hs_of(f, l),
                                                 Ml * ctx->dt / 2.0, ctx->dt, (int)Ml, nodes, d_so.p, L.d_U.p);
         TDBEM_HIP(hipGetLastError());
+        dim3 gk((unsigned)((f->Ps * f->Ps + 255) / 256), nslot);
+        m2l_spatial_kernel<<<gk, 256, 0, st>>>(f->ps, nk, hs_of(f, l), nodes, d_so.p, nslot, d_K.p);
+        TDBEM_HIP(hipGetLastError());
+        const int RBk = (f->Ps + 15) / 16, KBk = m2l_kblocks(f->Ps);
+        const int64_t perk = (int64_t)RBk * KBk * 64;
+        L.d_Ktf.alloc((size_t)nk * nslot * perk);
+        dim3 gfk((unsigned)((perk + 255) / 256), nk * nslot);
+        to_fragments_kernel<double><<<gfk, 256, 0, st>>>(f->Ps, f->Ps, 0, f->Ps, RBk, KBk, d_K.p, L.d_Ktf.p);
+        TDBEM_HIP(hipGetLastError());
+        TDBEM_HIP(hipStreamSynchronize(st));
       }
+      L.d_tm.alloc((size_t)L.ncell * ctx->d * f->Ps);
+      L.d_tsum.alloc((size_t)L.ncell * ctx->d);
+      L.d_V.alloc((size_t)std::max<int64_t>(L.npair, 1) * (ctx->d + (ctx->d >= 3 ? 1 : 0)) * f->Ps);
       L.d_mom.alloc((size_t)L.ncell * P);
       if (f->prec == 1) {
         L.d_mom32.alloc((size_t)L.ncell * P);
@@ -1409,27 +1543,20 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
-      for (int part = 0; part < 2; ++part) {
-        const int Gp = pass_blocks(f, part);
-        if (Gp == 0) continue;
-        const int row0 = part == 0 ? 0 : f->g_lo() * P;
-        const int RB = (Gp * P + 15) / 16, KB = m2l_kblocks(P);
+      {
+        const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
         const int64_t per = (int64_t)RB * KB * 64;
         dim3 gf((unsigned)((per + 255) / 256), std::max(nslot, 1));
-        if (pass_fp32(f, part)) {
+        if (f->prec == 1) {
           L.d_U32.alloc((size_t)std::max(nslot, 1) * per);
-          if (nslot > 0)
-            to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, row0, Gp * P, RB, KB, L.d_U.p, L.d_U32.p);
-          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * Gp * P);
+          if (nslot > 0) to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB, L.d_U.p, L.d_U32.p);
+          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
         } else {
           L.d_Uf.alloc((size_t)std::max(nslot, 1) * per);
-          if (nslot > 0)
-            to_fragments_kernel<double><<<gf, 256, 0, st>>>(P, G * P, row0, Gp * P, RB, KB, L.d_U.p, L.d_Uf.p);
-          L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * Gp * P);
+          if (nslot > 0) to_fragments_kernel<double><<<gf, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB, L.d_U.p, L.d_Uf.p);
+          L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
         }
         TDBEM_HIP(hipGetLastError());
-      }
-      {
         TDBEM_HIP(hipStreamSynchronize(st));
         L.d_U.release();  // row-major master no longer needed
       }
@@ -1557,29 +1684,35 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     }
     {
       ProfScope ps(ctx, K_M2L_GEMM);
-      launch_m2l_levels(f, ndue, f->m2l_choice[0][ndue], st, 0);
-    }
-    if (f->split()) {
-      ProfScope ps(ctx, K_M2L_GEMM64);
-      launch_m2l_levels(f, ndue, f->m2l_choice[1][ndue], st, 1);
+      launch_m2l_levels(f, ndue, f->m2l_choice[ndue], st);
     }
     for (int l = D; l > D - ndue; --l) {
       const int Ml = f->m_leaf * (1 << (D - l));
       const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
       FmmLevel& L = f->lev[l];
       if (L.npair > 0) {
+        {
+          // derivative products L^{(p)}_{k+mu+1,k} (FP64, separable form)
+          ProfScope ps(ctx, K_M2L_DERIV);
+          const double ht = Ml * ctx->dt / 2.0, T0 = ((f->mu + 1) * (double)Ml + 1.0) * ctx->dt;
+          m2l_time_moments_kernel<<<L.ncell, 64, 0, st>>>(f->Ps, f->pt, ctx->d, ht, f->nodes, L.ncell, L.d_mom.p,
+                                                          L.d_tm.p, L.d_tsum.p);
+          TDBEM_HIP(hipGetLastError());
+          launch_deriv_products(f, L, ctx->d, st);
+          m2l_deriv_expand_kernel<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
+              f->Ps, f->pt, ctx->d, ctx->c, T0, ht, f->nodes, L.ncell, L.npair, L.d_il_ptr.p, L.d_il_src.p,
+              L.d_V.p, L.d_tsum.p, L.d_dp.p);
+          TDBEM_HIP(hipGetLastError());
+        }
         ProfScope ps(ctx, K_M2L_RED);
-        dim3 g2(L.ncell, G, (P + 255) / 256);
+        dim3 g2(L.ncell, f->Gn, (P + 255) / 256);
         const int bs = std::min(256, ((P + 63) / 64) * 64);
-        const int64_t GPlo = (int64_t)f->g_lo() * P;
         if (f->prec == 1)
-          m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage32.p, GPlo,
-                                                       L.d_stage.p, (int64_t)(G - f->g_lo()) * P, L.ncell,
-                                                       L.d_ring.p, L.d_dp.p);
+          m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
+                                                       L.d_ring.p);
         else
-          m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->mu, f->R, k, L.d_il_ptr.p, L.d_stage.p, GPlo,
-                                                        L.d_stage.p + (int64_t)(f->mu + 1) * P, GPlo, L.ncell,
-                                                        L.d_ring.p, L.d_dp.p);
+          m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_stage.p, L.ncell,
+                                                        L.d_ring.p);
         TDBEM_HIP(hipGetLastError());
         const int64_t nrec = (int64_t)L.ncell * P;
         m2l_recurrence_kernel<<<(unsigned)((nrec + 255) / 256), 256, 0, st>>>(P, f->mu, ctx->d, f->R, k,
@@ -1612,10 +1745,7 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   info->mu = f->mu;
   info->m_leaf = f->m_leaf;
   int64_t bytes = 0;
-  for (int n = 1; n < f->D && n < 16; ++n) {
-    info->m2l_variant[n] = f->m2l_choice[0][n];
-    info->m2l_variant_fp64[n] = f->split() ? f->m2l_choice[1][n] : -1;
-  }
+  for (int n = 1; n < f->D && n < 16; ++n) info->m2l_variant[n] = f->m2l_choice[n];
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
     bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
@@ -1625,12 +1755,9 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
 
 int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
   Fmm* f = ctx->fmm;
-  const int part = n >= 16 ? 1 : 0;
-  if (part) n -= 16;
   if (!f || n < 1 || n > f->D - 1 || n >= 16 || choice < 0 || choice >= 2 * M2L_VARIANTS) return TDBEM_E_INVAL;
-  if (part && !f->split()) return TDBEM_E_INVAL;
   if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) return TDBEM_E_INVAL;
-  f->m2l_choice[part][n] = choice;
+  f->m2l_choice[n] = choice;
   return TDBEM_OK;
 }
 

@@ -151,7 +151,7 @@ struct tdbem_ctx {
 namespace tdbem {
 
 enum ProfKind { K_NEAR = 0, K_GMRES = 1, K_L2P = 2, K_P2M = 3, K_M2L_GEMM = 4, K_M2L_RED = 5, K_M2M = 6, K_L2L = 7,
-                K_OTHER = 8, K_MLP = 9, K_M2L_GEMM64 = 10 };
+                K_OTHER = 8, K_MLP = 9, K_M2L_DERIV = 10 };
 
 // Brackets the launches in its scope with events when profiling is enabled.
 struct ProfScope {

@@ -207,6 +207,23 @@ def test_kernel_interpolation_converges_after_the_wavefront():
         assert e[0] > 5 * e[1] > 25 * e[2], (o, e)
 
 
+def test_kernel_interpolation_stalls_where_the_wavefront_crosses():
+    """Why the FMM cannot approach the direct method to 1e-4 at affordable p (Section 3, eq.
+    U_intp): in a time gap where the wavefront c (t - s) = r crosses the cell pair, the kernel
+    (c (t - s) - r)_+^d / r has a kink inside the interpolation box, and the 8-variable
+    Chebyshev interpolant converges only algebraically there; once the wavefront has passed,
+    geometrically.  Doubling p from 4 to 8 (16 times the operator size P = p^4) gains orders
+    of magnitude behind the wavefront but little where it crosses."""
+    kinked = [((2, 0, 0), 1), ((3, 1, 0), 3), ((2, 2, 2), 4)]
+    smooth = [((2, 0, 0), 13), ((3, 1, 0), 13), ((2, 2, 2), 13)]
+    for o, gap in kinked:
+        e4, e8 = (_interp_error(o, gap, p, n=400) for p in (4, 8))
+        assert e8 > 5e-4 and e8 > e4 / 40, (o, gap, e4, e8)
+    for o, gap in smooth:
+        e4, e8 = (_interp_error(o, gap, p, n=400) for p in (4, 8))
+        assert e8 < 1e-5 and e8 < e4 / 300, (o, gap, e4, e8)
+
+
 def _basis_at(R, lev, center, half_side, t_center, y, s):
     """Basis functions of a space-time box evaluated at one point (y, s): the moments of a unit
     point source there, or the weights that evaluate a local at a target point.  Index
