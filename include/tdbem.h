@@ -57,11 +57,12 @@ enum {
 typedef enum { TDBEM_OBIE = 0, TDBEM_BMBIE = 1 } tdbem_bie;          /* eq. bie / eq. bmbie */
 typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1 } tdbem_bc;    /* u given (q unknown) / q given (u unknown) */
 /* Precision of the near-future M2L products (Section 4, eq. m2l_near, blocks
- * l = 1..mu+1): FP64, or FP32 with FP32 accumulation.  The derivative products
+ * l = 1..mu+1): FP64, FP32, or BF16 operators and moments (rounded to nearest)
+ * on the BF16 matrix cores; FP32 and BF16 accumulate in FP32.  The derivative products
  * U^{(p)} M (eq. L_l,k), which feed the recurrence of Formula 1 over every later
  * interval, are FP64 in both (evaluated exactly through the separable form of
  * U^{(p)}); moments, locals, recurrence, near field and solve are FP64. */
-typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1 } tdbem_m2l_prec;
+typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1, TDBEM_M2L_BF16 = 2 } tdbem_m2l_prec;
 typedef enum { TDBEM_INC_GAUSS_MOD = 0, TDBEM_INC_RAISED_COS = 1 } tdbem_inc_kind;
 /* Starting point of the per-step GMRES solve (the paper names no solver):
  * EXTRAP quadratic extrapolation of the last three solved rows (default),
@@ -137,7 +138,8 @@ typedef struct {
                            workgroup) 0 128x16x128, 1 64x16x128, 2 64x32x128, 3 32x16x128, 4 32x32x128,
                            5 32x16x256, 6 64x16x256, 7 32x32x256 (moment tile shared through LDS);
                            8 32x16x128, 9 32x16x256, 10 64x16x128, 11 64x16x256 (each lane reads its
-                           moments directly, no LDS or barrier in the K loop) */
+                           moments directly, no LDS or barrier in the K loop; BF16 contexts use only
+                           these four shapes, with K steps of 32) */
   int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
 } tdbem_info;
 

@@ -7,14 +7,15 @@ torch float64 CUDA (HIP) tensors; the library works on the current torch
 stream of the tensors' device.
 """
 import ctypes
+import sys
 
 import numpy as np
 
 from . import _native as N
 from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_MLP_ONLY, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
-                      INC_RAISED_COS, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
+                      INC_RAISED_COS, M2L_BF16, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
 
-__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32",
+__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32", "M2L_BF16",
            "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP", "GUESS_MLP_ONLY"]
 
 
@@ -129,6 +130,10 @@ class TDBEM:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be finalising: leave the
+        # device memory to the process exit instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

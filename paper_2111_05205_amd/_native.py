@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdbem.so
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 OBIE, BMBIE = 0, 1
 DIRICHLET, NEUMANN = 0, 1
-M2L_FP64, M2L_FP32 = 0, 1
+M2L_FP64, M2L_FP32, M2L_BF16 = 0, 1, 2
 INC_GAUSS_MOD, INC_RAISED_COS = 0, 1
 GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP, GUESS_MLP_ONLY = 0, 1, 2, 3, 4
 MLP_IN, MLP_IN_PAD, MLP_WIDTH, MLP_NPARAM = 12, 16, 256, 136193

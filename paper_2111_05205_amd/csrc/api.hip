@@ -483,8 +483,8 @@ static void prof_collect(tdbem_ctx* ctx) {
       ctx->prof_ms[e.first] += ms;
       ctx->prof_cnt[e.first] += 1;
     }
-    (void)hipEventDestroy(e.second.first);
-    (void)hipEventDestroy(e.second.second);
+    ctx->ev_pool.push_back(e.second.first);
+    ctx->ev_pool.push_back(e.second.second);
   }
   ctx->prof_ev.clear();
 }
@@ -530,6 +530,7 @@ int tdbem_profile_read(tdbem_ctx* ctx, double* ms, int64_t* launches, int n) {
 void tdbem_destroy(tdbem_ctx* ctx) {
   if (!ctx) return;
   for (auto& e : ctx->prof_ev) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->fmm) fmm_destroy(ctx->fmm);
   if (ctx->g_exec) (void)hipGraphExecDestroy(ctx->g_exec);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);

@@ -48,6 +48,14 @@ constexpr int MAXP = 8;  // nodes per axis
 
 struct NodeSet { double s[MAXP], t[MAXP]; };  // Chebyshev nodes in space and time
 
+// bfloat16 bits of x: rounded to float, then to nearest bf16, ties to even (NaN stays NaN).
+__device__ inline uint16_t bf16_rne(double x) {
+  const float f = (float)x;
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 struct FmmLevel {
   int ncell = 0;
   std::vector<std::array<int, 3>> key;      // integer cell coordinates
@@ -73,14 +81,16 @@ struct FmmLevel {
   DevBuf<double> d_V;                       // derivative pair products [product][pair][Ps]
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_dp;
   DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
+  DevBuf<uint16_t> d_U16, d_mom16;          // BF16 M2L: operators in fragment order; moments [cell][Pp] (zero padded)
 };
 
 struct Fmm {
   int D = 0, ps = 0, pt = 0, Ps = 0, P = 0, G = 0, mu = 0, R = 0, m_leaf = 1;
-  // precision of the near-future products: 0 FP64, 1 FP32 (FP32 accumulation);
-  // the derivative products are FP64 in both
+  // precision of the near-future products: 0 FP64, 1 FP32, 2 BF16 (both with FP32
+  // accumulation); the derivative products are FP64 in every case
   int prec = 0;
   int Gn = 0;                              // near-future operator blocks, mu + 1
+  int Pp = 0;                              // row stride of the BF16 moment copy: P rounded up to 32
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
   double om_s[MAXP], om_t[MAXP];
   NodeSet nodes{};                         // the same, as a kernel argument
@@ -283,7 +293,7 @@ __global__ void p2m_kernel(int Ps, int pt, int first, double Cd, TimeWeights tw,
                            const int32_t* __restrict__ leaf_elems, const double* __restrict__ A,
                            const double* __restrict__ B, const double* __restrict__ tau,
                            const double* __restrict__ sig, double* __restrict__ mom,
-                           float* __restrict__ mom32) {
+                           float* __restrict__ mom32, uint16_t* __restrict__ mom16, int Pp) {
   const int S = blockIdx.x;
   const int P = Ps * pt;
   for (int b = threadIdx.x; b < Ps; b += blockDim.x) {
@@ -298,6 +308,7 @@ __global__ void p2m_kernel(int Ps, int pt, int first, double Cd, TimeWeights tw,
       const double v = (first ? 0.0 : mom[ix]) + acc * tw.w[n];
       mom[ix] = v;
       if (mom32) mom32[ix] = (float)v;  // FP32 products read this copy; the last write of an interval is final
+      if (mom16) mom16[(int64_t)S * Pp + b + Ps * n] = bf16_rne(v);  // likewise the BF16 products
     }
   }
 }
@@ -334,7 +345,7 @@ __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__
                            const int32_t* __restrict__ child, const int32_t* __restrict__ octant,
                            const double* __restrict__ S, const double* __restrict__ T,
                            const double* __restrict__ mom_c, double* __restrict__ mom_p,
-                           float* __restrict__ mom32_p) {
+                           float* __restrict__ mom32_p, uint16_t* __restrict__ mom16_p, int Pp) {
   extern __shared__ double sm[];
   const int Ps = ps * ps * ps, P = Ps * pt;
   double* b0 = sm;
@@ -364,6 +375,7 @@ __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__
       const double v = (half == 0 ? 0.0 : mom_p[(int64_t)p * P + idx]) + acc[q];
       mom_p[(int64_t)p * P + idx] = v;
       if (mom32_p) mom32_p[(int64_t)p * P + idx] = (float)v;
+      if (mom16_p) mom16_p[(int64_t)p * Pp + idx] = bf16_rne(v);
     }
   }
 }
@@ -478,6 +490,7 @@ struct M2LLevelWork {
   const void* Uf;                // T operators in fragment order
   const double* mom;
   const float* mom32;            // FP32 copy of mom (FP32 products only)
+  const uint16_t* mom16;         // BF16 copy of mom, row stride Pp (BF16 products only)
   void* stage;                   // T per-pair products
   int ntiles;
   int item0;                     // first work item of this level
@@ -853,6 +866,123 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
   } while (w < total);
 }
 
+// BF16 near-future products (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+// A[i][k] sits in lane i + 16 (k / 8), element k % 8, B[k][j] in lane j + 16 (k / 8),
+// element k % 8, D[4 (lane / 16) + r][lane % 16] in accumulator element r.
+// Operators in that fragment order, K steps of 32 columns:
+//   U16[slot][rb][kb][lane][e] = U[16 rb + lane % 16][32 kb + 8 (lane / 16) + e]
+// (rows padded to RB blocks, columns to KB32 steps, zeros), so a lane's A fragment
+// of a K step is one 16-byte load and a wave's is 1 KB of contiguous memory; each
+// lane reads its B fragment (8 consecutive moments of its column's source cell)
+// as one 16-byte load from the zero-padded BF16 moment copy.  No LDS in the K
+// loop; fragments of the next K step are loaded while the current one multiplies.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+template <int NCB, int RPW, bool PERS>
+__global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB, int KB32, M2LWork W) {
+  typedef float f4_t __attribute__((ext_vector_type(4)));
+  constexpr int BN = NCB * 16;
+  __shared__ int pid[BN];
+  const int total = W.total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, k8 = 8 * (lane >> 4);
+  int w = blockIdx.x;
+  do {
+  const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
+  const int item = x8 * q8 + min(x8, r8) + w / 8;
+  int lv = 0;
+  while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
+  const M2LLevelWork& Lw = W.lev[lv];
+  const int local = item - Lw.item0;
+  const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
+  const int32_t* __restrict__ tiles = Lw.tiles;
+  const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
+  const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
+  float* __restrict__ stage = static_cast<float*>(Lw.stage);
+  const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
+  if constexpr (PERS) __syncthreads();  // the previous item's readers of pid are done
+  const int rb0 = (rowblk * 4 + wave) * RPW;
+  if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
+  const uint4* brow[NCB];
+  bool blive[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int col = cb * 16 + (lane & 15);
+    blive[cb] = col < cnt;
+    brow[cb] = reinterpret_cast<const uint4*>(Lw.mom16 + (int64_t)src_by_slot[first + min(col, cnt - 1)] * Pp + k8);
+  }
+  const uint4* Ar[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+    Ar[r] = reinterpret_cast<const uint4*>(Lw.Uf) +
+            ((int64_t)slot * RB + min(rb0 + r, RB - 1)) * KB32 * 64 + lane;
+  f4_t acc[RPW][NCB];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+  uint4 fa[2][RPW], fb[2][NCB];
+  auto load = [&](int set, int s) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) fa[set][r] = Ar[r][(int64_t)s * 64];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) fb[set][cb] = brow[cb][4 * s];
+  };
+  auto products = [&](int set) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const uint4 bz = blive[cb] ? fb[set][cb] : uint4{0u, 0u, 0u, 0u};
+      const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, bz);
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fa[set][r]), bv,
+                                                             acc[r][cb], 0, 0, 0);
+    }
+  };
+  load(0, 0);
+  int s = 0;
+  for (; s + 2 <= KB32; s += 2) {
+    load(1, s + 1 < KB32 ? s + 1 : s);
+    products(0);
+    if (s + 2 < KB32) load(0, s + 2);
+    if (s + 1 < KB32) products(1);
+  }
+  if (s < KB32) products(0);
+  __syncthreads();  // pid written by the first BN threads
+#pragma unroll
+  for (int h = 0; h < RPW; ++h)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int p = pid[cb * 16 + (lane & 15)];
+      const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
+      if (p < 0) continue;
+      if ((GP & 3) == 0 && row0 + 3 < GP) {
+        *reinterpret_cast<f4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < GP) stage[(int64_t)p * GP + row0 + r] = acc[h][cb][r];
+    }
+    if constexpr (!PERS) break;
+    w += gridDim.x;
+  } while (w < total);
+}
+
+// Operators in the BF16 fragment order above (rows GP of each slot's GPsrc-row stack from row0).
+__global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int RB, int KB32,
+                                         const double* __restrict__ U, uint16_t* __restrict__ Uf) {
+  const int slot = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)RB * KB32 * 512;
+  if (idx >= per) return;
+  const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+  const int64_t blk = idx >> 9;
+  const int kb = (int)(blk % KB32), rb = (int)(blk / KB32);
+  const int row = rb * 16 + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + e;
+  const double v = (row < GP && col < P) ? U[((int64_t)slot * GPsrc + row0 + row) * P + col] : 0.0;
+  Uf[(int64_t)slot * per + idx] = bf16_rne(v);
+}
+
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
 // wave).  The variant and whether the launch is persistent are chosen by
 // timing (autotuning).
@@ -876,6 +1006,17 @@ static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int 
     case 9: m2l_direct_kernel<T, 2, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     case 10: m2l_direct_kernel<T, 4, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
     default: m2l_direct_kernel<T, 4, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+  }
+}
+
+// BF16 contexts use the tile shapes of variants 8 .. 11 (columns x rows per workgroup).
+template <bool PERS>
+static void launch_m2l_bf16_tile(int v, int grid, hipStream_t st, int Pp, int GP, int RB, int KB32, const M2LWork& W) {
+  switch (v) {
+    case 8: m2l_bf16_kernel<2, 2, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 9: m2l_bf16_kernel<2, 4, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 10: m2l_bf16_kernel<4, 2, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    default: m2l_bf16_kernel<4, 4, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
   }
 }
 
@@ -1258,7 +1399,7 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
 // launch does their near-future products.  choice = 2 * variant + persistent.
 static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   const int P = f->P, G = f->Gn;
-  const bool lo = f->prec == 1;
+  const bool lo = f->prec == 1, b16 = f->prec == 2;
   const int v = choice >> 1, persistent = choice & 1;
   const int rows = 64 * kVariantRpw[v];
   const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + rows - 1) / rows;
@@ -1275,7 +1416,9 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     Lw.src_by_slot = L.d_src_by_slot.p;
     Lw.mom = L.d_mom.p;
     Lw.mom32 = L.d_mom32.p;
+    Lw.mom16 = L.d_mom16.p;
     if (lo) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
+    else if (b16) { Lw.Uf = L.d_U16.p; Lw.stage = L.d_stage32.p; }
     else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
     Lw.item0 = total;
     total += Lw.ntiles * nrb;
@@ -1284,7 +1427,11 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   if (total == 0) return;
   const bool pers = persistent && total > f->persistent_grid;
   const int grid = pers ? f->persistent_grid : total;
-  if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
+  if (b16) {
+    const int KB32 = (P + 31) / 32;
+    if (pers) launch_m2l_bf16_tile<true>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+    else launch_m2l_bf16_tile<false>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+  } else if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
   else launch_m2l_variant<double>(v, pers, grid, st, P, G * P, RB, KB, W);
   TDBEM_HIP(hipGetLastError());
 }
@@ -1310,6 +1457,7 @@ static void launch_deriv_products(const Fmm* f, const FmmLevel& L, int d, hipStr
     Lw.src_by_slot = L.d_src_by_slot.p;
     Lw.mom = L.d_tm.p + (int64_t)j * L.ncell * Ps;
     Lw.mom32 = nullptr;
+    Lw.mom16 = nullptr;
     Lw.Uf = L.d_Ktf.p + (int64_t)kern * nslot * perk;
     Lw.stage = L.d_V.p + (int64_t)v * L.npair * Ps;
     Lw.item0 = total;
@@ -1361,10 +1509,11 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
       TDBEM_HIP(hipEventCreate(&e1));
     }
     float best = 1e30f;
-    int bestc = 2;  // 64 x 16 x 128, one item per workgroup
+    int bestc = f->prec == 2 ? 2 * M2L_FIRST_DIRECT : 2;  // 64 x 16 x 128 (BF16: 32 x 128), one item per workgroup
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
       if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
-      if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) continue;
+      if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec != 2) continue;
+      if ((c >> 1) < M2L_FIRST_DIRECT && f->prec == 2) continue;  // BF16: the four LDS-free shapes
       launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
       for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
@@ -1388,8 +1537,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
   if (o.p_s < 2 || o.p_s > MAXP || o.p_t < 2 || o.p_t > MAXP)
     throw Error(TDBEM_E_INVAL, "p_s and p_t must be in [2, 8]");
   if (o.p_t <= ctx->d) throw Error(TDBEM_E_INVAL, "p_t must exceed the B-spline order d");
-  if (o.m2l_prec != TDBEM_M2L_FP64 && o.m2l_prec != TDBEM_M2L_FP32)
-    throw Error(TDBEM_E_INVAL, "m2l_prec must be FP64 (0) or FP32 (1)");
+  if (o.m2l_prec != TDBEM_M2L_FP64 && o.m2l_prec != TDBEM_M2L_FP32 && o.m2l_prec != TDBEM_M2L_BF16)
+    throw Error(TDBEM_E_INVAL, "m2l_prec must be FP64 (0), FP32 (1) or BF16 (2)");
   Fmm* f = new Fmm();
   try {
     f->D = o.depth;
@@ -1398,6 +1547,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     f->pt = o.p_t;
     f->Ps = f->ps * f->ps * f->ps;
     f->P = f->Ps * f->pt;
+    f->Pp = (f->P + 31) / 32 * 32;
     cheb(f->ps, f->om_s);
     cheb(f->pt, f->om_t);
     f->Cd = 1.0 / (4.0 * M_PI * std::pow(ctx->cdt, ctx->d));
@@ -1539,6 +1689,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         L.d_mom32.alloc((size_t)L.ncell * P);
         TDBEM_HIP(hipMemsetAsync(L.d_mom32.p, 0, L.d_mom32.n * sizeof(float), st));
       }
+      if (f->prec == 2) {  // the padding columns P .. Pp-1 stay zero
+        L.d_mom16.alloc((size_t)L.ncell * f->Pp);
+        TDBEM_HIP(hipMemsetAsync(L.d_mom16.p, 0, L.d_mom16.n * sizeof(uint16_t), st));
+      }
       L.d_ring.alloc((size_t)f->R * L.ncell * P);
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
@@ -1547,7 +1701,15 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
         const int64_t per = (int64_t)RB * KB * 64;
         dim3 gf((unsigned)((per + 255) / 256), std::max(nslot, 1));
-        if (f->prec == 1) {
+        if (f->prec == 2) {
+          const int KB32 = (P + 31) / 32;
+          const int64_t per16 = (int64_t)RB * KB32 * 512;
+          L.d_U16.alloc((size_t)std::max(nslot, 1) * per16);
+          dim3 g16((unsigned)((per16 + 255) / 256), std::max(nslot, 1));
+          if (nslot > 0)
+            to_fragments_bf16_kernel<<<g16, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB32, L.d_U.p, L.d_U16.p);
+          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+        } else if (f->prec == 1) {
           L.d_U32.alloc((size_t)std::max(nslot, 1) * per);
           if (nslot > 0) to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB, L.d_U.p, L.d_U32.p);
           L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
@@ -1652,7 +1814,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     const int first = (beta + 1) % Ml == 0;
     p2m_kernel<<<L.ncell, ((f->Ps + 63) / 64) * 64, 0, st>>>(f->Ps, f->pt, first, f->Cd, tw, f->d_leaf_ptr.p,
                                                               f->d_leaf_elems.p, f->d_A.p, f->d_B.p, f->d_tau.p,
-                                                              f->d_sig.p, L.d_mom.p, L.d_mom32.p);
+                                                              f->d_sig.p, L.d_mom.p, L.d_mom32.p, L.d_mom16.p, f->Pp);
     TDBEM_HIP(hipGetLastError());
   }
   delete p2m_scope;
@@ -1679,7 +1841,8 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
       FmmLevel& Pl = f->lev[l - 1];
       ProfScope ps(ctx, K_M2M);
       m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
-                                                         L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p, Pl.d_mom32.p);
+                                                         L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p, Pl.d_mom32.p,
+                                                         Pl.d_mom16.p, f->Pp);
       TDBEM_HIP(hipGetLastError());
     }
     {
@@ -1707,7 +1870,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
         ProfScope ps(ctx, K_M2L_RED);
         dim3 g2(L.ncell, f->Gn, (P + 255) / 256);
         const int bs = std::min(256, ((P + 63) / 64) * 64);
-        if (f->prec == 1)
+        if (f->prec != 0)
           m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
                                                        L.d_ring.p);
         else
@@ -1748,7 +1911,8 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   for (int n = 1; n < f->D && n < 16; ++n) info->m2l_variant[n] = f->m2l_choice[n];
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
-    bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float);
+    bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float) +
+             (int64_t)f->lev[l].d_U16.n * sizeof(uint16_t);
   }
   info->m2l_matrix_bytes = bytes;
 }
@@ -1756,7 +1920,8 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
 int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
   Fmm* f = ctx->fmm;
   if (!f || n < 1 || n > f->D - 1 || n >= 16 || choice < 0 || choice >= 2 * M2L_VARIANTS) return TDBEM_E_INVAL;
-  if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0) return TDBEM_E_INVAL;
+  if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec != 2) return TDBEM_E_INVAL;
+  if ((choice >> 1) < M2L_FIRST_DIRECT && f->prec == 2) return TDBEM_E_INVAL;
   f->m2l_choice[n] = choice;
   return TDBEM_OK;
 }

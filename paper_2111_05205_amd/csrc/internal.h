@@ -144,6 +144,7 @@ struct tdbem_ctx {
   bool prof = false;
   uint32_t prof_mask = 0xffffffffu;  // categories bracketed while profiling
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
+  std::vector<hipEvent_t> ev_pool;  // events of collected brackets, reused (created once, destroyed with the context)
   double prof_ms[16] = {0};
   int64_t prof_cnt[16] = {0};
 };
@@ -159,9 +160,15 @@ struct ProfScope {
   int kind;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ProfScope(tdbem_ctx* ctx, int k) : c(ctx), kind(k) {
-    if (c->prof && ((c->prof_mask >> k) & 1u) && hipEventCreate(&e0) == hipSuccess &&
-        hipEventCreate(&e1) == hipSuccess)
-      (void)hipEventRecord(e0, c->stream);
+    if (c->prof && ((c->prof_mask >> k) & 1u) && take(e0) && take(e1)) (void)hipEventRecord(e0, c->stream);
+  }
+  bool take(hipEvent_t& e) {
+    if (!c->ev_pool.empty()) {
+      e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+      return true;
+    }
+    return hipEventCreate(&e) == hipSuccess;
   }
   ~ProfScope() {
     if (c->prof && e0 && e1) {

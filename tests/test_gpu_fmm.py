@@ -116,6 +116,34 @@ def test_fmm_fp32_m2l_products(s3):
     assert 1e-12 < e < 1e-4, e
 
 
+@pytest.mark.parametrize("pp", [3, 4])
+def test_fmm_bf16_m2l_products(pp):
+    """BF16 near-future products (operators and moments rounded to bf16, FP32 accumulation on
+    v_mfma_f32_16x16x32_bf16), derivative products and everything else FP64: every BF16 tile
+    shape, one item per workgroup and persistent, against the FP64 oracle FMM.  p = 3 gives
+    P = 81 (K padded to 96), p = 4 P = 256."""
+    P = _P()
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    R = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, pp, pp)
+    ns = tri.shape[0]
+    u = synth.random_history(ns, 24, seed=5)
+    q = synth.random_history(ns, 24, seed=6)
+    want = R.history_rhs(21, u, q)
+    dev = torch.device("cuda")
+    g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=pp, p_t=pp, m2l_prec=P.M2L_BF16, nt_max=32)
+    errs = {}
+    for choice in range(16, 24):
+        g.set_m2l_variant(1, choice)
+        g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
+        errs[choice] = _rel(g.fmm_eval(21).cpu().numpy(), want)
+    print("BF16 history sum vs FP64 oracle FMM:", errs)
+    assert all(1e-8 < e < 1e-2 for e in errs.values()), errs
+    with pytest.raises(P.TDBEMError):
+        g.set_m2l_variant(1, 2)  # the LDS tiles are FP32 / FP64 only
+    g.close()
+
+
 N_M2L_TILES = 12  # tdbem_info.m2l_variant: choice = 2 * tile + persistent
 
 
