@@ -141,6 +141,9 @@ typedef struct {
                            moments directly, no LDS or barrier in the K loop; BF16 contexts use only
                            these four shapes, with K steps of 32) */
   int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
+  int64_t m2l_dense_blocks[16]; /* per level: sum over interaction pairs of the near-future gaps evaluated as dense
+                                   P x P products (the wavefront crosses the pair's node set there; the other gaps
+                                   are zero at every node pair, or wavefront-free and evaluated in separable form) */
 } tdbem_info;
 
 /* Build a context: copies and validates the mesh (closed, consistently

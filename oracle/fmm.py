@@ -103,7 +103,12 @@ def _tensor3(v1, v2, v3):
 class ReferenceFMM:
     """History part of the MOT right-hand side with near pairs direct and far pairs by the FMM."""
 
-    def __init__(self, xyz, tri, c, dt, d, bie, depth, p_s, p_t, mu=0, m2l="alg1", bc=None, src_ext=None):
+    def __init__(self, xyz, tri, c, dt, d, bie, depth, p_s, p_t, mu=0, m2l="alg1", bc=None, src_ext=None,
+                 near_round=None):
+        """near_round: None, or a function applied to both factors (moments and operator) of
+        every near-future product (eq. m2l_near) before it is formed, e.g. rounding to a
+        lower precision; the derivative products stay exact."""
+        self.near_round = near_round
         self.geom = g = Geometry(xyz, tri)
         self.bc = bc
         self._src_ext = src_ext
@@ -393,10 +398,12 @@ class ReferenceFMM:
         ring, Lp, aux = self.ring[lev], self.Lp[lev], self.aux[lev]
         nc = len(self.cells[lev])
         Dp = np.zeros((d + 1, nc, self.P))
+        rnd = self.near_round if self.near_round is not None else (lambda a: a)
         for o, (oi, si) in self.il_by_off[lev].items():
             X = Mk[si]
+            Xn = rnd(X)
             for l in range(1, mu + 2):
-                np.add.at(ring[(k + l) % R], oi, X @ self.m2l_matrix(lev, o, gap=l).T)
+                np.add.at(ring[(k + l) % R], oi, Xn @ rnd(self.m2l_matrix(lev, o, gap=l)).T)
             for p in range(1, d + 1):
                 np.add.at(Dp[p], oi, X @ self.m2l_matrix(lev, o, deriv=p).T)
         T = self.c * self.M[lev] * self.dt
@@ -431,8 +438,9 @@ class ReferenceFMM:
         for kk, Mk in self.mom_done[lev].items():
             if kk >= k:
                 continue
+            rnd = self.near_round if self.near_round is not None else (lambda a: a)
             for o, (oi, si) in self.il_by_off[lev].items():
-                np.add.at(L, oi, Mk[si] @ self.m2l_matrix(lev, o, gap=k - kk).T)
+                np.add.at(L, oi, rnd(Mk[si]) @ rnd(self.m2l_matrix(lev, o, gap=k - kk)).T)
         if lev > 2:
             kp = k // 2
             L += self._l2l_apply(lev - 1, self.local(lev - 1, kp), kp)[k]

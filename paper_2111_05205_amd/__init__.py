@@ -129,10 +129,10 @@ class TDBEM:
             self._L.tdbem_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be finalising: leave the
         # device memory to the process exit instead of calling into it
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -154,6 +154,7 @@ class TDBEM:
         out = {k: getattr(i, k) for k, _ in N.Info._fields_}
         out["il_pairs"] = list(i.il_pairs)
         out["m2l_variant"] = list(i.m2l_variant)
+        out["m2l_dense_blocks"] = list(i.m2l_dense_blocks)
         return out
 
     def reset(self):

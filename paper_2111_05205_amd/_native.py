@@ -47,7 +47,8 @@ class Info(ctypes.Structure):
                 ("p_s", ctypes.c_int), ("p_t", ctypes.c_int), ("mu", ctypes.c_int), ("m_leaf", ctypes.c_int),
                 ("near_pairs", ctypes.c_int64), ("near_coefs", ctypes.c_int64), ("a_nnz", ctypes.c_int64),
                 ("il_pairs", ctypes.c_int64 * 16), ("m2l_matrix_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
-                ("m2l_variant", ctypes.c_int * 16), ("gmres_workgroups", ctypes.c_int)]
+                ("m2l_variant", ctypes.c_int * 16), ("gmres_workgroups", ctypes.c_int),
+                ("m2l_dense_blocks", ctypes.c_int64 * 16)]
 
 
 PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other", "mlp",

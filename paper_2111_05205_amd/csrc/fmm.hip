@@ -78,7 +78,18 @@ struct FmmLevel {
   DevBuf<float> d_U32, d_stage32;           // FP32 (mixed precision): the same
   DevBuf<double> d_Ktf;                     // derivative products' spatial kernels r^{-1} (and r, d = 3), fragment order
   DevBuf<double> d_tm, d_tsum;              // time moments [j][cell][b] and their node sums [j][cell]
-  DevBuf<double> d_V;                       // derivative pair products [product][pair][Ps]
+  DevBuf<double> d_V;                       // separable pair products [product][pair][Ps]
+  // Per slot (offset): the near-future gaps gf .. g0-1 have node pairs on both sides of the
+  // wavefront and are dense operator blocks; gaps before gf are zero at every node pair,
+  // gaps from g0 on are wavefront-free (separable).
+  std::vector<int> gf, g0;
+  DevBuf<int64_t> d_uoff;                   // first operator element of each slot's dense blocks
+  DevBuf<int32_t> d_srows, d_soff;          // dense rows of each slot; their first row in a pair's products
+  DevBuf<int32_t> d_items[3][2];            // (tile, row block) work items by tile width (128/64/32) and rows (128/256)
+  int nitems[3][2] = {};
+  DevBuf<int32_t> d_items_sep;              // (tile, 0) for every 32-column tile (separable products)
+  DevBuf<int32_t> d_pair_gr;                // per interaction pair (target order): gf | g0 << 16
+  int64_t dense_blocks = 0;                 // sum over interaction pairs of their dense blocks
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_dp;
   DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
   DevBuf<uint16_t> d_U16, d_mom16;          // BF16 M2L: operators in fragment order; moments [cell][Pp] (zero padded)
@@ -176,9 +187,9 @@ __global__ void m2l_matrix_kernel(int ps, int pt, int P, int G, int mu, int d, d
   U[((int64_t)slot * G + g) * P * P + idx] = ipow(arg, d) / r;
 }
 
-// Spatial kernels of the derivative products between target node a and source
-// node b of a cell pair at offset `slot` (cell half side hs): K[0] = 1/r and,
-// for d = 3, K[1] = r; row-major [kernel][slot][a][b] (converted to MFMA
+// Spatial kernels of the separable products between target node a and source
+// node b of a cell pair at offset `slot` (cell half side hs): K[0] = 1/r, K[1] = r
+// (d >= 2), K[2] = r^2 (d = 3); row-major [kernel][slot][a][b] (converted to MFMA
 // fragment order afterwards).
 __global__ void m2l_spatial_kernel(int ps, int nk, double hs, NodeSet nodes, const int32_t* __restrict__ slot_off,
                                    int nslot, double* __restrict__ Kt) {
@@ -196,6 +207,7 @@ __global__ void m2l_spatial_kernel(int ps, int nk, double hs, NodeSet nodes, con
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
   Kt[(int64_t)slot * Ps * Ps + idx] = 1.0 / r;
   if (nk > 1) Kt[((int64_t)nslot + slot) * Ps * Ps + idx] = r;
+  if (nk > 2) Kt[((int64_t)2 * nslot + slot) * Ps * Ps + idx] = r * r;
 }
 
 // P2M / L2P element tables on the device.  Triangle quadrature: collapsed
@@ -494,7 +506,37 @@ struct M2LLevelWork {
   void* stage;                   // T per-pair products
   int ntiles;
   int item0;                     // first work item of this level
+  // Per-slot operator stacks (NULL: every slot has GP rows at slot * per, staged from row 0,
+  // and item i is (tile i % ntiles, row block i / ntiles)):
+  const int32_t* items;          // (tile, row block) per work item
+  const int64_t* uoff;           // first operator element of each slot
+  const int32_t* srows;          // operator rows of each slot
+  const int32_t* soff;           // row of a pair's staged products where the slot's rows start
 };
+
+// A work item's column tile and row block, and the operator stack of its slot.
+struct ItemGeom { int tile, rowblk, rows, soff; int64_t uoff; };
+__device__ inline ItemGeom item_geom(const M2LLevelWork& Lw, int local, int GP, int64_t per) {
+  ItemGeom g;
+  if (Lw.items) {
+    g.tile = Lw.items[2 * local];
+    g.rowblk = Lw.items[2 * local + 1];
+  } else {
+    g.tile = local % Lw.ntiles;
+    g.rowblk = local / Lw.ntiles;
+  }
+  const int slot = Lw.tiles[3 * g.tile];
+  if (Lw.uoff) {
+    g.uoff = Lw.uoff[slot];
+    g.rows = Lw.srows[slot];
+    g.soff = Lw.soff[slot];
+  } else {
+    g.uoff = (int64_t)slot * per;
+    g.rows = GP;
+    g.soff = 0;
+  }
+  return g;
+}
 struct M2LWork {
   M2LLevelWork lev[M2L_MAXLEV];
   int nlev;
@@ -536,14 +578,16 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
   while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
   const M2LLevelWork& Lw = W.lev[lv];
   const int local = item - Lw.item0;
-  const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
+  const int64_t per = (int64_t)RB * KB * 64;
+  const ItemGeom ig = item_geom(Lw, local, GP, per);
+  const int tile = ig.tile, rowblk = ig.rowblk, rows = ig.rows, RBs = (rows + 15) >> 4;
   const int32_t* __restrict__ tiles = Lw.tiles;
   const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
   const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
   const T* __restrict__ Uf = static_cast<const T*>(Lw.Uf);
   const double* __restrict__ mom = Lw.mom;
-  T* __restrict__ stage = static_cast<T*>(Lw.stage);
-  const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
+  T* __restrict__ stage = static_cast<T*>(Lw.stage) + ig.soff;
+  const int first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
   if constexpr (PERS) __syncthreads();  // the previous item's readers of src / pid / Bs are done
   const int rb0 = (rowblk * 4 + wave) * RPW;             // this wave: row blocks rb0 .. rb0+RPW-1
   if (tid < BN) {
@@ -552,8 +596,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
     src[tid] = tid < cnt ? src_by_slot[first + tid] : -1;
   }
   __syncthreads();
-  const int64_t per = (int64_t)RB * KB * 64;
-  // Row blocks past the operator's end (rb >= RB) read the last block again:
+  // Row blocks past the operator's end (rb >= RBs) read the last block again:
   // their products are never stored.  k blocks past KB likewise read the last
   // block and meet zero moments, so every load below is unconditional.
   typedef typename Vec16<T>::type vec_t;
@@ -562,7 +605,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
   const vec_t* Ar[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r)
-    Ar[r] = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0 + r, RB - 1) * KB) * 64) + lane;
+    Ar[r] = reinterpret_cast<const vec_t*>(Uf + ig.uoff + ((int64_t)min(rb0 + r, RBs - 1) * KB) * 64) + lane;
   const int ncb = (cnt + 15) >> 4;                                             // live column blocks
   acc_t acc[RPW][NCB];
 #pragma unroll
@@ -674,7 +717,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int pr = pid[cb * 16 + 4 * r + (lane >> 4)];
-          if (pr >= 0 && row < GP) stage[(int64_t)pr * GP + row] = acc[h][cb][r];
+          if (pr >= 0 && row < rows) stage[(int64_t)pr * GP + row] = acc[h][cb][r];
         }
         continue;
       }
@@ -683,7 +726,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
         // FP32 output: the lane holds rows 4 (lane/16) .. +3 of its pair, so write
         // them as one 16-byte vector (the four lanes of a pair: 64 contiguous bytes)
         const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
-        if (p >= 0 && (GP & 3) == 0 && row0 + 3 < GP) {
+        if (p >= 0 && ((GP | ig.soff) & 3) == 0 && row0 + 3 < rows) {
           *reinterpret_cast<flt4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
           continue;
         }
@@ -691,7 +734,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = (rb0 + h) * 16 + Mfma<T>::row(lane, r);
-        if (p >= 0 && row < GP) stage[(int64_t)p * GP + row] = acc[h][cb][r];
+        if (p >= 0 && row < rows) stage[(int64_t)p * GP + row] = acc[h][cb][r];
       }
     }
     if constexpr (!PERS) break;
@@ -732,14 +775,16 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
   while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
   const M2LLevelWork& Lw = W.lev[lv];
   const int local = item - Lw.item0;
-  const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
+  const int64_t per = (int64_t)RB * KB * 64;
+  const ItemGeom ig = item_geom(Lw, local, GP, per);
+  const int tile = ig.tile, rowblk = ig.rowblk, rows = ig.rows, RBs = (rows + 15) >> 4;
   const int32_t* __restrict__ tiles = Lw.tiles;
   const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
   const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
   const T* __restrict__ Uf = static_cast<const T*>(Lw.Uf);
   const double* __restrict__ mom = Lw.mom;
-  T* __restrict__ stage = static_cast<T*>(Lw.stage);
-  const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
+  T* __restrict__ stage = static_cast<T*>(Lw.stage) + ig.soff;
+  const int first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
   if constexpr (PERS) __syncthreads();  // the previous item's readers of pid are done
   const int rb0 = (rowblk * 4 + wave) * RPW;
   if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
@@ -756,11 +801,10 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
     blive[cb] = col < cnt;
     brow[cb] = mbase + (int64_t)src_by_slot[first + min(col, cnt - 1)] * P;
   }
-  const int64_t per = (int64_t)RB * KB * 64;
   const vec_t* Ar[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r)
-    Ar[r] = reinterpret_cast<const vec_t*>(Uf + (int64_t)slot * per + ((int64_t)min(rb0 + r, RB - 1) * KB) * 64) + lane;
+    Ar[r] = reinterpret_cast<const vec_t*>(Uf + ig.uoff + ((int64_t)min(rb0 + r, RBs - 1) * KB) * 64) + lane;
   const int ncb = (cnt + 15) >> 4;
   acc_t acc[RPW][NCB];
 #pragma unroll
@@ -843,14 +887,14 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int pr = pid[cb * 16 + 4 * r + (lane >> 4)];
-          if (pr >= 0 && row < GP) stage[(int64_t)pr * GP + row] = acc[h][cb][r];
+          if (pr >= 0 && row < rows) stage[(int64_t)pr * GP + row] = acc[h][cb][r];
         }
         continue;
       }
       const int p = pid[cb * 16 + (lane & 15)];
       if constexpr (sizeof(T) == 4) {
         const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
-        if (p >= 0 && (GP & 3) == 0 && row0 + 3 < GP) {
+        if (p >= 0 && ((GP | ig.soff) & 3) == 0 && row0 + 3 < rows) {
           *reinterpret_cast<flt4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
           continue;
         }
@@ -858,7 +902,7 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = (rb0 + h) * 16 + Mfma<T>::row(lane, r);
-        if (p >= 0 && row < GP) stage[(int64_t)p * GP + row] = acc[h][cb][r];
+        if (p >= 0 && row < rows) stage[(int64_t)p * GP + row] = acc[h][cb][r];
       }
     }
     if constexpr (!PERS) break;
@@ -893,12 +937,13 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
   while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
   const M2LLevelWork& Lw = W.lev[lv];
   const int local = item - Lw.item0;
-  const int tile = local % Lw.ntiles, rowblk = local / Lw.ntiles;
+  const ItemGeom ig = item_geom(Lw, local, GP, (int64_t)RB * KB32 * 512);
+  const int tile = ig.tile, rowblk = ig.rowblk, rows = ig.rows, RBs = (rows + 15) >> 4;
   const int32_t* __restrict__ tiles = Lw.tiles;
   const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
   const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
-  float* __restrict__ stage = static_cast<float*>(Lw.stage);
-  const int slot = tiles[3 * tile], first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
+  float* __restrict__ stage = static_cast<float*>(Lw.stage) + ig.soff;
+  const int first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
   if constexpr (PERS) __syncthreads();  // the previous item's readers of pid are done
   const int rb0 = (rowblk * 4 + wave) * RPW;
   if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
@@ -913,8 +958,8 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
   const uint4* Ar[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r)
-    Ar[r] = reinterpret_cast<const uint4*>(Lw.Uf) +
-            ((int64_t)slot * RB + min(rb0 + r, RB - 1)) * KB32 * 64 + lane;
+    Ar[r] = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Lw.Uf) + ig.uoff) +
+            (int64_t)min(rb0 + r, RBs - 1) * KB32 * 64 + lane;
   f4_t acc[RPW][NCB];
 #pragma unroll
   for (int i = 0; i < RPW; ++i)
@@ -955,13 +1000,13 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
       const int p = pid[cb * 16 + (lane & 15)];
       const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
       if (p < 0) continue;
-      if ((GP & 3) == 0 && row0 + 3 < GP) {
+      if (((GP | ig.soff) & 3) == 0 && row0 + 3 < rows) {
         *reinterpret_cast<f4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
         continue;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (row0 + r < GP) stage[(int64_t)p * GP + row0 + r] = acc[h][cb][r];
+        if (row0 + r < rows) stage[(int64_t)p * GP + row0 + r] = acc[h][cb][r];
     }
     if constexpr (!PERS) break;
     w += gridDim.x;
@@ -1044,100 +1089,141 @@ __device__ inline double sum_pairs(const ST* __restrict__ sp, int64_t ld, int p0
 }
 
 // Reduce the staged near-future products per target cell: grid (ncell, mu+1,
-// ceil(P/256)); block g adds its sum into the local L_{k+g+1}.  Each thread
-// sums one coefficient over the cell's interaction pairs (independent loads).
+// ceil(P/256)); block g adds its sum into the local L_{k+g+1}.  Only the pairs
+// whose offset has a dense block at gap g+1 (gf <= g+1 < g0, pair_gr = gf |
+// g0 << 16) contribute; the condition is the same for every thread of a block.
 template <class ST>
 __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Gn, int R, int k,
                                                          const int32_t* __restrict__ il_ptr,
+                                                         const int32_t* __restrict__ pair_gr,
                                                          const ST* __restrict__ stage, int ncell,
                                                          double* __restrict__ ring) {
-  const int O = blockIdx.x, g = blockIdx.y;
+  const int O = blockIdx.x, g = blockIdx.y, gap = g + 1;
   const int a = blockIdx.z * blockDim.x + threadIdx.x;
   if (a >= P) return;
   const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
-  const double s = sum_pairs(stage + (int64_t)g * P + a, (int64_t)Gn * P, p0, p1);
-  ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s;
+  const ST* sp = stage + (int64_t)g * P + a;
+  const int64_t ld = (int64_t)Gn * P;
+  double s0 = 0.0, s1 = 0.0;
+  int p = p0;
+  for (; p + 1 < p1; p += 2) {
+    const int r0 = pair_gr[p], r1 = pair_gr[p + 1];
+    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) s0 += (double)sp[(int64_t)p * ld];
+    if (gap >= (r1 & 0xffff) && gap < (r1 >> 16)) s1 += (double)sp[(int64_t)(p + 1) * ld];
+  }
+  if (p < p1) {
+    const int r0 = pair_gr[p];
+    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) s0 += (double)sp[(int64_t)p * ld];
+  }
+  ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s0 + s1;
 }
 
 // Time moments of the completed source interval's moments, per cell:
-// S[j][cell][b] = sum_n (ht w_n)^j M[cell][b + Ps n], j = 0..d-1 (ht w_n: the
+// S[j][cell][b] = sum_n (ht w_n)^j M[cell][b + Ps n], j = 0..d (ht w_n: the
 // source node's time from the interval centre), and their node sums
 // Ssum[j][cell] = sum_b S[j][cell][b].  One 64-lane wave per cell.
 __global__ __launch_bounds__(64) void m2l_time_moments_kernel(int Ps, int pt, int d, double ht, NodeSet nodes,
                                                               int ncell, const double* __restrict__ mom,
                                                               double* __restrict__ S, double* __restrict__ Ssum) {
   const int cell = blockIdx.x, lane = threadIdx.x;
-  double part[3] = {0.0, 0.0, 0.0};
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = lane; b < Ps; b += 64) {
     const double* M = mom + (int64_t)cell * Ps * pt + b;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int n = 0; n < pt; ++n) {
       const double v = M[(int64_t)Ps * n], tn = ht * nodes.t[n];
       double tp = 1.0;
-      for (int j = 0; j < d; ++j) { acc[j] += tp * v; tp *= tn; }
+      for (int j = 0; j <= d; ++j) { acc[j] += tp * v; tp *= tn; }
     }
-    for (int j = 0; j < d; ++j) {
+    for (int j = 0; j <= d; ++j) {
       S[((int64_t)j * ncell + cell) * Ps + b] = acc[j];
       part[j] += acc[j];
     }
   }
-  for (int j = 0; j < d; ++j) {
+  for (int j = 0; j <= d; ++j) {
     double v = part[j];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (lane == 0) Ssum[(int64_t)j * ncell + cell] = v;
   }
 }
 
-// Derivative products of Algorithm 1, L^{(p)}_{k+mu+1,k} = sum over the cell's
-// interaction pairs of U^{(p)} M (eq. L_l,k), p = 1..d, in FP64, through the
-// separable form of the operator: its entries are C(d,p) (c (A_m - B_n) - r_ab)^q / r_ab
-// with q = d - p, A_m = T0 + ht w_m (target node time), B_n = ht w_n (source
-// node time), T0 = the centre distance of the expansion interval, so by the
-// trinomial expansion
-//   (U^{(p)} M)[a, m] = C(d,p) sum_{i+j+k=q} q!/(i! j! k!) (c A_m)^i (-c)^j (-1)^k V_{k,j}[a],
-//   V_{k,j}[a] = sum_b r_ab^{k-1} S_j[b],   S_j[b] = sum_n B_n^j M[b, n].
-// Exact (no approximation): the pair products are P_s x P_s spatial kernels
-// times d time moments (matrix cores, FP64, per offset like the near-future
-// products) instead of P x P blocks.  V_{1,j} (kernel r^0) is the node sum of
-// S_j.  This kernel sums the pair products per target cell and expands them
-// in time: one workgroup per cell, thread per target node a.
-// V: [product][pair][Ps], products (k, j) = (0, 0) .. (0, d-1), then (2, 0) for d = 3.
-__global__ void m2l_deriv_expand_kernel(int Ps, int pt, int d, double c, double T0, double ht, NodeSet nodes,
-                                        int ncell, int64_t npair, const int32_t* __restrict__ il_ptr,
-                                        const int32_t* __restrict__ il_src, const double* __restrict__ V,
-                                        const double* __restrict__ Ssum, double* __restrict__ dp) {
+// Separable part of M2L.  Wherever c (t - s) - r > 0 at every node pair of an
+// offset's cell pair and time gap, the operator entry there is the polynomial
+// (c (A_m - B_n) - r_ab)^d / r_ab (no truncation at any node): A_m the target
+// node time, B_n = ht w_n the source node time, both from the source interval's
+// centre.  The trinomial expansion then gives
+//   (U M)[a, m] = sum_{i+j+k=q} q!/(i! j! k!) (c A_m)^i (-c)^j (-1)^k V_{k,j}[a],   q = d,
+//   V_{k,j}[a] = sum_b r_ab^{k-1} S_j[b],   S_j[b] = sum_n B_n^j M[b, n],
+// with the same V for every such gap, and the derivative products of Algorithm 1,
+// L^{(p)}_{k+mu+1,k} = U^{(p)} M (eq. L_l,k; entries C(d,p) (c (A_m - B_n) - r_ab)^{d-p} / r_ab
+// at the expansion gap mu+1), follow from the same V with q = d - p.  This is the
+// interpolated operator itself, factored: no approximation beyond the paper's.
+// The pair products V_{0,j} = K_{1/r} S_j, V_{2,j} = K_r S_j, V_{3,j} = K_{r^2} S_j
+// run on the FP64 matrix cores (launch_sep_products); V_{1,j} (kernel r^0) is the
+// node sum of S_j.  This kernel, one workgroup per target cell and a thread per
+// target node a, walks the near-future gaps g = 1 .. mu+1 in order, adds the V of
+// the pairs whose first wavefront-free gap g0 is g, and adds the expansion of the
+// running sum into L_{k+g}; after gap mu+1 every pair is in, and the sum gives the
+// derivative products.  FP64 throughout.
+// V: [product][pair][Ps] in the order (0, 0..d), (2, 0..d-2), (3, 0..d-3).
+__device__ inline int sep_vidx(int k, int j, int d) {
+  return k == 0 ? j : k == 2 ? d + 1 + j : d + 1 + (d - 1) + j;
+}
+
+__device__ inline double sep_expand(int q, int d, double cA, double c, const double (&Wc)[4][4]) {
+  double val = 0.0;
+  for (int k = 0; k <= q; ++k)
+    for (int j = 0; j + k <= q; ++j) {
+      const int i = q - j - k;
+      double coef = 1.0;  // q! / (i! j! k!)
+      for (int t = 2; t <= q; ++t) coef *= t;
+      for (int t = 2; t <= i; ++t) coef /= t;
+      for (int t = 2; t <= j; ++t) coef /= t;
+      for (int t = 2; t <= k; ++t) coef /= t;
+      double term = coef * ((j + k) & 1 ? -1.0 : 1.0);
+      for (int t = 0; t < i; ++t) term *= cA;
+      for (int t = 0; t < j; ++t) term *= c;
+      val += term * Wc[k][j];
+    }
+  (void)d;
+  return val;
+}
+
+__global__ void m2l_sep_expand_kernel(int Ps, int pt, int d, int mu, int R, int ks, double c, double dt, int Ml,
+                                      double ht, NodeSet nodes, int ncell, int64_t npair,
+                                      const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ il_src,
+                                      const int32_t* __restrict__ pair_gr, const double* __restrict__ V,
+                                      const double* __restrict__ Ssum, double* __restrict__ ring,
+                                      double* __restrict__ dp) {
   const int O = blockIdx.x;
   const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
   const int P = Ps * pt;
-  double vc[3] = {0.0, 0.0, 0.0};  // V_{1,j}: node sums, the same for every a
-  for (int p = p0; p < p1; ++p)
-    for (int j = 0; j + 1 < d; ++j) vc[j] += Ssum[(int64_t)j * ncell + il_src[p]];
   for (int a = threadIdx.x; a < Ps; a += blockDim.x) {
-    double W[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int j = 0; j < d; ++j) W[0][j] = sum_pairs(V + (int64_t)j * npair * Ps + a, Ps, p0, p1);
-    if (d >= 3) W[2][0] = sum_pairs(V + (int64_t)d * npair * Ps + a, Ps, p0, p1);
-    for (int j = 0; j + 1 < d; ++j) W[1][j] = vc[j];
+    double Wc[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    int in = 0;  // pairs added so far (the same for every thread)
+    for (int g = 1; g <= mu + 1; ++g) {
+      for (int p = p0; p < p1; ++p) {
+        if ((pair_gr[p] >> 16) != g) continue;
+        ++in;
+        for (int j = 0; j <= d; ++j) Wc[0][j] += V[((int64_t)sep_vidx(0, j, d) * npair + p) * Ps + a];
+        for (int j = 0; j + 1 <= d; ++j) Wc[1][j] += Ssum[(int64_t)j * ncell + il_src[p]];
+        for (int j = 0; j + 2 <= d; ++j) Wc[2][j] += V[((int64_t)sep_vidx(2, j, d) * npair + p) * Ps + a];
+        for (int j = 0; j + 3 <= d; ++j) Wc[3][j] += V[((int64_t)sep_vidx(3, j, d) * npair + p) * Ps + a];
+      }
+      if (in == 0) continue;
+      double* L = ring + ((int64_t)((ks + g) % R) * ncell + O) * P + a;
+      for (int m = 0; m < pt; ++m) {
+        const double cA = c * ((g * (double)Ml + 1.0) * dt + ht * nodes.t[m]);
+        L[(int64_t)Ps * m] += sep_expand(d, d, cA, c, Wc);
+      }
+    }
+    // derivative products at the expansion gap mu+1: every pair is in Wc
     for (int pp = 1; pp <= d; ++pp) {
-      const int q = d - pp;
       double binom = 1.0;
       for (int t = 0; t < pp; ++t) binom = binom * (d - t) / (t + 1);
       for (int m = 0; m < pt; ++m) {
-        const double cA = c * (T0 + ht * nodes.t[m]);
-        double val = 0.0;
-        for (int k = 0; k <= q; ++k)
-          for (int j = 0; j + k <= q; ++j) {
-            const int i = q - j - k;
-            double coef = 1.0;  // q! / (i! j! k!)
-            for (int t = 2; t <= q; ++t) coef *= t;
-            for (int t = 2; t <= i; ++t) coef /= t;
-            for (int t = 2; t <= j; ++t) coef /= t;
-            for (int t = 2; t <= k; ++t) coef /= t;
-            double term = coef * ((j + k) & 1 ? -1.0 : 1.0);
-            for (int t = 0; t < i; ++t) term *= cA;
-            for (int t = 0; t < j; ++t) term *= c;
-            val += term * W[k][j];
-          }
-        dp[((int64_t)(pp - 1) * ncell + O) * P + a + (int64_t)Ps * m] = binom * val;
+        const double cA = c * (((mu + 1) * (double)Ml + 1.0) * dt + ht * nodes.t[m]);
+        dp[((int64_t)(pp - 1) * ncell + O) * P + a + (int64_t)Ps * m] = binom * sep_expand(d - pp, d, cA, c, Wc);
       }
     }
   }
@@ -1397,18 +1483,20 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
 
 // Levels D, D-1, ..., D-n+1 end a source interval together (n = 1..D-1): one
 // launch does their near-future products.  choice = 2 * variant + persistent.
+static int cols_index(int cols) { return cols == 128 ? 0 : cols == 64 ? 1 : 2; }
+
 static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   const int P = f->P, G = f->Gn;
   const bool lo = f->prec == 1, b16 = f->prec == 2;
   const int v = choice >> 1, persistent = choice & 1;
   const int rows = 64 * kVariantRpw[v];
-  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P), nrb = (G * P + rows - 1) / rows;
-  const int cols = kVariantCols[v];
+  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
+  const int cols = kVariantCols[v], ci = cols_index(cols), ri = rows == 128 ? 0 : 1;
   M2LWork W{};
   int total = 0;
   for (int l = f->D; l > f->D - n && l >= 2; --l) {
     const FmmLevel& L = f->lev[l];
-    if (L.npair == 0) continue;
+    if (L.npair == 0 || L.nitems[ci][ri] == 0) continue;
     M2LLevelWork& Lw = W.lev[W.nlev++];
     Lw.ntiles = cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32;
     Lw.tiles = cols == 128 ? L.d_tiles128.p : cols == 64 ? L.d_tiles64.p : L.d_tiles32.p;
@@ -1420,8 +1508,12 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     if (lo) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
     else if (b16) { Lw.Uf = L.d_U16.p; Lw.stage = L.d_stage32.p; }
     else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
+    Lw.items = L.d_items[ci][ri].p;
+    Lw.uoff = L.d_uoff.p;
+    Lw.srows = L.d_srows.p;
+    Lw.soff = L.d_soff.p;
     Lw.item0 = total;
-    total += Lw.ntiles * nrb;
+    total += L.nitems[ci][ri];
   }
   W.total = total;
   if (total == 0) return;
@@ -1436,21 +1528,25 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   TDBEM_HIP(hipGetLastError());
 }
 
-// Derivative pair products of one level (see m2l_deriv_expand_kernel):
-// V_{0,j} = K_{1/r} S_j (j = 0..d-1) and, for d = 3, V_{2,0} = K_r S_0, FP64 on
-// the matrix cores with the near-future products' tiles (32 pairs of one offset,
+// Separable pair products of one level (see m2l_sep_expand_kernel):
+// V_{0,j} = K_{1/r} S_j, V_{2,j} = K_r S_j, V_{3,j} = K_{r^2} S_j, FP64 on the
+// matrix cores with the near-future products' tiles (32 pairs of one offset,
 // LDS-staged time moments), each product a "level" of one launch.
-static void launch_deriv_products(const Fmm* f, const FmmLevel& L, int d, hipStream_t st) {
+static void launch_sep_products(const Fmm* f, const FmmLevel& L, int d, hipStream_t st) {
   const int Ps = f->Ps, nslot = (int)L.slot_off.size();
   const int RBk = (Ps + 15) / 16, KBk = m2l_kblocks(Ps);
   const int64_t perk = (int64_t)RBk * KBk * 64;
-  const int nv = d + (d >= 3 ? 1 : 0);
   const int nrb = (Ps + 127) / 128;  // 128 operator rows per workgroup (tile 32 x 16 x 128)
   M2LWork W{};
   int total = 0;
+  // products in the order of sep_vidx: (K_{1/r}, S_0..S_d), (K_r, S_0..S_{d-2}), (K_{r^2}, S_0..S_{d-3})
+  int vk[8], vj[8], nv = 0;
+  for (int j = 0; j <= d; ++j) { vk[nv] = 0; vj[nv++] = j; }
+  for (int j = 0; j + 2 <= d; ++j) { vk[nv] = 1; vj[nv++] = j; }
+  for (int j = 0; j + 3 <= d; ++j) { vk[nv] = 2; vj[nv++] = j; }
   for (int v = 0; v < nv; ++v) {
     M2LLevelWork& Lw = W.lev[W.nlev++];
-    const int j = v < d ? v : 0, kern = v < d ? 0 : 1;
+    const int j = vj[v], kern = vk[v];
     Lw.ntiles = L.ntiles32;
     Lw.tiles = L.d_tiles32.p;
     Lw.pairs_by_slot = L.d_pairs_by_slot.p;
@@ -1482,13 +1578,9 @@ static std::mutex g_tune_mu;
 static std::map<M2LKey, int> g_tune_table;
 
 static int m2l_work_items(const Fmm* f, int n, int v) {
-  const int cols = kVariantCols[v], rows = 64 * kVariantRpw[v];
-  const int nrb = (f->Gn * f->P + rows - 1) / rows;
+  const int ci = cols_index(kVariantCols[v]), ri = kVariantRpw[v] == 2 ? 0 : 1;
   int total = 0;
-  for (int l = f->D; l > f->D - n && l >= 2; --l) {
-    const FmmLevel& L = f->lev[l];
-    if (L.npair) total += (cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32) * nrb;
-  }
+  for (int l = f->D; l > f->D - n && l >= 2; --l) total += f->lev[l].nitems[ci][ri];
   return total;
 }
 
@@ -1529,6 +1621,85 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+}
+
+// For every slot (offset) of level l: gf, the first near-future gap with a node
+// pair past the wavefront (c (t - s) - r > 0), and g0, the first gap with every
+// node pair past it, over the same node coordinates as m2l_matrix_kernel; then
+// the work items of the dense products (each slot's gaps gf .. g0-1), the per-pair
+// gap ranges in target order, and the per-slot row tables.
+static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector<int32_t>& tiles128,
+                          const std::vector<int32_t>& tiles64, const std::vector<int32_t>& tiles32, hipStream_t st) {
+  FmmLevel& L = f->lev[l];
+  const int nslot = (int)L.slot_off.size(), ps = f->ps, Ps = f->Ps, P = f->P;
+  const double hs = hs_of(f, l), Ml = (double)f->m_leaf * (1 << (f->D - l)), ht = Ml * ctx->dt / 2.0;
+  double dmin = 1e300, dmax = -1e300;
+  for (int m = 0; m < f->pt; ++m)
+    for (int n = 0; n < f->pt; ++n) {
+      dmin = std::min(dmin, f->om_t[m] - f->om_t[n]);
+      dmax = std::max(dmax, f->om_t[m] - f->om_t[n]);
+    }
+  L.gf.assign(nslot, 1);
+  L.g0.assign(nslot, 1);
+  for (int sl = 0; sl < nslot; ++sl) {
+    double rmin = 1e300, rmax = 0.0;
+    const auto& o = L.slot_off[sl];
+    for (int a = 0; a < Ps; ++a)
+      for (int b = 0; b < Ps; ++b) {
+        const int aa[3] = {a % ps, (a / ps) % ps, a / (ps * ps)}, bb[3] = {b % ps, (b / ps) % ps, b / (ps * ps)};
+        double r2 = 0.0;
+        for (int q = 0; q < 3; ++q) {
+          const double dq = 2.0 * hs * o[q] + hs * (f->om_s[bb[q]] - f->om_s[aa[q]]);
+          r2 += dq * dq;
+        }
+        const double r = std::sqrt(r2);
+        rmin = std::min(rmin, r);
+        rmax = std::max(rmax, r);
+      }
+    int gf = f->mu + 2, g0 = f->mu + 2;
+    for (int g = f->mu + 1; g >= 1; --g) {
+      const double t0 = (g * Ml + 1.0) * ctx->dt;
+      if (ctx->c * (t0 + ht * dmax) - rmin > 0.0) gf = g;
+      if (ctx->c * (t0 + ht * dmin) - rmax > 0.0) g0 = g;
+    }
+    if (g0 > f->mu + 1) throw Error(TDBEM_E_INVAL, "expansion gap not past the wavefront for some offset");
+    L.gf[sl] = std::min(gf, g0);
+    L.g0[sl] = g0;
+  }
+  std::vector<int32_t> srows(std::max(nslot, 1), 0), soff(std::max(nslot, 1), 0);
+  for (int sl = 0; sl < nslot; ++sl) {
+    srows[sl] = (L.g0[sl] - L.gf[sl]) * P;
+    soff[sl] = (L.gf[sl] - 1) * P;
+  }
+  upload(L.d_srows, srows, st);
+  upload(L.d_soff, soff, st);
+  std::vector<int32_t> gr(std::max<int64_t>(L.npair, 1), 0);
+  L.dense_blocks = 0;
+  for (int64_t p = 0; p < L.npair; ++p) {
+    const int sl = L.il_slot[p];
+    gr[p] = L.gf[sl] | (L.g0[sl] << 16);
+    L.dense_blocks += L.g0[sl] - L.gf[sl];
+  }
+  upload(L.d_pair_gr, gr, st);
+  const std::vector<int32_t>* tl[3] = {&tiles128, &tiles64, &tiles32};
+  for (int ci = 0; ci < 3; ++ci)
+    for (int ri = 0; ri < 2; ++ri) {
+      const int rows = ri == 0 ? 128 : 256;
+      const std::vector<int32_t>& t = *tl[ci];
+      const int nt = (int)t.size() / 3;
+      int maxrb = 0;
+      for (int sl = 0; sl < nslot; ++sl) maxrb = std::max(maxrb, (srows[sl] + rows - 1) / rows);
+      std::vector<int32_t> items;
+      for (int rb = 0; rb < maxrb; ++rb)
+        for (int ti = 0; ti < nt; ++ti)
+          if (rb < (srows[t[3 * ti]] + rows - 1) / rows) {
+            items.push_back(ti);
+            items.push_back(rb);
+          }
+      L.nitems[ci][ri] = (int)items.size() / 2;
+      if (items.empty()) items.assign(2, 0);
+      upload(L.d_items[ci][ri], items, st);
+    }
 }
 
 Fmm* fmm_create(tdbem_ctx* ctx) {
@@ -1661,7 +1832,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       DevBuf<int32_t> d_so;
       upload(d_so, so, st);
       L.d_U.alloc((size_t)std::max(nslot, 1) * G * P * P);
-      const int nk = ctx->d >= 3 ? 2 : 1;
+      const int nk = 1 + (ctx->d >= 2 ? 1 : 0) + (ctx->d >= 3 ? 1 : 0);
       DevBuf<double> d_K;  // row-major spatial kernels (set-up only)
       d_K.alloc((size_t)std::max(nslot, 1) * nk * f->Ps * f->Ps);
       if (nslot > 0) {
@@ -1681,9 +1852,11 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         TDBEM_HIP(hipGetLastError());
         TDBEM_HIP(hipStreamSynchronize(st));
       }
-      L.d_tm.alloc((size_t)L.ncell * ctx->d * f->Ps);
-      L.d_tsum.alloc((size_t)L.ncell * ctx->d);
-      L.d_V.alloc((size_t)std::max<int64_t>(L.npair, 1) * (ctx->d + (ctx->d >= 3 ? 1 : 0)) * f->Ps);
+      L.d_tm.alloc((size_t)L.ncell * (ctx->d + 1) * f->Ps);
+      L.d_tsum.alloc((size_t)L.ncell * (ctx->d + 1));
+      const int nv = (ctx->d + 1) + std::max(0, ctx->d - 1) + std::max(0, ctx->d - 2);
+      L.d_V.alloc((size_t)std::max<int64_t>(L.npair, 1) * nv * f->Ps);
+      classify_gaps(ctx, f, l, tiles128, tiles64, tiles32, st);
       L.d_mom.alloc((size_t)L.ncell * P);
       if (f->prec == 1) {
         L.d_mom32.alloc((size_t)L.ncell * P);
@@ -1698,27 +1871,35 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
       {
-        const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
-        const int64_t per = (int64_t)RB * KB * 64;
-        dim3 gf((unsigned)((per + 255) / 256), std::max(nslot, 1));
-        if (f->prec == 2) {
-          const int KB32 = (P + 31) / 32;
-          const int64_t per16 = (int64_t)RB * KB32 * 512;
-          L.d_U16.alloc((size_t)std::max(nslot, 1) * per16);
-          dim3 g16((unsigned)((per16 + 255) / 256), std::max(nslot, 1));
-          if (nslot > 0)
-            to_fragments_bf16_kernel<<<g16, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB32, L.d_U.p, L.d_U16.p);
-          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
-        } else if (f->prec == 1) {
-          L.d_U32.alloc((size_t)std::max(nslot, 1) * per);
-          if (nslot > 0) to_fragments_kernel<float><<<gf, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB, L.d_U.p, L.d_U32.p);
-          L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
-        } else {
-          L.d_Uf.alloc((size_t)std::max(nslot, 1) * per);
-          if (nslot > 0) to_fragments_kernel<double><<<gf, 256, 0, st>>>(P, G * P, 0, G * P, RB, KB, L.d_U.p, L.d_Uf.p);
-          L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+        // dense blocks only: each slot's gaps gf .. g0-1, converted slot by slot
+        const int KB = m2l_kblocks(P), KB32 = (P + 31) / 32;
+        std::vector<int64_t> uoff(std::max(nslot, 1) + 1, 0);
+        for (int sl = 0; sl < nslot; ++sl) {
+          const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16;
+          uoff[sl + 1] = uoff[sl] + (f->prec == 2 ? (int64_t)RBs * KB32 * 512 : (int64_t)RBs * KB * 64);
         }
-        TDBEM_HIP(hipGetLastError());
+        const size_t tot = (size_t)std::max<int64_t>(uoff[nslot > 0 ? nslot : 0], 1);
+        if (f->prec == 2) L.d_U16.alloc(tot);
+        else if (f->prec == 1) L.d_U32.alloc(tot);
+        else L.d_Uf.alloc(tot);
+        for (int sl = 0; sl < nslot; ++sl) {
+          const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16, row0 = (L.gf[sl] - 1) * P;
+          if (rows == 0) continue;
+          const double* Us = L.d_U.p + (int64_t)sl * G * P * P;
+          const int64_t n = uoff[sl + 1] - uoff[sl];
+          const unsigned nb = (unsigned)((n + 255) / 256);
+          if (f->prec == 2)
+            to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB32, Us, L.d_U16.p + uoff[sl]);
+          else if (f->prec == 1)
+            to_fragments_kernel<float><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, Us, L.d_U32.p + uoff[sl]);
+          else
+            to_fragments_kernel<double><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, Us, L.d_Uf.p + uoff[sl]);
+          TDBEM_HIP(hipGetLastError());
+        }
+        uoff.resize(std::max(nslot, 1));
+        upload(L.d_uoff, uoff, st);
+        if (f->prec != 0) L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+        else L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
         TDBEM_HIP(hipStreamSynchronize(st));
         L.d_U.release();  // row-major master no longer needed
       }
@@ -1855,28 +2036,31 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
       FmmLevel& L = f->lev[l];
       if (L.npair > 0) {
         {
-          // derivative products L^{(p)}_{k+mu+1,k} (FP64, separable form)
+          // separable products: the wavefront-free near-future gaps and the derivative
+          // products L^{(p)}_{k+mu+1,k}, FP64
           ProfScope ps(ctx, K_M2L_DERIV);
-          const double ht = Ml * ctx->dt / 2.0, T0 = ((f->mu + 1) * (double)Ml + 1.0) * ctx->dt;
+          const double ht = Ml * ctx->dt / 2.0;
           m2l_time_moments_kernel<<<L.ncell, 64, 0, st>>>(f->Ps, f->pt, ctx->d, ht, f->nodes, L.ncell, L.d_mom.p,
                                                           L.d_tm.p, L.d_tsum.p);
           TDBEM_HIP(hipGetLastError());
-          launch_deriv_products(f, L, ctx->d, st);
-          m2l_deriv_expand_kernel<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
-              f->Ps, f->pt, ctx->d, ctx->c, T0, ht, f->nodes, L.ncell, L.npair, L.d_il_ptr.p, L.d_il_src.p,
-              L.d_V.p, L.d_tsum.p, L.d_dp.p);
+          launch_sep_products(f, L, ctx->d, st);
+          m2l_sep_expand_kernel<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
+              f->Ps, f->pt, ctx->d, f->mu, f->R, k, ctx->c, ctx->dt, Ml, ht, f->nodes, L.ncell, L.npair,
+              L.d_il_ptr.p, L.d_il_src.p, L.d_pair_gr.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
           TDBEM_HIP(hipGetLastError());
         }
         ProfScope ps(ctx, K_M2L_RED);
-        dim3 g2(L.ncell, f->Gn, (P + 255) / 256);
-        const int bs = std::min(256, ((P + 63) / 64) * 64);
-        if (f->prec != 0)
-          m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_stage32.p, L.ncell,
-                                                       L.d_ring.p);
-        else
-          m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_stage.p, L.ncell,
-                                                        L.d_ring.p);
-        TDBEM_HIP(hipGetLastError());
+        if (L.dense_blocks > 0) {
+          dim3 g2(L.ncell, f->Gn, (P + 255) / 256);
+          const int bs = std::min(256, ((P + 63) / 64) * 64);
+          if (f->prec != 0)
+            m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_pair_gr.p,
+                                                         L.d_stage32.p, L.ncell, L.d_ring.p);
+          else
+            m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_pair_gr.p,
+                                                          L.d_stage.p, L.ncell, L.d_ring.p);
+          TDBEM_HIP(hipGetLastError());
+        }
         const int64_t nrec = (int64_t)L.ncell * P;
         m2l_recurrence_kernel<<<(unsigned)((nrec + 255) / 256), 256, 0, st>>>(P, f->mu, ctx->d, f->R, k,
                                                                                ctx->c * Ml * ctx->dt, L.ncell,
@@ -1911,6 +2095,7 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   for (int n = 1; n < f->D && n < 16; ++n) info->m2l_variant[n] = f->m2l_choice[n];
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
+    info->m2l_dense_blocks[l] = f->lev[l].dense_blocks;
     bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float) +
              (int64_t)f->lev[l].d_U16.n * sizeof(uint16_t);
   }

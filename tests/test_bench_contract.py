@@ -33,11 +33,19 @@ def test_traffic_record_matches_the_m2l_source():
     assert bench.measured_traffic(0) is None  # FP64 products: no counter record
 
 
-def test_m2l_flop_count_equals_the_products_the_oracle_makes(monkeypatch):
-    """The roofline's numerator: bench.py's algorithmic M2L flops of a march (2 G P^2 per
-    interaction pair per completed source interval, G = mu+1 near-future blocks) equal the
-    flops of the near-future matrix products (eq. m2l_near) the oracle's Algorithm 1
-    actually performs over the same march."""
+def oracle_dense(R, lev, o, gap):
+    """A near-future block is a dense product when the oracle's interpolated operator (eq.
+    Uabmn) is neither zero at every node pair (wavefront not yet there) nor free of the
+    truncation everywhere (wavefront past: its polynomial form is applied instead)."""
+    U = R.m2l_matrix(lev, o, gap=gap)
+    return bool((U == 0).any() and (U > 0).any())
+
+
+def test_m2l_flop_count_equals_the_dense_products_the_oracle_makes(monkeypatch):
+    """The roofline's numerator: bench.py's algorithmic M2L flops of a march (2 P^2 per
+    dense near-future block product, interval ends counted from the samples) equal the flops
+    of the dense near-future matrix products (eq. m2l_near) the oracle's Algorithm 1 makes
+    over the same march."""
     import synth
     from oracle import fmm as F
     xyz, tri = synth.icosphere(2)
@@ -47,14 +55,18 @@ def test_m2l_flop_count_equals_the_products_the_oracle_makes(monkeypatch):
 
     def counted(self, lev, o, gap=None, deriv=0):
         if deriv == 0:
-            made.append((lev, o))
+            made.append((lev, o, gap))
         return orig(self, lev, o, gap=gap, deriv=deriv)
     monkeypatch.setattr(F.ReferenceFMM, "m2l_matrix", counted)
     nt = 2 * R.M[2] + 3
     u = synth.random_history(R.geom.ns, nt, seed=1)
     q = synth.random_history(R.geom.ns, nt, seed=2)
     R.history_rhs(nt, u, q)       # samples 0 .. nt-2, as in a march of nt steps
-    flops = sum(2 * R.P ** 2 * len(R.il_by_off[lev][o][0]) for lev, o in made)
-    info = {"il_pairs": {lev: len(R.il[lev]) for lev in range(2, R.D + 1)}}
-    want = bench.m2l_flops_per_march(info, nt, R.m_leaf, R.D, R.mu + 1, R.P)
+    monkeypatch.setattr(F.ReferenceFMM, "m2l_matrix", orig)
+    flops = sum(2 * R.P ** 2 * len(R.il_by_off[lev][o][0]) for lev, o, gap in made if oracle_dense(R, lev, o, gap))
+    dense = [0] * (R.D + 1)
+    for lev in range(2, R.D + 1):
+        for o, (oi, _) in R.il_by_off[lev].items():
+            dense[lev] += len(oi) * sum(oracle_dense(R, lev, o, g) for g in range(1, R.mu + 2))
+    want = 2 * R.P ** 2 * bench.m2l_dense_blocks({"m2l_dense_blocks": dense}, range(0, nt - 1), R.m_leaf, R.D)
     assert flops > 0 and flops == want, (flops, want)
