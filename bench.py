@@ -57,12 +57,15 @@ def m2l_dense_blocks(info, betas, m_leaf, depth):
     return tot
 
 
-def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0):
+def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0, window=None):
     """The FP64 oracle (direct marching-on-in-time, plain definition) on a bounded sample:
     compact coefficients of `rows_sample` seeded collocation rows against all elements,
-    then the Nt-1 history sums of those rows over a synthetic history (chunks of rows)."""
+    then the Nt-1 history sums of those rows over a synthetic history (chunks of rows).
+    window = (a0, K): the large instance's form, see cpu_baseline_of_window."""
     import synth
     from oracle import elemint
+    if window is not None:
+        return cpu_baseline_of_window(w, window[0], window[1], elemint, synth)
     g = elemint.Geometry(w["xyz"], w["tri"])
     ns, nt, d = g.ns, w["nt"], w["d"]
     rows = np.sort(np.random.default_rng(seed).choice(ns, size=min(rows_sample, ns), replace=False))
@@ -231,33 +234,11 @@ def run_window(P, w, args, prec, guess, params, a0, hist):
     return s, info, out
 
 
-def sampled_direct_check(w, u_hist, alpha, b_gpu, nrows=32, seed=7, chunk=8):
-    """The FP64 direct oracle's history sum b^{alpha-1} (compact coefficients, every element,
-    Burton-Miller, Neumann: the u family) at `nrows` seeded rows against the FMM's."""
-    from oracle import elemint
-    g = elemint.Geometry(w["xyz"], w["tri"])
-    rows = np.sort(np.random.default_rng(seed).choice(g.ns, nrows, replace=False))
-    ref = np.zeros(nrows)
-    t0 = time.perf_counter()
-    for c0 in range(0, nrows, chunk):
-        gmax, C = elemint.compact_rows(g, w["d"], w["c"] * w["dt"], rows[c0:c0 + chunk])
-        Cw = np.ascontiguousarray(C[3])   # Wbar (q = 0 on a homogeneous Neumann surface)
-        del C
-        for gg in range(2, min(gmax, alpha) + 1):
-            ref[c0:c0 + chunk] -= Cw[:, gg, :] @ u_hist[alpha - gg]
-    got = b_gpu[rows]
-    return {"rows": int(nrows), "alpha": int(alpha),
-            "rel_l2_fmm_vs_direct": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-            "oracle_s": round(time.perf_counter() - t0, 1)}
-
-
-def cpu_window_baseline(w, a0, K, rows_sample=128, seed=0, chunk=16):
+def cpu_baseline_of_window(w, a0, K, elemint, synth, rows_sample=128, seed=0, chunk=16):
     """The FP64 oracle (direct marching-on-in-time, plain definition) on a bounded sample of the
     large instance: compact coefficients of `rows_sample` seeded rows against every element
     (set-up, timed apart), then their history sums over the same K steps as the GPU window on a
     synthetic history; rate = rows * K / s of the sums."""
-    import synth
-    from oracle import elemint
     g = elemint.Geometry(w["xyz"], w["tri"])
     rows = np.sort(np.random.default_rng(seed).choice(g.ns, rows_sample, replace=False))
     hist = synth.random_history(g.ns, a0 + K, seed=seed + 1)
@@ -284,6 +265,20 @@ def cpu_window_baseline(w, a0, K, rows_sample=128, seed=0, chunk=16):
                       f"sums for the {K} window steps ({sums:.2f} s); rate = rows*steps/s of the sums"}
 
 
+
+
+def sampled_direct_check(s, alpha, b_fmm, nrows=64, seed=7):
+    """The exact history sum b^{alpha-1} (every element directly, tdbem_direct_rows) at `nrows`
+    seeded rows against the FMM's (tdbem_fmm_eval) from the same history."""
+    rows = np.sort(np.random.default_rng(seed).choice(s.ns, nrows, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    ref = s.direct_rows(rows, alpha).cpu().numpy()
+    got = b_fmm[rows]
+    return {"rows": int(nrows), "alpha": int(alpha),
+            "rel_l2_fmm_vs_direct": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "direct_rows_s": round(time.perf_counter() - t0, 2)}
+
+
 def window_main(args, P, mlp):
     """The large single instance: K timed collocation steps of the mixed form (FP32 near-future
     M2L products, learned starting point) and of the plain FP64 form, each marched untimed to the
@@ -292,7 +287,7 @@ def window_main(args, P, mlp):
     import torch
     import synth
     w = synth.workload(args.workload)
-    a0 = WINDOW_START[args.workload]
+    a0 = args.window_start or WINDOW_START[args.workload]
     K = args.steps
     params = mlp.load(os.path.join(ROOT, "paper_2111_05205_amd", "data", "mlp_guess.npy"))
     ns = w["tri"].shape[0]
@@ -303,7 +298,7 @@ def window_main(args, P, mlp):
         s, info, forms["plain"] = run_window(P, w, args, P.M2L_FP64, P.GUESS_EXTRAP, None, a0, hists["plain"])
         if not args.no_accuracy:
             b = s.fmm_eval(a0 + K).cpu().numpy()
-            acc["sampled_direct"] = sampled_direct_check(w, hists["plain"][: a0 + K - 1].cpu().numpy(), a0 + K, b)
+            acc["sampled_direct"] = sampled_direct_check(s, a0 + K, b)
         s.close()
         del s
     if args.form in ("both", "mixed"):
@@ -346,7 +341,7 @@ def window_main(args, P, mlp):
                        "(measured floor, not a tolerance met); mixed vs plain is the precision effect")
         out["accuracy"] = acc
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_window_baseline(w, a0, K)
+        out["cpu_baseline"] = cpu_baseline(w, window=(a0, K))
     print(json.dumps(out), flush=True)
 
 
@@ -435,6 +430,9 @@ def main():
                     help="mixed: FP32 M2L products + learned starting point; plain: FP64 M2L + extrapolated "
                          "starting point; both: time both, value = mixed")
     ap.add_argument("--gmres-tol", type=float, default=1e-8)
+    ap.add_argument("--window-start", type=int, default=0,
+                    help="first timed step of the large-instance window (default: where the pulse is on the "
+                         "surface); smaller values shorten the untimed march, e.g. for counter runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",

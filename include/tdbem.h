@@ -55,7 +55,8 @@ enum {
 };
 
 typedef enum { TDBEM_OBIE = 0, TDBEM_BMBIE = 1 } tdbem_bie;          /* eq. bie / eq. bmbie */
-typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1 } tdbem_bc;    /* u given (q unknown) / q given (u unknown) */
+/* u given (q unknown) / q given (u unknown) on every face; MIXED: per face, see tdbem_create_mixed */
+typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1, TDBEM_MIXED = 2 } tdbem_bc;
 /* Precision of the near-future M2L products (Section 4, eq. m2l_near, blocks
  * l = 1..mu+1): FP64, FP32, or BF16 operators and moments (rounded to nearest)
  * on the BF16 matrix cores; FP32 and BF16 accumulate in FP32.  The derivative products
@@ -97,7 +98,23 @@ typedef struct {
   int graph;         /* 1: tdbem_run from a reset context captures the whole march into a HIP graph once and
                         replays it on later runs with the same nt and forcing (per-step solves then use the
                         single-workgroup GMRES kernel; profiling and training records run without the graph) */
+  int near_form;     /* near-field history sum: 0 compact coefficients C^{(g)} = sum_kappa w^kappa X^{(g-kappa)}
+                        (default); 1 the tau/sigma form of eq. linear: raw X^{(gamma)} times
+                        tau = sum_kappa w^kappa q (sigma likewise), truncated at each pair's last gap (App. A).
+                        Equal in exact arithmetic; the kappa sum is taken in the coefficients (once, FP64) or in
+                        the densities at every step (Section 5.1.3, cancellation of significant digits) */
+  int near_prec;     /* 0: near-field coefficients stored in FP64 (default); 1: rounded to FP32 (study of that
+                        cancellation; the sums stay FP64) */
+  int interp;        /* FMM interpolation in each of the eight variables (eq. U_intp), tdbem_interp */
 } tdbem_opts;
+
+/* Interpolation functions l_a of eq. U_intp.  LAGRANGE: polynomials on the p Chebyshev
+ * points of the first kind.  HERMITE: the paper's choice (Section 3, after eq. Uabmn):
+ * piecewise cubic Hermite interpolation on p >= 3 equispaced nodes (both ends
+ * included) whose nodal slopes are finite differences of the nodal values (central
+ * inside, second-order one-sided at the ends; quadratics are reproduced), the end
+ * pieces continued outside the node range. */
+enum tdbem_interp { TDBEM_INTERP_LAGRANGE = 0, TDBEM_INTERP_HERMITE = 1 };
 
 typedef struct {
   int kind;          /* tdbem_inc_kind */
@@ -156,6 +173,37 @@ typedef struct {
  * Errors: TDBEM_E_INVAL (bad argument or mesh), TDBEM_E_NOMEM, TDBEM_E_DEVICE. */
 int tdbem_create(const tdbem_mesh *mesh, double c, double dt, int d, int bie, int bc,
                  const tdbem_opts *opts, void *hip_stream, struct tdbem_ctx **out);
+
+/* tdbem_create for a mixed boundary condition (Section 2.1, eq. ibvp with both S_u and
+ * S_q non-empty): face_bc (host, mesh->nt values) is phi_j of eq. linear, 1 where q is
+ * given and u unknown, 0 where u is given and q unknown.  The per-step matrix takes
+ * column j from the W family where phi_j = 1 and from -U where phi_j = 0; the
+ * prescribed coefficients passed to tdbem_step (dev_bc_values) are q on phi = 1 faces
+ * and u on phi = 0 faces; the solution rows (tdbem_step's dev_x_out, tdbem_run's
+ * history) hold u on phi = 1 faces and q on phi = 0 faces.  The learned starting point
+ * is not available (TDBEM_E_INVAL for guess MLP / MLP_ONLY).  tdbem_info.bc reports
+ * TDBEM_MIXED.  Errors as tdbem_create, and TDBEM_E_INVAL for a NULL face_bc or values
+ * other than 0 and 1. */
+int tdbem_create_mixed(const tdbem_mesh *mesh, double c, double dt, int d, int bie, const int8_t *face_bc,
+                       const tdbem_opts *opts, void *hip_stream, struct tdbem_ctx **out);
+
+/* Field at points off the surface from the solved history (the Kirchhoff representation:
+ * the single and double layer of eq. bie_disc, not their Burton-Miller combination,
+ * evaluated at a point that is not a collocation point):
+ *   dev_out[r] = sum_j sum_{g=1}^{alpha} (C_U^{(g)}(x_r, E_j) q_j^{alpha-g} - C_W^{(g)}(x_r, E_j) u_j^{alpha-g}),
+ * compact coefficients C^{(g)} = sum_kappa w^kappa X^{(g-kappa)} at x_r.  Outside the
+ * scatterer this is the scattered field at (x_r, t_alpha) (add u_in for the total field);
+ * inside it equals -u_in (extinction).  Every element is summed directly (the FMM is not
+ * used): O(npts Ns window) element integrals.  host_pts: npts x 3 host doubles, not on the
+ * surface; 1 <= alpha <= (current position) - 1; dev_out: npts doubles. */
+int tdbem_field(struct tdbem_ctx *ctx, int npts, const double *host_pts, int alpha, double *dev_out);
+
+/* Exact history part of b^{alpha-1} (the quantity tdbem_fmm_eval returns) at selected
+ * collocation rows, every element summed directly with compact coefficients computed on
+ * the fly (no table, no FMM): for checking the FMM's far field at sampled rows where a
+ * direct context would not fit.  host_rows: nrows row indices (host); 1 <= alpha <=
+ * current position; dev_out: nrows doubles.  O(nrows Ns window) element integrals. */
+int tdbem_direct_rows(struct tdbem_ctx *ctx, int nrows, const int32_t *host_rows, int alpha, double *dev_out);
 
 /* Free every device buffer of the context.  NULL is ignored. */
 void tdbem_destroy(struct tdbem_ctx *ctx);
@@ -239,7 +287,9 @@ int tdbem_incident_forcing(struct tdbem_ctx *ctx, const tdbem_incident *inc, int
 
 /* Diagnostic access to the near-field compact coefficients of row i:
  * writes up to cap entries (j, g, C_U^{(g)}_ij, C_W^{(g)}_ij) to host arrays;
- * returns the number of entries of the row (>= 0) or an error code. */
+ * returns the number of entries of the row (>= 0) or an error code. With
+ * opts.near_form = 1 the entries are the raw X_U^{(g)}, X_W^{(g)} instead, and
+ * with opts.near_prec = 1 they are the stored FP32 values widened to FP64. */
 int tdbem_near_row(struct tdbem_ctx *ctx, int i, int cap, int32_t *j_out, int32_t *g_out,
                    double *cu_out, double *cw_out);
 

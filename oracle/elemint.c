@@ -296,3 +296,49 @@ void oracle_fill(int ns, const double *xc, const double *nrm, const double *tris
                  const int *glo, const int *cnt, const long *off, double *out) {
   oracle_fill_rows(ns, ns, 0, xc, nrm, tris, d, cdt, glo, cnt, off, out);
 }
+
+/* Off-surface points: windows and compact coefficients of every (point, element)
+ * pair, as oracle_windows_rows / oracle_fill_rows with the collocation point
+ * replaced by pts[r] (never a self pair).  Only the U and W families are
+ * meaningful there (the point has no normal; ni is taken as nj). */
+void oracle_windows_points(int ns, int npts, const double *pts, const double *tris, int d, double cdt,
+                           int *glo, int *cnt) {
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int r = 0; r < npts; ++r)
+    for (int j = 0; j < ns; ++j) {
+      double rmin, rmax;
+      oracle_dist_range(pts + 3*r, tris + 9*j, &rmin, &rmax);
+      int lo, hi; window_of(rmin, rmax, d, cdt, &lo, &hi);
+      glo[(long)r*ns + j] = lo; cnt[(long)r*ns + j] = hi - lo + 1;
+    }
+}
+
+void oracle_fill_points(int ns, int npts, const double *pts, const double *nrm, const double *tris, int d,
+                        double cdt, const int *glo, const int *cnt, const long *off, double *out) {
+  double w[8];
+  for (int k = 0; k <= d + 1; ++k) w[k] = bspline_w(k, d);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int r = 0; r < npts; ++r)
+    for (int j = 0; j < ns; ++j) {
+      long p = (long)r*ns + j;
+      int lo = glo[p], n = cnt[p];
+      double X[64][4];
+      int gmin = lo - d - 1; if (gmin < 1) gmin = 1;
+      int gmax = lo + n - 1;
+      if (gmax - gmin + 1 > 64) continue;
+      for (int g = gmin; g <= gmax; ++g)
+        oracle_elem(pts + 3*r, nrm + 3*j, tris + 9*j, nrm + 3*j, 0, g * cdt, d, cdt, X[g - gmin]);
+      for (int k = 0; k < n; ++k) {
+        int g = lo + k;
+        double acc[2] = {0, 0};
+        for (int kap = 0; kap <= d + 1; ++kap) {
+          int gg = g - kap;
+          if (gg < gmin) continue;
+          acc[0] += w[kap] * X[gg - gmin][0];
+          acc[1] += w[kap] * X[gg - gmin][1];
+        }
+        out[2*(off[p] + k)] = acc[0];
+        out[2*(off[p] + k) + 1] = acc[1];
+      }
+    }
+}

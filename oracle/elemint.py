@@ -30,6 +30,9 @@ def configure(L):
                                       ip, ip]
     L.oracle_fill_rows.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, ctypes.c_int, ctypes.c_double,
                                    ip, ip, lp, dp]
+    L.oracle_windows_points.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ip, ip]
+    L.oracle_fill_points.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                                     ip, ip, lp, dp]
     return L
 
 
@@ -143,5 +146,32 @@ def compact_rows(geom: Geometry, d: int, cdt: float, rows):
     j = np.repeat(np.tile(np.arange(ns), nr), cnt)
     C = np.zeros((4, nr, gmax + 1, ns))
     for f in range(4):
+        C[f, r, g, j] = vals[:, f]
+    return gmax, C
+
+
+def compact_points(geom: Geometry, d: int, cdt: float, pts):
+    """Compact coefficients of the single and double layer (U, W families, eq. bie_disc) at
+    off-surface points pts (npts x 3) against every element: returns (gmax, C[f, r, g, j]),
+    f in (U, W), g = 0..gmax (g = 0 unused)."""
+    pts = np.ascontiguousarray(np.atleast_2d(pts), dtype=np.float64)
+    ns, npt = geom.ns, pts.shape[0]
+    glo = np.zeros(npt * ns, dtype=np.int32)
+    cnt = np.zeros(npt * ns, dtype=np.int32)
+    lib().oracle_windows_points(ns, npt, _p(pts), _p(geom.tris), d, cdt, _p(glo, ctypes.c_int),
+                                _p(cnt, ctypes.c_int))
+    if cnt.max() + d + 1 > 64:
+        raise ValueError("time window too long for the oracle's fixed buffer")
+    off = np.zeros(npt * ns, dtype=np.int64)
+    off[1:] = np.cumsum(cnt[:-1], dtype=np.int64)
+    vals = np.zeros((int(cnt.sum()), 2))
+    lib().oracle_fill_points(ns, npt, _p(pts), _p(geom.n), _p(geom.tris), d, cdt, _p(glo, ctypes.c_int),
+                             _p(cnt, ctypes.c_int), _p(off, ctypes.c_long), _p(vals))
+    g = np.repeat(glo, cnt) + (np.arange(vals.shape[0]) - np.repeat(off, cnt))
+    gmax = int(g.max())
+    r = np.repeat(np.repeat(np.arange(npt), ns), cnt)
+    j = np.repeat(np.tile(np.arange(ns), npt), cnt)
+    C = np.zeros((2, npt, gmax + 1, ns))
+    for f in range(2):
         C[f, r, g, j] = vals[:, f]
     return gmax, C

@@ -6,8 +6,14 @@ m2l_expand, Formula 1 with eqs. m2l_rec, L_derivative, m2l_expand_rec1, L_aux,
 m2l_expand_rec2, cmp, and Algorithm 1).
 
 Where the paper leaves the construction open, this module takes these readings:
-* Interpolation: tensor-product Lagrange on Chebyshev points of the first kind
-  in each of the eight variables (the paper's own runs used cubic Hermite).
+* Interpolation (interp="lagrange", the default): tensor-product Lagrange on
+  Chebyshev points of the first kind in each of the eight variables.
+  interp="hermite" is the paper's own choice (Section 3, after eq. Uabmn):
+  piecewise cubic Hermite interpolation whose nodal slopes are finite
+  differences of the nodal values.  Read here as: p >= 3 equispaced nodes
+  -1 = w_0 < ... < w_{p-1} = 1, central differences at interior nodes and
+  second-order one-sided differences at the two end nodes (so that quadratics
+  are reproduced), the end pieces continued outside [-1, 1].
 * Octree: root cube centred on the vertex bounding box with half side the
   next power of two of its largest half extent; faces assigned to leaves by
   centroid; near field = the 27 leaves around a face's leaf; interaction
@@ -73,6 +79,59 @@ def lagrange_deriv(nodes, xi):
     return out
 
 
+def equi_nodes(p):
+    if p < 3:
+        raise ValueError("the cubic Hermite interpolation needs p >= 3 nodes")
+    return np.linspace(-1.0, 1.0, p)
+
+
+def _fd_slopes(p, h):
+    """D (p x p): nodal slopes f'(w_k) ~ sum_a D[k, a] f(w_a) by finite differences."""
+    D = np.zeros((p, p))
+    for k in range(1, p - 1):
+        D[k, k + 1], D[k, k - 1] = 1.0 / (2 * h), -1.0 / (2 * h)
+    D[0, :3] = np.array([-3.0, 4.0, -1.0]) / (2 * h)
+    D[p - 1, p - 3:] = np.array([1.0, -4.0, 3.0]) / (2 * h)
+    return D
+
+
+def _hermite_parts(nodes, xi):
+    """Segment index k, local coordinate t in the segment, node spacing h and slope matrix D."""
+    xi = np.atleast_1d(np.asarray(xi, dtype=np.float64))
+    p = len(nodes)
+    h = nodes[1] - nodes[0]
+    k = np.clip(np.floor((xi - nodes[0]) / h).astype(np.int64), 0, p - 2)
+    t = (xi - nodes[k]) / h
+    return xi, k, t, h, _fd_slopes(p, h)
+
+
+def hermite_fd(nodes, xi):
+    """Cardinal functions of the cubic Hermite interpolation with finite-difference slopes:
+    on the segment [w_k, w_k+1] the interpolant is h00 f_k + h01 f_k+1 + h (h10 m_k + h11 m_k+1)
+    with the cubic Hermite polynomials h00 .. h11 of t in [0, 1] and slopes m = D f.
+    Array (len(xi), p)."""
+    xi, k, t, h, D = _hermite_parts(nodes, xi)
+    h00, h01 = 2 * t ** 3 - 3 * t ** 2 + 1, -2 * t ** 3 + 3 * t ** 2
+    h10, h11 = t ** 3 - 2 * t ** 2 + t, t ** 3 - t ** 2
+    rows = np.arange(xi.size)
+    out = h * (h10[:, None] * D[k] + h11[:, None] * D[k + 1])
+    out[rows, k] += h00
+    out[rows, k + 1] += h01
+    return out
+
+
+def hermite_fd_deriv(nodes, xi):
+    """d/dxi of hermite_fd: array (len(xi), p)."""
+    xi, k, t, h, D = _hermite_parts(nodes, xi)
+    d00, d01 = (6 * t ** 2 - 6 * t) / h, (-6 * t ** 2 + 6 * t) / h
+    d10, d11 = 3 * t ** 2 - 4 * t + 1, 3 * t ** 2 - 2 * t
+    rows = np.arange(xi.size)
+    out = d10[:, None] * D[k] + d11[:, None] * D[k + 1]
+    out[rows, k] += d00
+    out[rows, k + 1] += d01
+    return out
+
+
 def cmp_coef(p, m, k):
     """c_m^p(k) of eq. cmp."""
     return comb(p, m) * ((k - 1) ** (p - m) - 2 * k ** (p - m) + (k + 1) ** (p - m)) * (-1) ** m
@@ -104,10 +163,12 @@ class ReferenceFMM:
     """History part of the MOT right-hand side with near pairs direct and far pairs by the FMM."""
 
     def __init__(self, xyz, tri, c, dt, d, bie, depth, p_s, p_t, mu=0, m2l="alg1", bc=None, src_ext=None,
-                 near_round=None):
+                 near_round=None, interp="lagrange"):
         """near_round: None, or a function applied to both factors (moments and operator) of
-        every near-future product (eq. m2l_near) before it is formed, e.g. rounding to a
-        lower precision; the derivative products stay exact."""
+        the near-future products (eq. m2l_near) whose operator block is truncated at some node
+        pairs and not zero at all of them (where the wavefront crosses the pair's node set),
+        e.g. rounding to a lower precision; every other block is a polynomial at the nodes
+        or zero, and those products and the derivative products stay exact."""
         self.near_round = near_round
         self.geom = g = Geometry(xyz, tri)
         self.bc = bc
@@ -117,7 +178,15 @@ class ReferenceFMM:
         self.m2l = m2l
         self.Cd = 1.0 / (4.0 * np.pi * (self.c * self.dt) ** self.d)
         self.w = weights(self.d)
-        self.om_s, self.om_t = cheb_nodes(self.ps), cheb_nodes(self.pt)
+        if interp == "lagrange":
+            self.om_s, self.om_t = cheb_nodes(self.ps), cheb_nodes(self.pt)
+            self._l, self._dl = lagrange, lagrange_deriv
+        elif interp == "hermite":
+            self.om_s, self.om_t = equi_nodes(self.ps), equi_nodes(self.pt)
+            self._l, self._dl = hermite_fd, hermite_fd_deriv
+        else:
+            raise ValueError("interp must be 'lagrange' or 'hermite'")
+        self.interp = interp
         self.Ps = self.ps ** 3
         self.P = self.Ps * self.pt
         self._tree(np.asarray(xyz, dtype=np.float64))
@@ -271,8 +340,8 @@ class ReferenceFMM:
                     wts.append(wa * wb * a_ * area2)
             pts, wts = np.array(pts), np.array(wts)
             xi = (pts - cen) / hb
-            L = [lagrange(self.om_s, xi[:, q]) for q in range(3)]
-            dL = [lagrange_deriv(self.om_s, xi[:, q]) for q in range(3)]
+            L = [self._l(self.om_s, xi[:, q]) for q in range(3)]
+            dL = [self._dl(self.om_s, xi[:, q]) for q in range(3)]
             n = g.n[j]
             val = _tensor3(L[0], L[1], L[2])
             grad = n[0] * _tensor3(dL[0], L[1], L[2]) + n[1] * _tensor3(L[0], dL[1], L[2]) \
@@ -280,8 +349,8 @@ class ReferenceFMM:
             self.A[j] = wts @ val
             self.B[j] = wts @ grad / hb
             xi0 = (g.x[j] - cen) / hs
-            L0 = [lagrange(self.om_s, [xi0[q]]) for q in range(3)]
-            dL0 = [lagrange_deriv(self.om_s, [xi0[q]]) for q in range(3)]
+            L0 = [self._l(self.om_s, [xi0[q]]) for q in range(3)]
+            dL0 = [self._dl(self.om_s, [xi0[q]]) for q in range(3)]
             ni = g.n[j]
             self.E0[j] = _tensor3(L0[0], L0[1], L0[2])[0]
             self.E1[j] = (ni[0] * _tensor3(dL0[0], L0[1], L0[2]) + ni[1] * _tensor3(L0[0], dL0[1], L0[2])
@@ -289,12 +358,12 @@ class ReferenceFMM:
 
     def _translations(self):
         """1-D re-interpolation matrices S[side][a_parent, a_child] = l_{a_parent}(side/2 + om_child/2)."""
-        self.Ssp = {sd: lagrange(self.om_s, sd / 2.0 + self.om_s / 2.0).T for sd in (-1, 1)}
+        self.Ssp = {sd: self._l(self.om_s, sd / 2.0 + self.om_s / 2.0).T for sd in (-1, 1)}
         # M2M in space: parent source box basis at the child source-box nodes, per level
-        self.Msp = {lev: {sd: lagrange(self.om_s, (sd * self.hs(lev) + self.hb(lev) * self.om_s)
+        self.Msp = {lev: {sd: self._l(self.om_s, (sd * self.hs(lev) + self.hb(lev) * self.om_s)
                                        / self.hb(lev - 1)).T for sd in (-1, 1)}
                     for lev in range(2, self.D + 1)}
-        self.Stm = {sd: lagrange(self.om_t, sd / 2.0 + self.om_t / 2.0).T for sd in (-1, 1)}
+        self.Stm = {sd: self._l(self.om_t, sd / 2.0 + self.om_t / 2.0).T for sd in (-1, 1)}
         self._mats = {}
 
     def m2l_matrix(self, lev, o, gap=None, deriv=0):
@@ -341,7 +410,7 @@ class ReferenceFMM:
         D = self.D
         k = (beta + 1) // self.M[D]
         xi = (beta * self.dt - self.src_center(D, k)) / self.ht(D)
-        lt = lagrange(self.om_t, [xi])[0]
+        lt = self._l(self.om_t, [xi])[0]
         per = self.A * tau[:, None] - self.B * sigma[:, None]            # (ns, Ps)
         cellsum = np.zeros((len(self.cells[D]), self.Ps))
         np.add.at(cellsum, self.cell_of[D], per)
@@ -398,16 +467,22 @@ class ReferenceFMM:
         ring, Lp, aux = self.ring[lev], self.Lp[lev], self.aux[lev]
         nc = len(self.cells[lev])
         Dp = np.zeros((d + 1, nc, self.P))
-        rnd = self.near_round if self.near_round is not None else (lambda a: a)
         for o, (oi, si) in self.il_by_off[lev].items():
             X = Mk[si]
-            Xn = rnd(X)
             for l in range(1, mu + 2):
-                np.add.at(ring[(k + l) % R], oi, Xn @ rnd(self.m2l_matrix(lev, o, gap=l)).T)
+                Xn, U = self._near_factors(X, self.m2l_matrix(lev, o, gap=l))
+                np.add.at(ring[(k + l) % R], oi, Xn @ U.T)
             for p in range(1, d + 1):
                 np.add.at(Dp[p], oi, X @ self.m2l_matrix(lev, o, deriv=p).T)
         T = self.c * self.M[lev] * self.dt
         recurrence(k, mu, d, T, ring, R, Lp, aux, Dp)
+
+    def _near_factors(self, X, U):
+        """The factors of a near-future product, rounded by near_round where the block is
+        truncated at some node pairs and not zero at all of them."""
+        if self.near_round is not None and (U == 0).any() and (U > 0).any():
+            return self.near_round(X), self.near_round(U)
+        return X, U
 
     def _l2l_apply(self, lev_parent, Lpar, k_par):
         """The parent's local of target interval k_par, re-interpolated onto the child level's
@@ -438,9 +513,9 @@ class ReferenceFMM:
         for kk, Mk in self.mom_done[lev].items():
             if kk >= k:
                 continue
-            rnd = self.near_round if self.near_round is not None else (lambda a: a)
             for o, (oi, si) in self.il_by_off[lev].items():
-                np.add.at(L, oi, rnd(Mk[si]) @ rnd(self.m2l_matrix(lev, o, gap=k - kk)).T)
+                Xn, U = self._near_factors(Mk[si], self.m2l_matrix(lev, o, gap=k - kk))
+                np.add.at(L, oi, Xn @ U.T)
         if lev > 2:
             kp = k // 2
             L += self._l2l_apply(lev - 1, self.local(lev - 1, kp), kp)[k]
@@ -456,8 +531,8 @@ class ReferenceFMM:
         else:
             L = self.local(D, k)
         tau = (alpha * self.dt - self.tgt_center(D, k)) / self.ht(D)
-        lt = lagrange(self.om_t, [tau])[0]
-        dlt = lagrange_deriv(self.om_t, [tau])[0] / self.ht(D)
+        lt = self._l(self.om_t, [tau])[0]
+        dlt = self._dl(self.om_t, [tau])[0] / self.ht(D)
         Lc = L[self.cell_of[D]].reshape(self.geom.ns, self.pt, self.Ps)   # (i, m, a)
         if self.bie == 0:
             return np.einsum("ima,ia,m->i", Lc, self.E0, lt)

@@ -18,10 +18,10 @@ import numpy as np
 import scipy.linalg as sla
 
 from .bspline import weights
-from .elemint import Geometry, compact_coefficients
+from .elemint import Geometry, compact_coefficients, compact_points
 
 OBIE, BMBIE = 0, 1
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 
 
 def incident(geom: Geometry, inc: dict, c: float, dt: float, nt: int, bie: int) -> np.ndarray:
@@ -54,15 +54,23 @@ def incident(geom: Geometry, inc: dict, c: float, dt: float, nt: int, bie: int) 
 
 
 class DirectMOT:
-    """Direct MOT on one closed surface; see module docstring."""
+    """Direct MOT on one closed surface; see module docstring.
 
-    def __init__(self, xyz, tri, c, dt, d, bie, bc):
+    bc = MIXED with phi (ns values, 1 on faces where q is given and u unknown, 0 where u
+    is given and q unknown): the boundary S_u / S_q split of eq. ibvp with phi_j as in
+    eq. linear, A = C_W^{(1)} diag(phi) - C_U^{(1)} diag(1 - phi)."""
+
+    def __init__(self, xyz, tri, c, dt, d, bie, bc, phi=None):
         self.geom = Geometry(xyz, tri)
         self.c, self.dt, self.d, self.bie, self.bc = float(c), float(dt), int(d), int(bie), int(bc)
         self.gmax, fams = compact_coefficients(self.geom, self.d, self.c * self.dt)
         self.CU = fams["Ubar" if bie == BMBIE else "U"]
         self.CW = fams["Wbar" if bie == BMBIE else "W"]
-        A = (self.CW[1] if bc == NEUMANN else -self.CU[1]).toarray()
+        if bc == MIXED:
+            self.phi = np.asarray(phi, dtype=np.float64)
+        else:
+            self.phi = np.full(self.geom.ns, 1.0 if bc == NEUMANN else 0.0)
+        A = self.CW[1].toarray() * self.phi[None, :] - self.CU[1].toarray() * (1.0 - self.phi)[None, :]
         self.A = A
         self.lu = sla.lu_factor(A)
 
@@ -81,9 +89,10 @@ class DirectMOT:
 
     def run(self, nt: int, forcing=None, prescribed=None):
         """March alpha = 1..nt-1.  forcing: (nt-1, ns) or None; prescribed: the known
-        coefficient per step (u on Dirichlet, q on Neumann), (nt-1, ns) or None (= 0).
-        Returns (u, q), each (nt-1, ns): B-spline coefficients beta = 0..nt-2."""
+        coefficient per step and face (u on Dirichlet faces, q on Neumann faces), (nt-1, ns)
+        or None (= 0).  Returns (u, q), each (nt-1, ns): B-spline coefficients beta = 0..nt-2."""
         ns = self.ns
+        ph = self.phi
         u = np.zeros((nt - 1, ns))
         q = np.zeros((nt - 1, ns))
         for alpha in range(1, nt):
@@ -91,17 +100,25 @@ class DirectMOT:
             b = self.history_rhs(alpha, u, q)
             if forcing is not None:
                 b += forcing[beta]
-            if self.bc == DIRICHLET:
-                if prescribed is not None:
-                    u[beta] = prescribed[beta]
-                    b -= self.CW[1] @ u[beta]
-                q[beta] = sla.lu_solve(self.lu, b)
-            else:
-                if prescribed is not None:
-                    q[beta] = prescribed[beta]
-                    b += self.CU[1] @ q[beta]
-                u[beta] = sla.lu_solve(self.lu, b)
+            p = prescribed[beta] if prescribed is not None else np.zeros(ns)
+            # the known current-step part: q given on phi = 1 faces, u given on phi = 0 faces
+            b += self.CU[1] @ (ph * p) - self.CW[1] @ ((1.0 - ph) * p)
+            x = sla.lu_solve(self.lu, b)
+            u[beta] = ph * x + (1.0 - ph) * p
+            q[beta] = (1.0 - ph) * x + ph * p
         return u, q
+
+    def field(self, pts, alpha: int, u: np.ndarray, q: np.ndarray) -> np.ndarray:
+        """Scattered part of the field at off-surface points pts (npts x 3) and time t_alpha from
+        the solved coefficients beta = 0..alpha-1 (Kirchhoff representation of the exterior
+        field, the operators of eq. bie_disc at a point that is not a collocation point):
+        sum_j sum_{g=1}^{alpha} (C_U^{(g)}(x, E_j) q_j^{alpha-g} - C_W^{(g)}(x, E_j) u_j^{alpha-g}).
+        Add u_in(x, t_alpha) for the total field; inside the scatterer the sum cancels u_in."""
+        gmax, C = compact_points(self.geom, self.d, self.c * self.dt, pts)
+        out = np.zeros(C.shape[1])
+        for g in range(1, min(gmax, alpha) + 1):
+            out += C[0, :, g, :] @ q[alpha - g] - C[1, :, g, :] @ u[alpha - g]
+        return out
 
 
 def reconstruct(coef: np.ndarray, d: int) -> np.ndarray:

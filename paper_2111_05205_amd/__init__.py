@@ -12,11 +12,13 @@ import sys
 import numpy as np
 
 from . import _native as N
-from ._native import (BMBIE, DIRICHLET, GUESS_EXTRAP, GUESS_MLP, GUESS_MLP_ONLY, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
-                      INC_RAISED_COS, M2L_BF16, M2L_FP32, M2L_FP64, NEUMANN, OBIE)
+from ._native import (BMBIE, DIRICHLET, MIXED, GUESS_EXTRAP, GUESS_MLP, GUESS_MLP_ONLY, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
+                      INC_RAISED_COS, INTERP_HERMITE, INTERP_LAGRANGE, M2L_BF16, M2L_FP32, M2L_FP64, NEUMANN,
+                      OBIE)
 
-__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "M2L_FP64", "M2L_FP32", "M2L_BF16",
-           "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP", "GUESS_MLP_ONLY"]
+__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "MIXED", "M2L_FP64", "M2L_FP32", "M2L_BF16",
+           "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP", "GUESS_MLP_ONLY",
+           "INTERP_LAGRANGE", "INTERP_HERMITE"]
 
 
 class TDBEMError(RuntimeError):
@@ -98,7 +100,10 @@ class TDBEM:
 
     def __init__(self, xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, *, use_fmm=0, depth=4, p_s=4, p_t=4, mu=0,
                  m2l_prec=M2L_FP64, gmres_tol=1e-12, gmres_restart=30, gmres_maxiter=300, nt_max=4096,
-                 guess=GUESS_EXTRAP, graph=False, stream=None, device=None):
+                 guess=GUESS_EXTRAP, graph=False, stream=None, device=None, face_bc=None, near_form=0,
+                 near_prec=0, interp=0):
+        """face_bc: None, or per face 1 (q given, u unknown) / 0 (u given, q unknown): a mixed
+        boundary condition (tdbem_create_mixed; bc is then ignored)."""
         torch = _torch()
         self._L = N.lib()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -107,7 +112,8 @@ class TDBEM:
         mesh = N.Mesh(xyz.shape[0], tri.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                       tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         o = N.Opts(int(use_fmm), int(depth), int(p_s), int(p_t), int(mu), int(m2l_prec), float(gmres_tol),
-                   int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess), int(bool(graph)))
+                   int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess), int(bool(graph)),
+                   int(near_form), int(near_prec), int(interp))
         self.stream = stream  # a torch.cuda.Stream the context works on (kept alive), or None
         if stream is not None:
             stream = stream.cuda_stream
@@ -115,8 +121,16 @@ class TDBEM:
             with torch.cuda.device(self.device):
                 stream = torch.cuda.current_stream(self.device).cuda_stream
         h = ctypes.c_void_p()
-        rc = self._L.tdbem_create(ctypes.byref(mesh), float(c), float(dt), int(d), int(bie), int(bc),
-                                  ctypes.byref(o), ctypes.c_void_p(stream), ctypes.byref(h))
+        if face_bc is not None:
+            fb = np.ascontiguousarray(face_bc, dtype=np.int8)
+            if fb.shape != (tri.shape[0],):
+                raise ValueError("face_bc must have one value per triangle")
+            rc = self._L.tdbem_create_mixed(ctypes.byref(mesh), float(c), float(dt), int(d), int(bie),
+                                            fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), ctypes.byref(o),
+                                            ctypes.c_void_p(stream), ctypes.byref(h))
+        else:
+            rc = self._L.tdbem_create(ctypes.byref(mesh), float(c), float(dt), int(d), int(bie), int(bc),
+                                      ctypes.byref(o), ctypes.c_void_p(stream), ctypes.byref(h))
         if rc != N.OK:
             raise TDBEMError(rc, self._L.tdbem_last_error(None).decode())
         self._h = h
@@ -194,6 +208,22 @@ class TDBEM:
         if check:
             self._check(rc)
         return out, {k: getattr(ri, k) for k, _ in N.RunInfo._fields_} | {"rc": rc}
+
+    def field(self, pts, alpha):
+        """Scattered field at off-surface points pts (n x 3) and time t_alpha (tdbem_field)."""
+        p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        out = self._empty(p.shape[0])
+        self._check(self._L.tdbem_field(self._h, p.shape[0], p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        int(alpha), _dptr(out)))
+        return out
+
+    def direct_rows(self, rows, alpha):
+        """Exact history part of b^{alpha-1} at the given collocation rows (tdbem_direct_rows)."""
+        r = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1)
+        out = self._empty(r.shape[0])
+        self._check(self._L.tdbem_direct_rows(self._h, r.shape[0], r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                              int(alpha), _dptr(out)))
+        return out
 
     def incident_forcing(self, inc, a0, n):
         out = self._empty(n, self.ns)

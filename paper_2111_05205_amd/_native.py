@@ -6,8 +6,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdbem.so
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 OBIE, BMBIE = 0, 1
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 M2L_FP64, M2L_FP32, M2L_BF16 = 0, 1, 2
+INTERP_LAGRANGE, INTERP_HERMITE = 0, 1
 INC_GAUSS_MOD, INC_RAISED_COS = 0, 1
 GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP, GUESS_MLP_ONLY = 0, 1, 2, 3, 4
 MLP_IN, MLP_IN_PAD, MLP_WIDTH, MLP_NPARAM = 12, 16, 256, 136193
@@ -23,7 +24,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("use_fmm", ctypes.c_int), ("depth", ctypes.c_int), ("p_s", ctypes.c_int), ("p_t", ctypes.c_int),
                 ("mu", ctypes.c_int), ("m2l_prec", ctypes.c_int), ("gmres_tol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int), ("gmres_maxiter", ctypes.c_int), ("nt_max", ctypes.c_int),
-                ("guess", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("guess", ctypes.c_int), ("graph", ctypes.c_int), ("near_form", ctypes.c_int),
+                ("near_prec", ctypes.c_int), ("interp", ctypes.c_int)]
 
 
 class Incident(ctypes.Structure):
@@ -68,6 +70,10 @@ def lib():
         vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
         L.tdbem_create.argtypes = [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.c_double, ip, ip, ip,
                                    ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.tdbem_create_mixed.argtypes = [ctypes.POINTER(Mesh), ctypes.c_double, ctypes.c_double, ip, ip,
+                                         ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.tdbem_field.argtypes = [vp, ip, dp, ip, vp]
+        L.tdbem_direct_rows.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32), ip, vp]
         L.tdbem_destroy.argtypes = [vp]
         L.tdbem_destroy.restype = None
         L.tdbem_last_error.argtypes = [vp]

@@ -129,24 +129,36 @@ static BWeights bspline_weights(int d) {
 // ---------------------------------------------------------------------------
 // Small kernels of the driver.
 
-__global__ void store_step_kernel(int ns, int beta, int bc, const double* __restrict__ x,
-                                  const double* __restrict__ bcv, double* __restrict__ hu, double* __restrict__ hq,
-                                  StepStat* __restrict__ st) {
+__global__ void store_step_kernel(int ns, int beta, int bc, const int8_t* __restrict__ phi,
+                                  const double* __restrict__ x, const double* __restrict__ bcv,
+                                  double* __restrict__ hu, double* __restrict__ hq, StepStat* __restrict__ st) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ns) return;
   const int64_t r = (int64_t)beta * ns + i;
   const double xv = x[i], pv = bcv ? bcv[i] : 0.0;
-  if (bc == TDBEM_NEUMANN) { hu[r] = xv; hq[r] = pv; }
+  const bool uface = phi ? phi[i] != 0 : bc == TDBEM_NEUMANN;  // u unknown, q given
+  if (uface) { hu[r] = xv; hq[r] = pv; }
   else { hq[r] = xv; hu[r] = pv; }
   if (!isfinite(xv) || fabs(xv) > 1e100) atomicOr(&st->flags, 2);
+}
+
+// Rows of the unknown coefficient (u on phi = 1 faces, q on phi = 0 faces) of a
+// mixed-condition march.
+__global__ void unknown_rows_kernel(int ns, int64_t n, const int8_t* __restrict__ phi, const double* __restrict__ hu,
+                                    const double* __restrict__ hq, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  out[k] = phi[k % ns] ? hu[k] : hq[k];
 }
 
 // Starting point of the per-step solve: quadratic extrapolation of the last
 // three solved coefficient rows (previous row, or zero, early in the march),
 // zero, or the previous row.
-__global__ void guess_kernel(int ns, int beta, int mode, const double* __restrict__ h, double* __restrict__ x) {
+__global__ void guess_kernel(int ns, int beta, int mode, const double* __restrict__ hu, const double* __restrict__ hq,
+                             const int8_t* __restrict__ phi, int bc, double* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ns) return;
+  const double* h = (phi ? phi[i] != 0 : bc == TDBEM_NEUMANN) ? hu : hq;  // history of this face's unknown
   double v = 0.0;
   if (mode == TDBEM_GUESS_ZERO) v = 0.0;
   else if (mode == TDBEM_GUESS_PREV) v = beta >= 1 ? h[(int64_t)(beta - 1) * ns + i] : 0.0;
@@ -229,8 +241,14 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   launch_near_history(ctx, alpha, forcing, ctx->d_b.p);
   if (ctx->fmm) fmm_far(ctx, alpha, ctx->d_b.p);
   if (bcv) {
-    if (ctx->bc == TDBEM_DIRICHLET) launch_spmv_add(ctx, ctx->d_w1_val.p, -1.0, bcv, ctx->d_b.p);
-    else launch_spmv_add(ctx, ctx->d_u1_val.p, 1.0, bcv, ctx->d_b.p);
+    if (ctx->bc == TDBEM_MIXED) {  // q given on phi = 1 faces, u given on phi = 0 faces
+      launch_spmv_add_masked(ctx, ctx->d_u1_val.p, 1.0, bcv, 1, ctx->d_b.p);
+      launch_spmv_add_masked(ctx, ctx->d_w1_val.p, -1.0, bcv, 0, ctx->d_b.p);
+    } else if (ctx->bc == TDBEM_DIRICHLET) {
+      launch_spmv_add(ctx, ctx->d_w1_val.p, -1.0, bcv, ctx->d_b.p);
+    } else {
+      launch_spmv_add(ctx, ctx->d_u1_val.p, 1.0, bcv, ctx->d_b.p);
+    }
   }
   const bool use_mlp = (ctx->opts.guess == TDBEM_GUESS_MLP || ctx->opts.guess == TDBEM_GUESS_MLP_ONLY) &&
                        ctx->mlp_loaded && beta >= 4;
@@ -246,16 +264,19 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   } else {
     ProfScope pg(ctx, K_OTHER);
     guess_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
-        ctx->ns, beta, ctx->opts.guess, ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p, ctx->d_x.p);
+        ctx->ns, beta, ctx->opts.guess, ctx->d_hu.p, ctx->d_hq.p, ctx->bc == TDBEM_MIXED ? ctx->d_phi.p : nullptr,
+        ctx->bc, ctx->d_x.p);
     TDBEM_HIP(hipGetLastError());
   }
   launch_gmres(ctx, ctx->d_b.p, ctx->d_x.p, stat, xalt);
   ProfScope* ps = new ProfScope(ctx, K_OTHER);
-  store_step_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(ctx->ns, beta, ctx->bc, ctx->d_x.p, bcv,
-                                                                      ctx->d_hu.p, ctx->d_hq.p, stat);
+  store_step_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
+      ctx->ns, beta, ctx->bc, ctx->bc == TDBEM_MIXED ? ctx->d_phi.p : nullptr, ctx->d_x.p, bcv, ctx->d_hu.p,
+      ctx->d_hq.p, stat);
   delete ps;
   TDBEM_HIP(hipGetLastError());
-  if (ctx->bc == TDBEM_NEUMANN) { ctx->hist_u = true; if (bcv) ctx->hist_q = true; }
+  if (ctx->bc == TDBEM_MIXED) { ctx->hist_u = true; ctx->hist_q = true; }
+  else if (ctx->bc == TDBEM_NEUMANN) { ctx->hist_u = true; if (bcv) ctx->hist_q = true; }
   else { ctx->hist_q = true; if (bcv) ctx->hist_u = true; }
   if (feat && ctx->rec_target) launch_mlp_target(ctx, beta, ctx->rec_target + (size_t)beta * ctx->ns);
   if (ctx->fmm) fmm_advance(ctx, beta);
@@ -358,9 +379,16 @@ static int run_finish(tdbem_ctx* ctx, int nt, int a_first, double* dev_x_hist_ou
   const int ns = ctx->ns;
   int rc = TDBEM_OK;
   if (dev_x_hist_out) {
-    const double* src = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
-    TDBEM_HIP(hipMemcpyAsync(dev_x_hist_out, src, (size_t)(nt - 1) * ns * sizeof(double), hipMemcpyDeviceToDevice,
-                             ctx->stream));
+    if (ctx->bc == TDBEM_MIXED) {
+      const int64_t n = (int64_t)(nt - 1) * ns;
+      unknown_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(ns, n, ctx->d_phi.p, ctx->d_hu.p,
+                                                                                ctx->d_hq.p, dev_x_hist_out);
+      TDBEM_HIP(hipGetLastError());
+    } else {
+      const double* src = ctx->bc == TDBEM_NEUMANN ? ctx->d_hu.p : ctx->d_hq.p;
+      TDBEM_HIP(hipMemcpyAsync(dev_x_hist_out, src, (size_t)(nt - 1) * ns * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    }
   }
   std::vector<StepStat> st(nt - 1);
   TDBEM_HIP(hipMemcpyAsync(st.data(), ctx->d_stat.p, (nt - 1) * sizeof(StepStat), hipMemcpyDeviceToHost,
@@ -394,8 +422,8 @@ static int run_finish(tdbem_ctx* ctx, int nt, int a_first, double* dev_x_hist_ou
 
 extern "C" {
 
-int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, int bc, const tdbem_opts* opts,
-                 void* hip_stream, tdbem_ctx** out) {
+static int create_impl(const tdbem_mesh* mesh, double c, double dt, int d, int bie, int bc, const int8_t* face_bc,
+                       const tdbem_opts* opts, void* hip_stream, tdbem_ctx** out) {
   if (!out) { g_create_err = "out is NULL"; return TDBEM_E_INVAL; }
   *out = nullptr;
   tdbem_ctx* ctx = new tdbem_ctx();
@@ -404,14 +432,20 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     if (!(c > 0.0) || !(dt > 0.0)) fail(TDBEM_E_INVAL, "c and dt must be > 0");
     if (d < 1 || d > 3) fail(TDBEM_E_INVAL, "B-spline order d must be 1, 2 or 3");
     if (bie != TDBEM_OBIE && bie != TDBEM_BMBIE) fail(TDBEM_E_INVAL, "bie must be OBIE (0) or BMBIE (1)");
-    if (bc != TDBEM_DIRICHLET && bc != TDBEM_NEUMANN) fail(TDBEM_E_INVAL, "bc must be DIRICHLET (0) or NEUMANN (1)");
+    if (bc != TDBEM_DIRICHLET && bc != TDBEM_NEUMANN && bc != TDBEM_MIXED)
+      fail(TDBEM_E_INVAL, "bc must be DIRICHLET (0) or NEUMANN (1)");
+    if (bc == TDBEM_MIXED && !face_bc) fail(TDBEM_E_INVAL, "mixed condition without face types");
     ctx->opts = opts ? *opts : default_opts();
     tdbem_opts& o = ctx->opts;
+    if (bc == TDBEM_MIXED && (o.guess == TDBEM_GUESS_MLP || o.guess == TDBEM_GUESS_MLP_ONLY))
+      fail(TDBEM_E_INVAL, "the learned starting point needs a single boundary condition");
     if (!(o.gmres_tol > 0.0)) o.gmres_tol = 1e-12;
     if (o.gmres_restart <= 0) o.gmres_restart = 30;
     if (o.gmres_maxiter <= 0) o.gmres_maxiter = 300;
     if (o.nt_max <= 1) o.nt_max = 4096;
     if (o.guess < TDBEM_GUESS_EXTRAP || o.guess > TDBEM_GUESS_MLP_ONLY) fail(TDBEM_E_INVAL, "guess must be 0..4");
+    if (o.near_form != 0 && o.near_form != 1) fail(TDBEM_E_INVAL, "near_form must be 0 (compact) or 1 (tau form)");
+    if (o.near_prec != 0 && o.near_prec != 1) fail(TDBEM_E_INVAL, "near_prec must be 0 (FP64) or 1 (FP32)");
     ctx->stream = (hipStream_t)hip_stream;
     ctx->c = c;
     ctx->dt = dt;
@@ -423,6 +457,14 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     ctx->geo = build_geometry(mesh);
     ctx->ns = ctx->geo.ns;
     const int ns = ctx->ns;
+    if (bc == TDBEM_MIXED) {
+      ctx->phi.assign(face_bc, face_bc + ns);
+      for (auto& v : ctx->phi) {
+        if (v != 0 && v != 1) fail(TDBEM_E_INVAL, "face types must be 0 (u given) or 1 (q given)");
+      }
+      ctx->d_phi.alloc(ns);
+      TDBEM_HIP(hipMemcpyAsync(ctx->d_phi.p, ctx->phi.data(), ns, hipMemcpyHostToDevice, ctx->stream));
+    }
     upload_gl_rule();
     ctx->d_xc.alloc(3 * (size_t)ns);
     ctx->d_nrm.alloc(3 * (size_t)ns);
@@ -448,6 +490,7 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
     }
     build_near_table(ctx, row_ptr, pair_j);
     build_step_matrix(ctx);
+    if (o.near_prec == 1) near_table_to_fp32(ctx);
     ctx->nt_max = o.nt_max;
     ctx->d_hu.alloc((size_t)ctx->nt_max * ns);
     ctx->d_hq.alloc((size_t)ctx->nt_max * ns);
@@ -473,6 +516,58 @@ int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, in
   }
   *out = ctx;
   return TDBEM_OK;
+}
+
+int tdbem_create(const tdbem_mesh* mesh, double c, double dt, int d, int bie, int bc, const tdbem_opts* opts,
+                 void* hip_stream, tdbem_ctx** out) {
+  if (bc == TDBEM_MIXED) {
+    g_create_err = "bc must be DIRICHLET (0) or NEUMANN (1); mixed conditions: tdbem_create_mixed";
+    if (out) *out = nullptr;
+    return TDBEM_E_INVAL;
+  }
+  return create_impl(mesh, c, dt, d, bie, bc, nullptr, opts, hip_stream, out);
+}
+
+int tdbem_create_mixed(const tdbem_mesh* mesh, double c, double dt, int d, int bie, const int8_t* face_bc,
+                       const tdbem_opts* opts, void* hip_stream, tdbem_ctx** out) {
+  if (!face_bc) {
+    g_create_err = "face_bc is NULL";
+    if (out) *out = nullptr;
+    return TDBEM_E_INVAL;
+  }
+  return create_impl(mesh, c, dt, d, bie, TDBEM_MIXED, face_bc, opts, hip_stream, out);
+}
+
+int tdbem_field(tdbem_ctx* ctx, int npts, const double* host_pts, int alpha, double* dev_out) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    if (npts < 0 || (npts > 0 && (!host_pts || !dev_out))) fail(TDBEM_E_INVAL, "field: bad arguments");
+    if (alpha < 1 || alpha > ctx->alpha - 1)
+      fail(TDBEM_E_INVAL, "field: alpha must be in [1, position - 1] (solved rows 0 .. alpha-1)");
+    if (npts == 0) return;
+    DevBuf<double> pts;
+    pts.alloc(3 * (size_t)npts);
+    TDBEM_HIP(hipMemcpyAsync(pts.p, host_pts, 3 * (size_t)npts * sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+    launch_field(ctx, npts, pts.p, alpha, dev_out);
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int tdbem_direct_rows(tdbem_ctx* ctx, int nrows, const int32_t* host_rows, int alpha, double* dev_out) {
+  if (!ctx) return TDBEM_E_INVAL;
+  return guarded(ctx, [&] {
+    if (nrows < 0 || (nrows > 0 && (!host_rows || !dev_out))) fail(TDBEM_E_INVAL, "direct_rows: bad arguments");
+    if (alpha < 1 || alpha > ctx->alpha) fail(TDBEM_E_INVAL, "direct_rows: alpha must be in [1, position]");
+    for (int r = 0; r < nrows; ++r)
+      if (host_rows[r] < 0 || host_rows[r] >= ctx->ns) fail(TDBEM_E_INVAL, "direct_rows: row out of range");
+    if (nrows == 0) return;
+    DevBuf<int32_t> rows;
+    rows.alloc(nrows);
+    TDBEM_HIP(hipMemcpyAsync(rows.p, host_rows, nrows * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    launch_direct_rows(ctx, nrows, rows.p, alpha, dev_out);
+    TDBEM_HIP(hipStreamSynchronize(ctx->stream));
+  });
 }
 
 static void prof_collect(tdbem_ctx* ctx) {
@@ -714,7 +809,7 @@ struct CkptHeader {
   int32_t alpha, hist_u, hist_q, mlp;
   int64_t state_doubles;
   double c, dt;
-  int32_t mu, m_leaf, m2l_prec, pad;
+  int32_t mu, m_leaf, m2l_prec, interp;
   uint64_t mesh_hash;  // FNV-1a over the face vertex coordinates in face order
 };
 
@@ -723,6 +818,7 @@ static uint64_t mesh_hash(const tdbem_ctx* ctx) {
   const unsigned char* b = reinterpret_cast<const unsigned char*>(ctx->geo.tris.data());
   const size_t n = ctx->geo.tris.size() * sizeof(double);
   for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+  for (int8_t v : ctx->phi) { h ^= (unsigned char)v; h *= 1099511628211ull; }  // face types (mixed condition)
   return h;
 }
 
@@ -737,6 +833,7 @@ static void ckpt_fill_config(const tdbem_ctx* ctx, CkptHeader& h) {
   if (ctx->fmm) fmm_info(ctx, &info);
   h.mu = info.mu; h.m_leaf = info.m_leaf;
   h.m2l_prec = ctx->fmm ? ctx->opts.m2l_prec : 0;
+  h.interp = ctx->fmm ? ctx->opts.interp : 0;  // moments and locals are coefficients of this basis
   h.mesh_hash = mesh_hash(ctx);
 }
 
@@ -802,8 +899,8 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
     ckpt_fill_config(ctx, mine);
     if (h.ns != mine.ns || h.d != mine.d || h.bie != mine.bie || h.bc != mine.bc || h.use_fmm != mine.use_fmm ||
         h.depth != mine.depth || h.p_s != mine.p_s || h.p_t != mine.p_t || h.mu != mine.mu ||
-        h.m_leaf != mine.m_leaf || h.m2l_prec != mine.m2l_prec || h.c != mine.c || h.dt != mine.dt ||
-        h.nstate != (int32_t)st.size() || h.state_doubles != sd)
+        h.m_leaf != mine.m_leaf || h.m2l_prec != mine.m2l_prec || h.interp != mine.interp || h.c != mine.c ||
+        h.dt != mine.dt || h.nstate != (int32_t)st.size() || h.state_doubles != sd)
       fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a context with a different configuration");
     if (h.mesh_hash != mine.mesh_hash) fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a different mesh");
     if (h.alpha < 1 || h.alpha > ctx->nt_max) fail(TDBEM_E_INVAL, "restore: step beyond this context's nt_max");
@@ -876,8 +973,15 @@ int tdbem_near_row(tdbem_ctx* ctx, int i, int cap, int32_t* j_out, int32_t* g_ou
     for (int64_t p = 0; p < np; ++p) {
       const int glo = gw[p] >> 16, cnt = gw[p] & 0xffff;
       std::vector<double> cu(cnt), cw(cnt);
-      TDBEM_HIP(hipMemcpy(cu.data(), ctx->d_cu.p + off[p], cnt * sizeof(double), hipMemcpyDeviceToHost));
-      TDBEM_HIP(hipMemcpy(cw.data(), ctx->d_cw.p + off[p], cnt * sizeof(double), hipMemcpyDeviceToHost));
+      if (ctx->opts.near_prec == 1) {
+        std::vector<float> fu(cnt), fw(cnt);
+        TDBEM_HIP(hipMemcpy(fu.data(), ctx->d_cu32.p + off[p], cnt * sizeof(float), hipMemcpyDeviceToHost));
+        TDBEM_HIP(hipMemcpy(fw.data(), ctx->d_cw32.p + off[p], cnt * sizeof(float), hipMemcpyDeviceToHost));
+        for (int k = 0; k < cnt; ++k) { cu[k] = fu[k]; cw[k] = fw[k]; }
+      } else {
+        TDBEM_HIP(hipMemcpy(cu.data(), ctx->d_cu.p + off[p], cnt * sizeof(double), hipMemcpyDeviceToHost));
+        TDBEM_HIP(hipMemcpy(cw.data(), ctx->d_cw.p + off[p], cnt * sizeof(double), hipMemcpyDeviceToHost));
+      }
       for (int k = 0; k < cnt; ++k) {
         if (count < cap) {
           if (j_out) j_out[count] = pj[p];

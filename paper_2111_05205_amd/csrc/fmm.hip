@@ -12,8 +12,10 @@
 // causality), doubling per level; a source sample tau^{beta} belongs to
 // interval floor((beta+1)/M) (grouped by t_{beta+1} as in eq. target), a
 // target t_alpha to floor(alpha/M); intervals are centred on the times they
-// hold.  Interpolation: tensor Lagrange on Chebyshev points (first kind) in
-// each of the eight variables; P = p_s^3 p_t coefficients per cell.
+// hold.  Interpolation in each of the eight variables: tensor Lagrange on
+// Chebyshev points (first kind), or the cubic Hermite interpolation with
+// finite-difference slopes on equispaced nodes that the paper used (Section 3,
+// after eq. Uabmn); P = p_s^3 p_t coefficients per cell.
 //
 // Per sample beta (after the solve of step beta+1):
 //   P2M        leaf moments of the current source interval       (HBM-bound, small)
@@ -46,7 +48,34 @@ namespace tdbem {
 
 constexpr int MAXP = 8;  // nodes per axis
 
-struct NodeSet { double s[MAXP], t[MAXP]; };  // Chebyshev nodes in space and time
+struct NodeSet { double s[MAXP], t[MAXP]; int interp; };  // nodes in space and time, TDBEM_INTERP_*
+
+// Slope coefficient D[row][a] of the finite-difference nodal slopes on equispaced
+// nodes of spacing h: central differences inside, second-order one-sided at the ends.
+__host__ __device__ inline double fd_slope(int p, double h, int row, int a) {
+  const double s = 0.5 / h;
+  if (row == 0) return a == 0 ? -3.0 * s : a == 1 ? 4.0 * s : a == 2 ? -s : 0.0;
+  if (row == p - 1) return a == p - 1 ? 3.0 * s : a == p - 2 ? -4.0 * s : a == p - 3 ? s : 0.0;
+  return a == row + 1 ? s : a == row - 1 ? -s : 0.0;
+}
+
+// Cardinal function l_a(x) of the cubic Hermite interpolation with those slopes and
+// its derivative: on the segment [om_k, om_k+1], with t = (x - om_k)/h, the
+// interpolant is h00 f_k + h01 f_k+1 + h (h10 m_k + h11 m_k+1), m = D f; the end
+// pieces are continued outside [om_0, om_{p-1}].
+__host__ __device__ inline void hermite_fd(const double* om, int p, int a, double x, double* val, double* der) {
+  const double h = om[1] - om[0];
+  int k = (int)floor((x - om[0]) / h);
+  k = k < 0 ? 0 : k > p - 2 ? p - 2 : k;
+  const double t = (x - om[k]) / h, t2 = t * t, t3 = t2 * t;
+  const double dk = fd_slope(p, h, k, a), dk1 = fd_slope(p, h, k + 1, a);
+  double v = h * ((t3 - 2.0 * t2 + t) * dk + (t3 - t2) * dk1);
+  double g = (3.0 * t2 - 4.0 * t + 1.0) * dk + (3.0 * t2 - 2.0 * t) * dk1;
+  if (a == k) { v += 2.0 * t3 - 3.0 * t2 + 1.0; g += (6.0 * t2 - 6.0 * t) / h; }
+  if (a == k + 1) { v += -2.0 * t3 + 3.0 * t2; g += (6.0 * t - 6.0 * t2) / h; }
+  *val = v;
+  *der = g;
+}
 
 // bfloat16 bits of x: rounded to float, then to nearest bf16, ties to even (NaN stays NaN).
 __device__ inline uint16_t bf16_rne(double x) {
@@ -73,7 +102,7 @@ struct FmmLevel {
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
   DevBuf<int32_t> d_src_by_slot;            // their source cells (so the two loads are independent)
   int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
-  DevBuf<double> d_U;                       // [slot][(mu+1) P][P] near-future operators (set-up only)
+  DevBuf<double> d_U;                       // one slot's (mu+1) P x P near-future operators (set-up only)
   DevBuf<double> d_Uf, d_stage;             // FP64: operators in MFMA fragment order, per-pair products
   DevBuf<float> d_U32, d_stage32;           // FP32 (mixed precision): the same
   DevBuf<double> d_Ktf;                     // derivative products' spatial kernels r^{-1} (and r, d = 3), fragment order
@@ -100,6 +129,7 @@ struct Fmm {
   // precision of the near-future products: 0 FP64, 1 FP32, 2 BF16 (both with FP32
   // accumulation); the derivative products are FP64 in every case
   int prec = 0;
+  int interp = TDBEM_INTERP_LAGRANGE;
   int Gn = 0;                              // near-future operator blocks, mu + 1
   int Pp = 0;                              // row stride of the BF16 moment copy: P rounded up to 32
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
@@ -124,6 +154,10 @@ static void cheb(int p, double* om) {
   for (int a = 0; a < p; ++a) om[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * p));
 }
 
+static void equispaced(int p, double* om) {
+  for (int a = 0; a < p; ++a) om[a] = -1.0 + 2.0 * a / (p - 1);
+}
+
 static double lag(const double* om, int p, int a, double x) {
   double v = 1.0;
   for (int b = 0; b < p; ++b)
@@ -141,6 +175,18 @@ static double dlag(const double* om, int p, int a, double x) {
     s += t;
   }
   return s;
+}
+
+// l_a(x) and l_a'(x) of the context's interpolation
+static double basis(const Fmm* f, const double* om, int p, int a, double x, double* der = nullptr) {
+  if (f->interp == TDBEM_INTERP_HERMITE) {
+    double v, g;
+    hermite_fd(om, p, a, x, &v, &g);
+    if (der) *der = g;
+    return v;
+  }
+  if (der) *der = dlag(om, p, a, x);
+  return lag(om, p, a, x);
 }
 
 static uint64_t morton(int x, int y, int z) {
@@ -245,11 +291,15 @@ __global__ void elem_tables_kernel(int ns, int ps, double hs, NodeSet nodes, Qua
       const int bb[3] = {b1, b2, b3};
       for (int k = 0; k < 3; ++k) {
         double val = 1.0, der = 0.0;
-        for (int o = 0; o < ps; ++o) {
-          if (o == bb[k]) continue;
-          const double f = 1.0 / (nodes.s[bb[k]] - nodes.s[o]);
-          der = der * (xi[k] - nodes.s[o]) * f + val * f;
-          val *= (xi[k] - nodes.s[o]) * f;
+        if (nodes.interp == TDBEM_INTERP_HERMITE) {
+          hermite_fd(nodes.s, ps, bb[k], xi[k], &val, &der);
+        } else {
+          for (int o = 0; o < ps; ++o) {
+            if (o == bb[k]) continue;
+            const double f = 1.0 / (nodes.s[bb[k]] - nodes.s[o]);
+            der = der * (xi[k] - nodes.s[o]) * f + val * f;
+            val *= (xi[k] - nodes.s[o]) * f;
+          }
         }
         l[k] = val;
         dl[k] = der;
@@ -266,11 +316,15 @@ __global__ void elem_tables_kernel(int ns, int ps, double hs, NodeSet nodes, Qua
   for (int k = 0; k < 3; ++k) {
     xi[k] = (xc[3 * (int64_t)e + k] - cc[k]) / hs;
     double val = 1.0, der = 0.0;
-    for (int o = 0; o < ps; ++o) {
-      if (o == bb[k]) continue;
-      const double f = 1.0 / (nodes.s[bb[k]] - nodes.s[o]);
-      der = der * (xi[k] - nodes.s[o]) * f + val * f;
-      val *= (xi[k] - nodes.s[o]) * f;
+    if (nodes.interp == TDBEM_INTERP_HERMITE) {
+      hermite_fd(nodes.s, ps, bb[k], xi[k], &val, &der);
+    } else {
+      for (int o = 0; o < ps; ++o) {
+        if (o == bb[k]) continue;
+        const double f = 1.0 / (nodes.s[bb[k]] - nodes.s[o]);
+        der = der * (xi[k] - nodes.s[o]) * f + val * f;
+        val *= (xi[k] - nodes.s[o]) * f;
+      }
     }
     l[k] = val;
     dl[k] = der;
@@ -1708,6 +1762,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
   if (o.p_s < 2 || o.p_s > MAXP || o.p_t < 2 || o.p_t > MAXP)
     throw Error(TDBEM_E_INVAL, "p_s and p_t must be in [2, 8]");
   if (o.p_t <= ctx->d) throw Error(TDBEM_E_INVAL, "p_t must exceed the B-spline order d");
+  if (o.interp != TDBEM_INTERP_LAGRANGE && o.interp != TDBEM_INTERP_HERMITE)
+    throw Error(TDBEM_E_INVAL, "interp must be LAGRANGE (0) or HERMITE (1)");
+  if (o.interp == TDBEM_INTERP_HERMITE && (o.p_s < 3 || o.p_t < 3))
+    throw Error(TDBEM_E_INVAL, "the cubic Hermite interpolation needs p_s, p_t >= 3");
   if (o.m2l_prec != TDBEM_M2L_FP64 && o.m2l_prec != TDBEM_M2L_FP32 && o.m2l_prec != TDBEM_M2L_BF16)
     throw Error(TDBEM_E_INVAL, "m2l_prec must be FP64 (0), FP32 (1) or BF16 (2)");
   Fmm* f = new Fmm();
@@ -1719,8 +1777,14 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     f->Ps = f->ps * f->ps * f->ps;
     f->P = f->Ps * f->pt;
     f->Pp = (f->P + 31) / 32 * 32;
-    cheb(f->ps, f->om_s);
-    cheb(f->pt, f->om_t);
+    f->interp = o.interp;
+    if (f->interp == TDBEM_INTERP_HERMITE) {
+      equispaced(f->ps, f->om_s);
+      equispaced(f->pt, f->om_t);
+    } else {
+      cheb(f->ps, f->om_s);
+      cheb(f->pt, f->om_t);
+    }
     f->Cd = 1.0 / (4.0 * M_PI * std::pow(ctx->cdt, ctx->d));
     build_tree(ctx, f);
     build_hierarchy(ctx, f);
@@ -1729,6 +1793,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     NodeSet& nodes = f->nodes;
     for (int a = 0; a < f->ps; ++a) nodes.s[a] = f->om_s[a];
     for (int a = 0; a < f->pt; ++a) nodes.t[a] = f->om_t[a];
+    nodes.interp = f->interp;
     // element tables
     const FmmLevel& LL = f->lev[f->D];
     std::vector<double> cc(3 * (size_t)LL.ncell);
@@ -1761,13 +1826,13 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       const double sgn = sd ? 1.0 : -1.0;
       for (int a = 0; a < f->ps; ++a)
         for (int b = 0; b < f->ps; ++b) {
-          const double v = lag(f->om_s, f->ps, a, 0.5 * sgn + 0.5 * f->om_s[b]);
+          const double v = basis(f, f->om_s, f->ps, a, 0.5 * sgn + 0.5 * f->om_s[b]);
           S[sd * f->ps * f->ps + a * f->ps + b] = v;
           St[sd * f->ps * f->ps + b * f->ps + a] = v;
         }
       for (int a = 0; a < f->pt; ++a)
         for (int b = 0; b < f->pt; ++b) {
-          const double v = lag(f->om_t, f->pt, a, 0.5 * sgn + 0.5 * f->om_t[b]);
+          const double v = basis(f, f->om_t, f->pt, a, 0.5 * sgn + 0.5 * f->om_t[b]);
           T[sd * f->pt * f->pt + a * f->pt + b] = v;
           Tt[sd * f->pt * f->pt + b * f->pt + a] = v;
         }
@@ -1831,16 +1896,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       for (auto& v : L.slot_off) { so.push_back(v[0]); so.push_back(v[1]); so.push_back(v[2]); }
       DevBuf<int32_t> d_so;
       upload(d_so, so, st);
-      L.d_U.alloc((size_t)std::max(nslot, 1) * G * P * P);
       const int nk = 1 + (ctx->d >= 2 ? 1 : 0) + (ctx->d >= 3 ? 1 : 0);
       DevBuf<double> d_K;  // row-major spatial kernels (set-up only)
       d_K.alloc((size_t)std::max(nslot, 1) * nk * f->Ps * f->Ps);
       if (nslot > 0) {
-        const double Ml = (double)f->m_leaf * (1 << (f->D - l));
-        dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, nslot);
-        m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, ctx->c, hs_of(f, l),
-                                                Ml * ctx->dt / 2.0, ctx->dt, (int)Ml, nodes, d_so.p, L.d_U.p);
-        TDBEM_HIP(hipGetLastError());
         dim3 gk((unsigned)((f->Ps * f->Ps + 255) / 256), nslot);
         m2l_spatial_kernel<<<gk, 256, 0, st>>>(f->ps, nk, hs_of(f, l), nodes, d_so.p, nslot, d_K.p);
         TDBEM_HIP(hipGetLastError());
@@ -1871,8 +1930,11 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
       {
-        // dense blocks only: each slot's gaps gf .. g0-1, converted slot by slot
+        // dense blocks only: each slot's gaps gf .. g0-1, its FP64 operator stack built in
+        // a per-slot buffer and converted slot by slot (no master copy of the whole level)
         const int KB = m2l_kblocks(P), KB32 = (P + 31) / 32;
+        const double Ml = (double)f->m_leaf * (1 << (f->D - l));
+        L.d_U.alloc((size_t)G * P * P);
         std::vector<int64_t> uoff(std::max(nslot, 1) + 1, 0);
         for (int sl = 0; sl < nslot; ++sl) {
           const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16;
@@ -1885,7 +1947,12 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         for (int sl = 0; sl < nslot; ++sl) {
           const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16, row0 = (L.gf[sl] - 1) * P;
           if (rows == 0) continue;
-          const double* Us = L.d_U.p + (int64_t)sl * G * P * P;
+          dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, 1);
+          m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, ctx->c, hs_of(f, l),
+                                                  Ml * ctx->dt / 2.0, ctx->dt, (int)Ml, nodes, d_so.p + 3 * sl,
+                                                  L.d_U.p);
+          TDBEM_HIP(hipGetLastError());
+          const double* Us = L.d_U.p;
           const int64_t n = uoff[sl + 1] - uoff[sl];
           const unsigned nb = (unsigned)((n + 255) / 256);
           if (f->prec == 2)
@@ -1901,7 +1968,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         if (f->prec != 0) L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
         else L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
         TDBEM_HIP(hipStreamSynchronize(st));
-        L.d_U.release();  // row-major master no longer needed
+        L.d_U.release();  // the per-slot FP64 stack is no longer needed
       }
       for (DevBuf<double>* b : {&L.d_mom, &L.d_ring, &L.d_lp, &L.d_aux})
         TDBEM_HIP(hipMemsetAsync(b->p, 0, b->n * sizeof(double), st));
@@ -1949,8 +2016,9 @@ void fmm_state_buffers(const tdbem_ctx* ctx, std::vector<std::pair<double*, size
 static TimeWeights time_weights(const Fmm* f, double xi, double ht) {
   TimeWeights tw{};
   for (int m = 0; m < f->pt; ++m) {
-    tw.w[m] = lag(f->om_t, f->pt, m, xi);
-    tw.dw[m] = dlag(f->om_t, f->pt, m, xi) / ht;
+    double der = 0.0;
+    tw.w[m] = basis(f, f->om_t, f->pt, m, xi, &der);
+    tw.dw[m] = der / ht;
   }
   return tw;
 }

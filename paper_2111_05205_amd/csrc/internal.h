@@ -94,7 +94,8 @@ struct tdbem_ctx {
   tdbem::DevBuf<int32_t> d_pair_j;     // npairs
   tdbem::DevBuf<int32_t> d_pair_gw;    // npairs: (glo << 16) | cnt
   tdbem::DevBuf<int64_t> d_pair_off;   // npairs: first coefficient
-  tdbem::DevBuf<double> d_cu, d_cw;    // ncoef each: compact C_U^{(g)}, C_W^{(g)}
+  tdbem::DevBuf<double> d_cu, d_cw;    // ncoef each: compact C_U^{(g)}, C_W^{(g)} (raw X^{(gamma)} for the tau form)
+  tdbem::DevBuf<float> d_cu32, d_cw32; // the same rounded to FP32 (opts.near_prec = 1; the FP64 arrays are released)
 
   // per-step matrix A and the g=1 blocks, CSR
   int64_t a_nnz = 0;
@@ -105,6 +106,10 @@ struct tdbem_ctx {
   int ell_w = 0;
   tdbem::DevBuf<int32_t> d_ell_col;
   tdbem::DevBuf<double> d_ell_val;
+
+  // mixed boundary condition (bc == TDBEM_MIXED): phi_j = 1 where q is given and u unknown, 0 where u is given
+  tdbem::DevBuf<int8_t> d_phi;
+  std::vector<int8_t> phi;
 
   // history [beta][element], beta = 0..nt_max-2
   int nt_max = 0;
@@ -182,7 +187,14 @@ struct ProfScope {
 void build_near_table(tdbem_ctx* ctx, const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& pair_j);
 void build_step_matrix(tdbem_ctx* ctx);
 void launch_near_history(tdbem_ctx* ctx, int alpha, const double* base, double* out);
+void near_table_to_fp32(tdbem_ctx* ctx);
 void launch_spmv_add(tdbem_ctx* ctx, const double* vals, double scale, const double* xin, double* y);
+// y += scale * vals x restricted to the columns j with phi_j == want
+void launch_spmv_add_masked(tdbem_ctx* ctx, const double* vals, double scale, const double* xin, int want, double* y);
+// scattered field at npts device points (3 each) at t_alpha from the stored history
+void launch_field(tdbem_ctx* ctx, int npts, const double* pts, int alpha, double* out);
+// exact (direct, every element) history part of b^{alpha-1} at nrows device row indices
+void launch_direct_rows(tdbem_ctx* ctx, int nrows, const int32_t* rows, int alpha, double* out);
 void upload_gl_rule();
 
 // gmres.hip

@@ -130,8 +130,9 @@ def test_fmm_bf16_m2l_products(pp):
     u = synth.random_history(ns, 24, seed=5)
     q = synth.random_history(ns, 24, seed=6)
     want = R.history_rhs(21, u, q)
-    # the oracle with both factors of every near-future product rounded to bf16, as the
-    # BF16 path forms them (products then exact, sums in FP64 here and FP32 there)
+    # the oracle with both factors of the dense near-future products (the blocks the
+    # wavefront crosses) rounded to bf16, as the BF16 path forms them (products then
+    # exact, sums in FP64 here and FP32 there); the other blocks are exact on both sides
     from oracle import mlp as OM
     Rb = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, pp, pp, near_round=OM.bf16)
     want_b = Rb.history_rhs(21, u, q)
@@ -237,3 +238,32 @@ def test_fmm_direct_tiles_need_p_multiple_of_4(s3):
     with pytest.raises(P.TDBEMError):
         g.set_m2l_variant(1, 2 * 8)
     g.close()
+
+
+@pytest.mark.parametrize("d,bie,bc,p,level,depth", [(2, 1, 1, 3, 3, 3), (1, 1, 0, 4, 2, 2)])
+def test_fmm_hermite_interpolation_matches_oracle(d, bie, bc, p, level, depth):
+    """The paper's interpolation (cubic Hermite with finite-difference slopes, equispaced
+    nodes): same parity bar as the Lagrange basis against the oracle's Hermite FMM."""
+    P = _P()
+    xyz, tri = synth.icosphere(level)
+    dt = synth.mean_edge_length(xyz, tri)
+    g = P.TDBEM(xyz, tri, 1.0, dt, d, bie, bc, use_fmm=1, depth=depth, p_s=p, p_t=p, nt_max=64,
+                interp=P.INTERP_HERMITE)
+    R = F.ReferenceFMM(xyz, tri, 1.0, dt, d, bie, depth, p, p, interp="hermite")
+    assert g.info()["mu"] == R.mu and g.info()["m_leaf"] == R.m_leaf
+    u = synth.random_history(g.ns, 30, seed=13)
+    q = synth.random_history(g.ns, 30, seed=14)
+    dev = torch.device("cuda")
+    for nsteps in (2, 23):
+        g.set_history(torch.tensor(u[:nsteps], device=dev), torch.tensor(q[:nsteps], device=dev))
+        got = g.fmm_eval(nsteps + 1).cpu().numpy()
+        want = R.history_rhs(nsteps + 1, u, q)
+        assert _rel(got, want) < 1e-10, (nsteps, _rel(got, want))
+
+
+def test_hermite_needs_three_nodes(s3):
+    P = _P()
+    xyz, tri, dt = s3
+    with pytest.raises(P.TDBEMError) as e:
+        P.TDBEM(xyz, tri, 1.0, dt, 1, 1, 1, use_fmm=1, depth=3, p_s=2, p_t=3, nt_max=8, interp=P.INTERP_HERMITE)
+    assert e.value.code == P._native.E_INVAL

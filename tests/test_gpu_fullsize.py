@@ -67,7 +67,11 @@ def test_fmm_near_table_matches_oracle_at_sampled_rows(w5k):
 
 
 def test_fmm_march_accuracy_and_fp32_products(w5k, direct_march):
-    """FMM vs direct (interpolation error, measured 3.7e-2) and FP32 vs FP64 M2L products."""
+    """FMM vs direct, and FP32 vs FP64 near-future products.  The FMM's error is its
+    interpolation error (Section 3, eq. U_intp), which the <= 1e-4 gate does not meet at the
+    workload's order: the measured floor at p = 4 is 3.74e-2, and it falls with the spatial
+    order (p = 6: 2.98e-3; the oracle pins why it cannot fall faster: the kernel's kink where
+    the wavefront crosses a cell pair)."""
     import paper_2111_05205_amd as P
     u_direct, _ = direct_march
     s = _ctx(w5k)
@@ -75,7 +79,12 @@ def test_fmm_march_accuracy_and_fp32_products(w5k, direct_march):
     x64 = x64.cpu().numpy()
     s.close()
     e = np.linalg.norm(x64 - u_direct) / np.linalg.norm(u_direct)
-    assert 1e-3 < e < 0.05, e
+    assert e <= 0.038, e
+    s6 = _ctx(w5k, p_s=6, p_t=6)
+    x6, _ = s6.run(w5k["nt"], inc=w5k["inc"])
+    e6 = np.linalg.norm(x6.cpu().numpy() - u_direct) / np.linalg.norm(u_direct)
+    s6.close()
+    assert e6 <= 0.0031 and e / e6 > 10, (e, e6)
     s32 = _ctx(w5k, m2l_prec=P.M2L_FP32)
     x32, _ = s32.run(w5k["nt"], inc=w5k["inc"])
     d = np.linalg.norm(x32.cpu().numpy() - x64) / np.linalg.norm(x64)
@@ -89,3 +98,48 @@ def test_fmm_march_accuracy_and_fp32_products(w5k, direct_march):
 def test_smoke_entry_point():
     import __graft_entry__
     __graft_entry__.smoke()
+
+
+def _golden_sphere5k():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "fmm_sphere5k_alpha64.txt")
+    meta = {}
+    with open(path) as fh:
+        for line in fh:
+            if not line.startswith("#"):
+                break
+            toks = line[1:].split()
+            for k, v in zip(toks[::2], toks[1::2]):
+                meta[k] = v
+    return np.loadtxt(path, comments="#"), meta
+
+
+def test_fmm_history_sum_matches_oracle_fmm_at_the_benchmarked_size(w5k):
+    """GPU FMM vs the oracle's reference FMM (Algorithm 1, FP64) at the workload's parameters
+    (5120 faces, depth 4, p_s = p_t = 4, mu = 11, three M2L levels), every row: the history sum
+    b^{alpha-1} at alpha = 64 (an interval end at every level) for a seeded synthetic history,
+    stored by tests/golden/make_fmm_sphere5k.py.  FP64 products with every tile the autotuner
+    may pick, and FP32 products."""
+    import paper_2111_05205_amd as P
+    want, meta = _golden_sphere5k()
+    alpha = int(meta["alpha"])
+    ns = w5k["tri"].shape[0]
+    u = synth.random_history(ns, alpha - 1, seed=11)
+    q = synth.random_history(ns, alpha - 1, seed=12)
+    dev = torch.device("cuda")
+    for prec, tol in ((P.M2L_FP64, 1e-10), (P.M2L_FP32, 1e-4)):
+        s = _ctx(w5k, m2l_prec=prec, nt_max=alpha + 2)
+        info = s.info()
+        assert info["mu"] == int(meta["mu"]) and info["m_leaf"] == int(meta["m_leaf"])
+        assert info["near_pairs"] == int(meta["near_pairs"])
+        choices = [None] if prec == P.M2L_FP32 else [None, 2 * 6, 2 * 9, 2 * 11 + 1]
+        for ch in choices:
+            if ch is not None:
+                for n in (1, 2, 3):
+                    s.set_m2l_variant(n, ch)
+            s.set_history(torch.tensor(u, device=dev), torch.tensor(q, device=dev))
+            got = s.fmm_eval(alpha).cpu().numpy()
+            e = np.linalg.norm(got - want) / np.linalg.norm(want)
+            print(f"prec {prec} variant {ch}: rel L2 vs oracle FMM {e:.2e}")
+            assert e < tol, (prec, ch, e)
+        s.close()
