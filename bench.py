@@ -10,12 +10,13 @@ W warm-up steps follow, then K timed steps.  Workloads sphere5k / sphere20k: one
 operators) are resident in HBM before the timed region.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload sphere82k|sphere5k|batch64]
-                  [--mode fmm|direct] [--form both|mixed|plain] [--gmres-tol 1e-8]
-                  [--no-cpu-baseline] [--no-accuracy]
+                  [--mode fmm|direct] [--form both|mixed|plain] [--mixed-m2l bf16x3|fp32]
+                  [--gmres-tol 1e-8] [--no-cpu-baseline] [--no-accuracy]
 
-The headline value is the mixed form (FP32 near-future M2L products, learned GMRES
-starting point); the plain FP64 form is timed beside it (plain_fp64,
-speedup_vs_fp64_plain).
+The headline value is the mixed form (near-future M2L products from split BF16
+factors, x = hi + lo, three bf16 products with FP32 accumulation, or FP32 with
+--mixed-m2l fp32; learned GMRES starting point); the plain FP64 form is timed beside
+it (plain_fp64, speedup_vs_fp64_plain).
 """
 import argparse
 import json
@@ -32,6 +33,9 @@ METRIC = "Ns·Nt/sec FMM-TDBEM at rel err ≤1e-4 vs direct; speedup vs FP64 pla
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6        # MI355X dense FP64 (matrix and vector)
 PEAK_FP32_TFLOPS = 157.3       # MI355X dense FP32
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 matrix
+PREC_NAME = {0: "FP64", 1: "FP32", 2: "BF16", 3: "BF16X3: three bf16 products per product"}
+MIXED_TEXT = {"fp32": ("f32", "FP32"), "bf16x3": ("split bf16 x3", "split-BF16 (x = hi + lo, three bf16 products)")}
 
 WORKLOAD_TEXT = {
     "sphere5k": "unit icosphere level 4 (Ns=5120), Nt=256, c dt = mean edge, Burton-Miller BIE, B-spline d=2, "
@@ -89,13 +93,13 @@ def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0, window=None):
                       f"their {nt - 1} history sums ({sec:.1f} s); rate = rows*(Nt-1)/s"}
 
 
-def measured_traffic(prec):
-    """HBM bytes per M2L launch from the committed rocprofv3 counter summary, if it
-    was taken on the current M2L source (else None)."""
+def measured_traffic(prec, workload="sphere5k"):
+    """HBM bytes per M2L launch from the committed rocprofv3 counter summary of this
+    workload, if it was taken on the current M2L source (else None)."""
     import hashlib
     if prec != 1:
         return None
-    path = os.path.join(ROOT, "profiles", "m2l_fp32_sphere5k_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"m2l_fp32_{workload}_traffic.json")
     try:
         rec = json.load(open(path))
         src = m2l_kernel_source()
@@ -159,9 +163,10 @@ def run_form(P, w, args, prec, guess, params=None):
         # the derivative products go through their separable form, a separate small kernel)
         flops = 2 * Pn * Pn * m2l_dense_blocks(info, range(0, nt - 1), info["m_leaf"], info["depth"]) * args.steps
         ms, n = prof["m2l_gemm"]
-        peak = PEAK_FP32_TFLOPS if prec == P.M2L_FP32 else PEAK_FP64_TFLOPS
-        achieved = flops / (ms * 1e-3) / 1e12
-        roof = {"kernel": "m2l_gemm (dense near-future blocks, " + ("FP32)" if mixed else "FP64)"),
+        mult = 3 if prec == P.M2L_BF16X3 else 1
+        peak = {P.M2L_FP32: PEAK_FP32_TFLOPS, P.M2L_BF16X3: PEAK_BF16_TFLOPS}.get(prec, PEAK_FP64_TFLOPS)
+        achieved = mult * flops / (ms * 1e-3) / 1e12
+        roof = {"kernel": "m2l_gemm (dense near-future blocks, " + PREC_NAME[prec] + ")",
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(prec) if args.workload == "sphere5k" else None,
@@ -220,11 +225,15 @@ def run_window(P, w, args, prec, guess, params, a0, hist):
     blocks = m2l_dense_blocks(info, range(a0 - 1, a0 + K - 1), info["m_leaf"], info["depth"])
     flops = 2 * Pn * Pn * blocks
     ms, n = prof["m2l_gemm"]
-    peak = PEAK_FP32_TFLOPS if prec == P.M2L_FP32 else PEAK_FP64_TFLOPS
-    achieved = flops / (ms * 1e-3) / 1e12
-    roof = {"kernel": "m2l_gemm (dense near-future blocks, " + ("FP32)" if prec == P.M2L_FP32 else "FP64)"),
+    # split BF16 products: three bf16 products per product, against the bf16 matrix peak
+    mult = 3 if prec == P.M2L_BF16X3 else 1
+    peak = {P.M2L_FP32: PEAK_FP32_TFLOPS, P.M2L_BF16X3: PEAK_BF16_TFLOPS}.get(prec, PEAK_FP64_TFLOPS)
+    achieved = mult * flops / (ms * 1e-3) / 1e12
+    roof = {"kernel": "m2l_gemm (dense near-future blocks, " + PREC_NAME[prec] + ")",
             "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4), "traffic": measured_traffic(prec, args.workload),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated, averaged over a "
+                            "32-step window)",
             "launches": n, "avg_launch_ms": round(ms / max(n, 1), 4), "dense_block_products": blocks,
             "flops": flops}
     out = {"value": round(ns / sec, 1), "ms_per_step": round(sec * 1e3, 3),
@@ -280,8 +289,8 @@ def sampled_direct_check(s, alpha, b_fmm, nrows=64, seed=7):
 
 
 def window_main(args, P, mlp):
-    """The large single instance: K timed collocation steps of the mixed form (FP32 near-future
-    M2L products, learned starting point) and of the plain FP64 form, each marched untimed to the
+    """The large single instance: K timed collocation steps of the mixed form (split-BF16 or FP32
+    near-future M2L products, learned starting point) and of the plain FP64 form, each marched untimed to the
     window first; accuracy of mixed vs plain over every solved row, and of the FMM history sum
     against the direct oracle at sampled rows."""
     import torch
@@ -303,7 +312,8 @@ def window_main(args, P, mlp):
         del s
     if args.form in ("both", "mixed"):
         hists["mixed"] = torch.zeros(a0 + K, ns, dtype=torch.float64, device="cuda")
-        s, info, forms["mixed"] = run_window(P, w, args, P.M2L_FP32, P.GUESS_MLP, params, a0, hists["mixed"])
+        mprec = P.M2L_BF16X3 if args.mixed_m2l == "bf16x3" else P.M2L_FP32
+        s, info, forms["mixed"] = run_window(P, w, args, mprec, P.GUESS_MLP, params, a0, hists["mixed"])
         s.close()
         del s
     head = forms["mixed"] if "mixed" in forms else forms["plain"]
@@ -313,11 +323,13 @@ def window_main(args, P, mlp):
     out = {"metric": METRIC, "value": head["value"], "unit": "Ns*Nt/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
-           "dtype": "f64 (near-future M2L products f32, starting-point network bf16)" if mixed else "f64",
+           "dtype": f"f64 (near-future M2L products {MIXED_TEXT[args.mixed_m2l][0]}, starting-point network bf16)"
+                    if mixed else "f64",
            "data": "synthetic",
            "config": {"workload": args.workload + ": " + WORKLOAD_TEXT.get(args.workload, ""),
-                      "form": "mixed: FP32 near-future M2L products, FP64 derivative products, near field, "
-                              "recurrences and solve, learned GMRES starting point" if mixed else "plain FP64",
+                      "form": f"mixed: {MIXED_TEXT[args.mixed_m2l][1]} near-future M2L products, FP64 derivative "
+                              "products, near field, recurrences and solve, learned GMRES starting point"
+                              if mixed else "plain FP64",
                       "step": "one collocation step (near field, L2P, GMRES, history update, P2M, and the M2L, "
                               "M2M, L2L of every interval ending there)",
                       "window": f"steps {a0}..{a0 + K - 1} after an untimed march from step 1",
@@ -427,9 +439,13 @@ def main():
     ap.add_argument("--workload", default="sphere82k")
     ap.add_argument("--mode", default="fmm", choices=["fmm", "direct"])
     ap.add_argument("--form", default="both", choices=["both", "mixed", "plain"],
-                    help="mixed: FP32 M2L products + learned starting point; plain: FP64 M2L + extrapolated "
+                    help="mixed: reduced-precision M2L products (--mixed-m2l) + learned starting point; plain: "
+                         "FP64 M2L + extrapolated "
                          "starting point; both: time both, value = mixed")
     ap.add_argument("--gmres-tol", type=float, default=1e-8)
+    ap.add_argument("--mixed-m2l", default="bf16x3", choices=["fp32", "bf16x3"],
+                    help="near-future product precision of the mixed form on the large instance: FP32, or split "
+                         "BF16 (x = hi + lo, three bf16 products)")
     ap.add_argument("--window-start", type=int, default=0,
                     help="first timed step of the large-instance window (default: where the pulse is on the "
                          "surface); smaller values shorten the untimed march, e.g. for counter runs")
@@ -474,7 +490,8 @@ def main():
         s, info, xs["plain"], forms["plain"] = run_form(P, w, args, P.M2L_FP64, P.GUESS_EXTRAP)
         s.close()
     if args.form in ("both", "mixed"):
-        s, info, xs["mixed"], forms["mixed"] = run_form(P, w, args, P.M2L_FP32, P.GUESS_MLP, params)
+        mprec = P.M2L_BF16X3 if args.mixed_m2l == "bf16x3" else P.M2L_FP32
+        s, info, xs["mixed"], forms["mixed"] = run_form(P, w, args, mprec, P.GUESS_MLP, params)
         s.close()
     head = forms["mixed"] if "mixed" in forms else forms["plain"]
     for k, f in forms.items():
@@ -485,11 +502,13 @@ def main():
     out = {"metric": METRIC, "value": head["value"], "unit": "Ns*Nt/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
-           "dtype": "f64 (M2L products f32, starting-point network bf16)" if mixed else "f64",
+           "dtype": f"f64 (near-future M2L products {MIXED_TEXT[args.mixed_m2l][0]}, starting-point network bf16)"
+                    if mixed else "f64",
            "data": "synthetic",
            "config": {"workload": args.workload + ": " + WORKLOAD_TEXT.get(args.workload, ""),
-                      "form": "mixed: FP32 M2L products, FP64 near field/recurrences/solve, learned GMRES "
-                              "starting point" if mixed else "plain FP64",
+                      "form": f"mixed: {MIXED_TEXT[args.mixed_m2l][1]} near-future M2L products, FP64 "
+                              "derivative products, near field, recurrences and solve, learned GMRES starting point"
+                              if mixed else "plain FP64",
                       "mode": "fmm" if use_fmm else "direct", "ns": ns, "nt": nt, "d": info["d"],
                       "mu": info["mu"], "m_leaf": info["m_leaf"], "near_pairs": info["near_pairs"],
                       "il_pairs": info["il_pairs"][: (info["depth"] or 0) + 1],

@@ -50,7 +50,7 @@ enum {
   TDBEM_E_NOMEM = -2,         /* device allocation failed */
   TDBEM_E_DEVICE = -3,        /* HIP runtime error */
   TDBEM_E_NOT_CONVERGED = -4, /* per-step GMRES did not reach its tolerance */
-  TDBEM_E_DIVERGED = -5,      /* non-finite or exploding solution */
+  TDBEM_E_DIVERGED = -5,      /* non-finite or exploding solution, or growth beyond opts.growth_limit */
   TDBEM_E_STATE = -6          /* call out of order (e.g. step beyond nt_max) */
 };
 
@@ -59,11 +59,14 @@ typedef enum { TDBEM_OBIE = 0, TDBEM_BMBIE = 1 } tdbem_bie;          /* eq. bie 
 typedef enum { TDBEM_DIRICHLET = 0, TDBEM_NEUMANN = 1, TDBEM_MIXED = 2 } tdbem_bc;
 /* Precision of the near-future M2L products (Section 4, eq. m2l_near, blocks
  * l = 1..mu+1): FP64, FP32, or BF16 operators and moments (rounded to nearest)
- * on the BF16 matrix cores; FP32 and BF16 accumulate in FP32.  The derivative products
+ * on the BF16 matrix cores, or BF16X3: each factor split as x = hi + lo with hi,
+ * lo in bf16 (lo the rounded remainder), products hi*hi + hi*lo + lo*hi on the
+ * BF16 matrix cores (the lo*lo term, ~2^-16 of the product, is dropped; the same
+ * bytes as FP32).  All but FP64 accumulate in FP32.  The derivative products
  * U^{(p)} M (eq. L_l,k), which feed the recurrence of Formula 1 over every later
- * interval, are FP64 in both (evaluated exactly through the separable form of
+ * interval, are FP64 in every case (evaluated exactly through the separable form of
  * U^{(p)}); moments, locals, recurrence, near field and solve are FP64. */
-typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1, TDBEM_M2L_BF16 = 2 } tdbem_m2l_prec;
+typedef enum { TDBEM_M2L_FP64 = 0, TDBEM_M2L_FP32 = 1, TDBEM_M2L_BF16 = 2, TDBEM_M2L_BF16X3 = 3 } tdbem_m2l_prec;
 typedef enum { TDBEM_INC_GAUSS_MOD = 0, TDBEM_INC_RAISED_COS = 1 } tdbem_inc_kind;
 /* Starting point of the per-step GMRES solve (the paper names no solver):
  * EXTRAP quadratic extrapolation of the last three solved rows (default),
@@ -106,6 +109,12 @@ typedef struct {
   int near_prec;     /* 0: near-field coefficients stored in FP64 (default); 1: rounded to FP32 (study of that
                         cancellation; the sums stay FP64) */
   int interp;        /* FMM interpolation in each of the eight variables (eq. U_intp), tdbem_interp */
+  double growth_limit; /* > 0: growth check of the march (the instability of Section 5.1 shows as a solution
+                          that keeps growing after the incident pulse has passed): step beta fails with
+                          TDBEM_E_DIVERGED when max_i |x_i^beta| exceeds growth_limit times the largest
+                          max_i |x_i^gamma| over gamma <= beta - growth_lag; 0: off (only non-finite or
+                          |x| > 1e100 fail) */
+  int growth_lag;    /* steps between the checked row and the newest reference row (>= 1 when growth_limit > 0) */
 } tdbem_opts;
 
 /* Interpolation functions l_a of eq. U_intp.  LAGRANGE: polynomials on the p Chebyshev

@@ -163,13 +163,16 @@ class ReferenceFMM:
     """History part of the MOT right-hand side with near pairs direct and far pairs by the FMM."""
 
     def __init__(self, xyz, tri, c, dt, d, bie, depth, p_s, p_t, mu=0, m2l="alg1", bc=None, src_ext=None,
-                 near_round=None, interp="lagrange"):
+                 near_round=None, interp="lagrange", near_product=None):
         """near_round: None, or a function applied to both factors (moments and operator) of
         the near-future products (eq. m2l_near) whose operator block is truncated at some node
         pairs and not zero at all of them (where the wavefront crosses the pair's node set),
         e.g. rounding to a lower precision; every other block is a polynomial at the nodes
-        or zero, and those products and the derivative products stay exact."""
+        or zero, and those products and the derivative products stay exact.
+        near_product: None, or a function (X, U) -> X @ U.T as a lower-precision path forms
+        the products of those same blocks (e.g. from split factors)."""
         self.near_round = near_round
+        self.near_product = near_product
         self.geom = g = Geometry(xyz, tri)
         self.bc = bc
         self._src_ext = src_ext
@@ -470,19 +473,21 @@ class ReferenceFMM:
         for o, (oi, si) in self.il_by_off[lev].items():
             X = Mk[si]
             for l in range(1, mu + 2):
-                Xn, U = self._near_factors(X, self.m2l_matrix(lev, o, gap=l))
-                np.add.at(ring[(k + l) % R], oi, Xn @ U.T)
+                np.add.at(ring[(k + l) % R], oi, self._near_prod(X, self.m2l_matrix(lev, o, gap=l)))
             for p in range(1, d + 1):
                 np.add.at(Dp[p], oi, X @ self.m2l_matrix(lev, o, deriv=p).T)
         T = self.c * self.M[lev] * self.dt
         recurrence(k, mu, d, T, ring, R, Lp, aux, Dp)
 
-    def _near_factors(self, X, U):
-        """The factors of a near-future product, rounded by near_round where the block is
-        truncated at some node pairs and not zero at all of them."""
-        if self.near_round is not None and (U == 0).any() and (U > 0).any():
-            return self.near_round(X), self.near_round(U)
-        return X, U
+    def _near_prod(self, X, U):
+        """A near-future product X @ U.T, formed by near_product or from factors rounded by
+        near_round where the block is truncated at some node pairs and not zero at all of them."""
+        if (U == 0).any() and (U > 0).any():
+            if self.near_product is not None:
+                return self.near_product(X, U)
+            if self.near_round is not None:
+                return self.near_round(X) @ self.near_round(U).T
+        return X @ U.T
 
     def _l2l_apply(self, lev_parent, Lpar, k_par):
         """The parent's local of target interval k_par, re-interpolated onto the child level's
@@ -514,8 +519,7 @@ class ReferenceFMM:
             if kk >= k:
                 continue
             for o, (oi, si) in self.il_by_off[lev].items():
-                Xn, U = self._near_factors(Mk[si], self.m2l_matrix(lev, o, gap=k - kk))
-                np.add.at(L, oi, Xn @ U.T)
+                np.add.at(L, oi, self._near_prod(Mk[si], self.m2l_matrix(lev, o, gap=k - kk)))
         if lev > 2:
             kp = k // 2
             L += self._l2l_apply(lev - 1, self.local(lev - 1, kp), kp)[k]

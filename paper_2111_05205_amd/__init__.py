@@ -13,10 +13,10 @@ import numpy as np
 
 from . import _native as N
 from ._native import (BMBIE, DIRICHLET, MIXED, GUESS_EXTRAP, GUESS_MLP, GUESS_MLP_ONLY, GUESS_PREV, GUESS_ZERO, INC_GAUSS_MOD,
-                      INC_RAISED_COS, INTERP_HERMITE, INTERP_LAGRANGE, M2L_BF16, M2L_FP32, M2L_FP64, NEUMANN,
+                      INC_RAISED_COS, INTERP_HERMITE, INTERP_LAGRANGE, M2L_BF16, M2L_BF16X3, M2L_FP32, M2L_FP64, NEUMANN,
                       OBIE)
 
-__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "MIXED", "M2L_FP64", "M2L_FP32", "M2L_BF16",
+__all__ = ["TDBEM", "TDBEMError", "incident", "run_batch", "create_fmm", "BMBIE", "OBIE", "DIRICHLET", "NEUMANN", "MIXED", "M2L_FP64", "M2L_FP32", "M2L_BF16", "M2L_BF16X3",
            "INC_GAUSS_MOD", "INC_RAISED_COS", "GUESS_EXTRAP", "GUESS_ZERO", "GUESS_PREV", "GUESS_MLP", "GUESS_MLP_ONLY",
            "INTERP_LAGRANGE", "INTERP_HERMITE"]
 
@@ -101,7 +101,7 @@ class TDBEM:
     def __init__(self, xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, *, use_fmm=0, depth=4, p_s=4, p_t=4, mu=0,
                  m2l_prec=M2L_FP64, gmres_tol=1e-12, gmres_restart=30, gmres_maxiter=300, nt_max=4096,
                  guess=GUESS_EXTRAP, graph=False, stream=None, device=None, face_bc=None, near_form=0,
-                 near_prec=0, interp=0):
+                 near_prec=0, interp=0, growth_limit=0.0, growth_lag=1):
         """face_bc: None, or per face 1 (q given, u unknown) / 0 (u given, q unknown): a mixed
         boundary condition (tdbem_create_mixed; bc is then ignored)."""
         torch = _torch()
@@ -113,7 +113,7 @@ class TDBEM:
                       tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         o = N.Opts(int(use_fmm), int(depth), int(p_s), int(p_t), int(mu), int(m2l_prec), float(gmres_tol),
                    int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess), int(bool(graph)),
-                   int(near_form), int(near_prec), int(interp))
+                   int(near_form), int(near_prec), int(interp), float(growth_limit), int(growth_lag))
         self.stream = stream  # a torch.cuda.Stream the context works on (kept alive), or None
         if stream is not None:
             stream = stream.cuda_stream
@@ -152,6 +152,10 @@ class TDBEM:
             self.close()
         except Exception:
             pass
+
+    def last_error(self):
+        """Message of the context's last failed call (tdbem_last_error)."""
+        return self._L.tdbem_last_error(self._h).decode()
 
     def _check(self, rc):
         if rc < 0:

@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdbem.so
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 OBIE, BMBIE = 0, 1
 DIRICHLET, NEUMANN, MIXED = 0, 1, 2
-M2L_FP64, M2L_FP32, M2L_BF16 = 0, 1, 2
+M2L_FP64, M2L_FP32, M2L_BF16, M2L_BF16X3 = 0, 1, 2, 3
 INTERP_LAGRANGE, INTERP_HERMITE = 0, 1
 INC_GAUSS_MOD, INC_RAISED_COS = 0, 1
 GUESS_EXTRAP, GUESS_ZERO, GUESS_PREV, GUESS_MLP, GUESS_MLP_ONLY = 0, 1, 2, 3, 4
@@ -25,7 +25,8 @@ class Opts(ctypes.Structure):
                 ("mu", ctypes.c_int), ("m2l_prec", ctypes.c_int), ("gmres_tol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int), ("gmres_maxiter", ctypes.c_int), ("nt_max", ctypes.c_int),
                 ("guess", ctypes.c_int), ("graph", ctypes.c_int), ("near_form", ctypes.c_int),
-                ("near_prec", ctypes.c_int), ("interp", ctypes.c_int)]
+                ("near_prec", ctypes.c_int), ("interp", ctypes.c_int), ("growth_limit", ctypes.c_double),
+                ("growth_lag", ctypes.c_int)]
 
 
 class Incident(ctypes.Structure):

@@ -140,6 +140,20 @@ __global__ void store_step_kernel(int ns, int beta, int bc, const int8_t* __rest
   if (uface) { hu[r] = xv; hq[r] = pv; }
   else { hq[r] = xv; hu[r] = pv; }
   if (!isfinite(xv) || fabs(xv) > 1e100) atomicOr(&st->flags, 2);
+  // max |x| of the step: non-negative doubles order like their bit patterns
+  else atomicMax(reinterpret_cast<unsigned long long*>(&st->xmax), (unsigned long long)__double_as_longlong(fabs(xv)));
+}
+
+// Growth check of row beta (opts.growth_limit): the reference takes in row beta - lag, then the
+// row fails when its largest coefficient exceeds limit times the reference.
+__global__ void growth_check_kernel(int beta, int lag, double limit, StepStat* __restrict__ stats,
+                                    double* __restrict__ ref) {
+  double r = *ref;
+  if (beta >= lag) {
+    r = fmax(r, stats[beta - lag].xmax);
+    *ref = r;
+  }
+  if (r > 0.0 && stats[beta].xmax > limit * r) atomicOr(&stats[beta].flags, 16);
 }
 
 // Rows of the unknown coefficient (u on phi = 1 faces, q on phi = 0 faces) of a
@@ -273,6 +287,10 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   store_step_kernel<<<(ctx->ns + 255) / 256, 256, 0, ctx->stream>>>(
       ctx->ns, beta, ctx->bc, ctx->bc == TDBEM_MIXED ? ctx->d_phi.p : nullptr, ctx->d_x.p, bcv, ctx->d_hu.p,
       ctx->d_hq.p, stat);
+  if (ctx->opts.growth_limit > 0.0) {
+    growth_check_kernel<<<1, 1, 0, ctx->stream>>>(beta, ctx->opts.growth_lag, ctx->opts.growth_limit,
+                                                   stat - beta, ctx->d_growth_ref.p);
+  }
   delete ps;
   TDBEM_HIP(hipGetLastError());
   if (ctx->bc == TDBEM_MIXED) { ctx->hist_u = true; ctx->hist_q = true; }
@@ -411,6 +429,9 @@ static int run_finish(tdbem_ctx* ctx, int nt, int a_first, double* dev_x_hist_ou
     if ((s.flags & 2) && rc == TDBEM_OK) {
       rc = TDBEM_E_DIVERGED;
       ctx->err = "non-finite or exploding solution at step " + std::to_string(a);
+    } else if ((s.flags & 16) && rc == TDBEM_OK) {
+      rc = TDBEM_E_DIVERGED;
+      ctx->err = "solution grew beyond growth_limit at step " + std::to_string(a);
     } else if ((s.flags & 1) && rc == TDBEM_OK) {
       rc = TDBEM_E_NOT_CONVERGED;
       ctx->err = "GMRES did not converge at step " + std::to_string(a);
@@ -446,6 +467,8 @@ static int create_impl(const tdbem_mesh* mesh, double c, double dt, int d, int b
     if (o.guess < TDBEM_GUESS_EXTRAP || o.guess > TDBEM_GUESS_MLP_ONLY) fail(TDBEM_E_INVAL, "guess must be 0..4");
     if (o.near_form != 0 && o.near_form != 1) fail(TDBEM_E_INVAL, "near_form must be 0 (compact) or 1 (tau form)");
     if (o.near_prec != 0 && o.near_prec != 1) fail(TDBEM_E_INVAL, "near_prec must be 0 (FP64) or 1 (FP32)");
+    if (!(o.growth_limit >= 0.0)) fail(TDBEM_E_INVAL, "growth_limit must be >= 0");
+    if (o.growth_limit > 0.0 && o.growth_lag < 1) fail(TDBEM_E_INVAL, "growth_lag must be >= 1");
     ctx->stream = (hipStream_t)hip_stream;
     ctx->c = c;
     ctx->dt = dt;
@@ -501,11 +524,13 @@ static int create_impl(const tdbem_mesh* mesh, double c, double dt, int d, int b
     ctx->d_zero.alloc(ns);
     ctx->d_V.alloc((size_t)(std::min(ctx->opts.gmres_restart, 32) + 1) * ns);
     ctx->d_stat.alloc(ctx->nt_max);
+    ctx->d_growth_ref.alloc(1);
     ctx->gmres_wg = gmres_workgroups(ns);
     ctx->d_gpart.alloc((size_t)2 * std::max(ctx->gmres_wg, 1) * 33);
     TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_zero.p, 0, ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_growth_ref.p, 0, sizeof(double), ctx->stream));
     autotune_gmres(ctx);
     TDBEM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -660,6 +685,7 @@ int tdbem_reset(tdbem_ctx* ctx) {
     TDBEM_HIP(hipMemsetAsync(ctx->d_hq.p, 0, ctx->d_hq.n * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_x.p, 0, ctx->ns * sizeof(double), ctx->stream));
     TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_growth_ref.p, 0, sizeof(double), ctx->stream));
     ctx->alpha = 1;
     ctx->hist_u = ctx->hist_q = false;
     if (ctx->fmm) fmm_reset(ctx);
@@ -718,6 +744,7 @@ int tdbem_step(tdbem_ctx* ctx, const double* dev_forcing, const double* dev_bc_v
       info->resid = hs.resid;
     }
     if (hs.flags & 2) { ctx->err = "non-finite or exploding solution at step " + std::to_string(alpha); rc = TDBEM_E_DIVERGED; }
+    else if (hs.flags & 16) { ctx->err = "solution grew beyond growth_limit at step " + std::to_string(alpha); rc = TDBEM_E_DIVERGED; }
     else if (hs.flags & 1) { ctx->err = "GMRES did not converge at step " + std::to_string(alpha); rc = TDBEM_E_NOT_CONVERGED; }
   });
   return r != TDBEM_OK ? r : rc;
@@ -931,6 +958,7 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
       ctx->mlp_loaded = true;
     }
     TDBEM_HIP(hipMemsetAsync(ctx->d_stat.p, 0, ctx->nt_max * sizeof(StepStat), ctx->stream));
+    TDBEM_HIP(hipMemsetAsync(ctx->d_growth_ref.p, 0, sizeof(double), ctx->stream));
     TDBEM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->alpha = h.alpha;
     ctx->hist_u = h.hist_u != 0;

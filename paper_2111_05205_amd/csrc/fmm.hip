@@ -85,6 +85,11 @@ __device__ inline uint16_t bf16_rne(double x) {
   return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// The second bf16 term of x = hi + lo: the rounded remainder x - hi (split products).
+__device__ inline uint16_t bf16_lo(double x, uint16_t hi) {
+  return bf16_rne(x - (double)__uint_as_float((uint32_t)hi << 16));
+}
+
 struct FmmLevel {
   int ncell = 0;
   std::vector<std::array<int, 3>> key;      // integer cell coordinates
@@ -359,7 +364,7 @@ __global__ void p2m_kernel(int Ps, int pt, int first, double Cd, TimeWeights tw,
                            const int32_t* __restrict__ leaf_elems, const double* __restrict__ A,
                            const double* __restrict__ B, const double* __restrict__ tau,
                            const double* __restrict__ sig, double* __restrict__ mom,
-                           float* __restrict__ mom32, uint16_t* __restrict__ mom16, int Pp) {
+                           float* __restrict__ mom32, uint16_t* __restrict__ mom16, int Pp, int64_t lo16) {
   const int S = blockIdx.x;
   const int P = Ps * pt;
   for (int b = threadIdx.x; b < Ps; b += blockDim.x) {
@@ -374,7 +379,12 @@ __global__ void p2m_kernel(int Ps, int pt, int first, double Cd, TimeWeights tw,
       const double v = (first ? 0.0 : mom[ix]) + acc * tw.w[n];
       mom[ix] = v;
       if (mom32) mom32[ix] = (float)v;  // FP32 products read this copy; the last write of an interval is final
-      if (mom16) mom16[(int64_t)S * Pp + b + Ps * n] = bf16_rne(v);  // likewise the BF16 products
+      if (mom16) {  // likewise the BF16 products (and, lo16 > 0, the second term of the split products)
+        const int64_t j = (int64_t)S * Pp + b + Ps * n;
+        const uint16_t h = bf16_rne(v);
+        mom16[j] = h;
+        if (lo16) mom16[lo16 + j] = bf16_lo(v, h);
+      }
     }
   }
 }
@@ -411,7 +421,7 @@ __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__
                            const int32_t* __restrict__ child, const int32_t* __restrict__ octant,
                            const double* __restrict__ S, const double* __restrict__ T,
                            const double* __restrict__ mom_c, double* __restrict__ mom_p,
-                           float* __restrict__ mom32_p, uint16_t* __restrict__ mom16_p, int Pp) {
+                           float* __restrict__ mom32_p, uint16_t* __restrict__ mom16_p, int Pp, int64_t lo16) {
   extern __shared__ double sm[];
   const int Ps = ps * ps * ps, P = Ps * pt;
   double* b0 = sm;
@@ -441,7 +451,12 @@ __global__ void m2m_kernel(int ps, int pt, int half, const int32_t* __restrict__
       const double v = (half == 0 ? 0.0 : mom_p[(int64_t)p * P + idx]) + acc[q];
       mom_p[(int64_t)p * P + idx] = v;
       if (mom32_p) mom32_p[(int64_t)p * P + idx] = (float)v;
-      if (mom16_p) mom16_p[(int64_t)p * Pp + idx] = bf16_rne(v);
+      if (mom16_p) {
+        const int64_t j = (int64_t)p * Pp + idx;
+        const uint16_t h = bf16_rne(v);
+        mom16_p[j] = h;
+        if (lo16) mom16_p[lo16 + j] = bf16_lo(v, h);
+      }
     }
   }
 }
@@ -557,6 +572,8 @@ struct M2LLevelWork {
   const double* mom;
   const float* mom32;            // FP32 copy of mom (FP32 products only)
   const uint16_t* mom16;         // BF16 copy of mom, row stride Pp (BF16 products only)
+  const void* Uf_lo;             // split BF16 products: second bf16 term of the operators (layout of Uf)
+  const uint16_t* mom16_lo;      // and of the moments (layout of mom16)
   void* stage;                   // T per-pair products
   int ntiles;
   int item0;                     // first work item of this level
@@ -668,7 +685,11 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
     for (int j = 0; j < NCB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
   const int bc = tid / TPC, bk = (tid % TPC) * BPT;
   const int bsrc = src[bc];
-  const double* mrow = mom + (int64_t)(bsrc >= 0 ? bsrc : 0) * P;
+  // B values come from the moments in the products' own precision (FP32 contexts keep
+  // an FP32 copy: half the bytes of the FP64 moments, the same values once rounded)
+  typedef std::conditional_t<sizeof(T) == 4, float, double> MT;
+  const MT* mrow = (sizeof(T) == 4 ? reinterpret_cast<const MT*>(Lw.mom32) : reinterpret_cast<const MT*>(mom)) +
+                   (int64_t)(bsrc >= 0 ? bsrc : 0) * P;
   // DEPTH K steps ahead in registers (DEPTH sets, used in turn): A fragments
   // (QS k-blocks x 2 row blocks) and this thread's BPT raw moment values of the
   // B tile.  The moments are masked and converted only when they are written
@@ -680,7 +701,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
   constexpr int DEPTH = (sizeof(T) == 4 && RPW == 2) ? 2 : 1;
   constexpr int NSET = DEPTH + 1;
   T fa[NSET][RPW][QS];
-  double fb[NSET][BPT];
+  MT fb[NSET][BPT];
   auto load = [&](int set, int k0) {
     const int g0 = (k0 >> 2) / V;
 #pragma unroll
@@ -976,7 +997,7 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
 // loop; fragments of the next K step are loaded while the current one multiplies.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-template <int NCB, int RPW, bool PERS>
+template <int NCB, int RPW, bool PERS, bool X3>
 __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB, int KB32, M2LWork W) {
   typedef float f4_t __attribute__((ext_vector_type(4)));
   constexpr int BN = NCB * 16;
@@ -1003,34 +1024,66 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
   if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
   const uint4* brow[NCB];
   bool blive[NCB];
+  int64_t boff[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) {
     const int col = cb * 16 + (lane & 15);
     blive[cb] = col < cnt;
-    brow[cb] = reinterpret_cast<const uint4*>(Lw.mom16 + (int64_t)src_by_slot[first + min(col, cnt - 1)] * Pp + k8);
+    boff[cb] = (int64_t)src_by_slot[first + min(col, cnt - 1)] * Pp + k8;
+    brow[cb] = reinterpret_cast<const uint4*>(Lw.mom16 + boff[cb]);
   }
   const uint4* Ar[RPW];
+  int64_t aoff[RPW];
 #pragma unroll
-  for (int r = 0; r < RPW; ++r)
-    Ar[r] = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Lw.Uf) + ig.uoff) +
-            (int64_t)min(rb0 + r, RBs - 1) * KB32 * 64 + lane;
+  for (int r = 0; r < RPW; ++r) {
+    aoff[r] = (int64_t)min(rb0 + r, RBs - 1) * KB32 * 64 + lane;
+    Ar[r] = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Lw.Uf) + ig.uoff) + aoff[r];
+  }
+  // X3: x = hi + lo in bf16 for both factors, products hi*hi + hi*lo + lo*hi (lo*lo dropped)
+  const uint4* Arl[X3 ? RPW : 1];
+  const uint4* browl[X3 ? NCB : 1];
+  if constexpr (X3) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+      Arl[r] = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Lw.Uf_lo) + ig.uoff) + aoff[r];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) browl[cb] = reinterpret_cast<const uint4*>(Lw.mom16_lo + boff[cb]);
+  }
   f4_t acc[RPW][NCB];
 #pragma unroll
   for (int i = 0; i < RPW; ++i)
 #pragma unroll
     for (int j = 0; j < NCB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
   uint4 fa[2][RPW], fb[2][NCB];
+  uint4 fal[2][X3 ? RPW : 1], fbl[2][X3 ? NCB : 1];
   auto load = [&](int set, int s) {
 #pragma unroll
     for (int r = 0; r < RPW; ++r) fa[set][r] = Ar[r][(int64_t)s * 64];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) fb[set][cb] = brow[cb][4 * s];
+    if constexpr (X3) {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) fal[set][r] = Arl[r][(int64_t)s * 64];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) fbl[set][cb] = browl[cb][4 * s];
+    }
   };
   auto products = [&](int set) {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       const uint4 bz = blive[cb] ? fb[set][cb] : uint4{0u, 0u, 0u, 0u};
       const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, bz);
+      if constexpr (X3) {
+        const uint4 bzl = blive[cb] ? fbl[set][cb] : uint4{0u, 0u, 0u, 0u};
+        const bf16x8_t bvl = __builtin_bit_cast(bf16x8_t, bzl);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {  // the two small terms first
+          acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fal[set][r]), bv,
+                                                               acc[r][cb], 0, 0, 0);
+          acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fa[set][r]), bvl,
+                                                               acc[r][cb], 0, 0, 0);
+        }
+      }
 #pragma unroll
       for (int r = 0; r < RPW; ++r)
         acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fa[set][r]), bv,
@@ -1068,8 +1121,10 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
 }
 
 // Operators in the BF16 fragment order above (rows GP of each slot's GPsrc-row stack from row0).
+// Uf_lo: NULL, or where the second bf16 term of each value goes (split products).
 __global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int RB, int KB32,
-                                         const double* __restrict__ U, uint16_t* __restrict__ Uf) {
+                                         const double* __restrict__ U, uint16_t* __restrict__ Uf,
+                                         uint16_t* __restrict__ Uf_lo) {
   const int slot = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)RB * KB32 * 512;
@@ -1079,7 +1134,9 @@ __global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int
   const int kb = (int)(blk % KB32), rb = (int)(blk / KB32);
   const int row = rb * 16 + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + e;
   const double v = (row < GP && col < P) ? U[((int64_t)slot * GPsrc + row0 + row) * P + col] : 0.0;
-  Uf[(int64_t)slot * per + idx] = bf16_rne(v);
+  const uint16_t h = bf16_rne(v);
+  Uf[(int64_t)slot * per + idx] = h;
+  if (Uf_lo) Uf_lo[(int64_t)slot * per + idx] = bf16_lo(v, h);
 }
 
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
@@ -1109,13 +1166,13 @@ static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int 
 }
 
 // BF16 contexts use the tile shapes of variants 8 .. 11 (columns x rows per workgroup).
-template <bool PERS>
+template <bool PERS, bool X3>
 static void launch_m2l_bf16_tile(int v, int grid, hipStream_t st, int Pp, int GP, int RB, int KB32, const M2LWork& W) {
   switch (v) {
-    case 8: m2l_bf16_kernel<2, 2, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    case 9: m2l_bf16_kernel<2, 4, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    case 10: m2l_bf16_kernel<4, 2, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    default: m2l_bf16_kernel<4, 4, PERS><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 8: m2l_bf16_kernel<2, 2, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 9: m2l_bf16_kernel<2, 4, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 10: m2l_bf16_kernel<4, 2, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    default: m2l_bf16_kernel<4, 4, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
   }
 }
 
@@ -1541,7 +1598,7 @@ static int cols_index(int cols) { return cols == 128 ? 0 : cols == 64 ? 1 : 2; }
 
 static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   const int P = f->P, G = f->Gn;
-  const bool lo = f->prec == 1, b16 = f->prec == 2;
+  const bool lo = f->prec == 1, b16 = f->prec >= 2, x3 = f->prec == 3;
   const int v = choice >> 1, persistent = choice & 1;
   const int rows = 64 * kVariantRpw[v];
   const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
@@ -1559,6 +1616,10 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     Lw.mom = L.d_mom.p;
     Lw.mom32 = L.d_mom32.p;
     Lw.mom16 = L.d_mom16.p;
+    if (x3) {  // second terms after the first (same layouts)
+      Lw.Uf_lo = L.d_U16.p + L.d_U16.n / 2;
+      Lw.mom16_lo = L.d_mom16.p + L.d_mom16.n / 2;
+    }
     if (lo) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
     else if (b16) { Lw.Uf = L.d_U16.p; Lw.stage = L.d_stage32.p; }
     else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
@@ -1575,8 +1636,13 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   const int grid = pers ? f->persistent_grid : total;
   if (b16) {
     const int KB32 = (P + 31) / 32;
-    if (pers) launch_m2l_bf16_tile<true>(v, grid, st, f->Pp, G * P, RB, KB32, W);
-    else launch_m2l_bf16_tile<false>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+    if (x3) {
+      if (pers) launch_m2l_bf16_tile<true, true>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+      else launch_m2l_bf16_tile<false, true>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+    } else {
+      if (pers) launch_m2l_bf16_tile<true, false>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+      else launch_m2l_bf16_tile<false, false>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+    }
   } else if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
   else launch_m2l_variant<double>(v, pers, grid, st, P, G * P, RB, KB, W);
   TDBEM_HIP(hipGetLastError());
@@ -1655,11 +1721,11 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
       TDBEM_HIP(hipEventCreate(&e1));
     }
     float best = 1e30f;
-    int bestc = f->prec == 2 ? 2 * M2L_FIRST_DIRECT : 2;  // 64 x 16 x 128 (BF16: 32 x 128), one item per workgroup
+    int bestc = f->prec >= 2 ? 2 * M2L_FIRST_DIRECT : 2;  // 64 x 16 x 128 (BF16: 32 x 128), one item per workgroup
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
       if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
-      if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec != 2) continue;
-      if ((c >> 1) < M2L_FIRST_DIRECT && f->prec == 2) continue;  // BF16: the four LDS-free shapes
+      if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec < 2) continue;
+      if ((c >> 1) < M2L_FIRST_DIRECT && f->prec >= 2) continue;  // BF16: the four LDS-free shapes
       launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
       for (int r = 0; r < 2; ++r) launch_m2l_levels(f, n, c, st);
@@ -1766,7 +1832,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     throw Error(TDBEM_E_INVAL, "interp must be LAGRANGE (0) or HERMITE (1)");
   if (o.interp == TDBEM_INTERP_HERMITE && (o.p_s < 3 || o.p_t < 3))
     throw Error(TDBEM_E_INVAL, "the cubic Hermite interpolation needs p_s, p_t >= 3");
-  if (o.m2l_prec != TDBEM_M2L_FP64 && o.m2l_prec != TDBEM_M2L_FP32 && o.m2l_prec != TDBEM_M2L_BF16)
+  if (o.m2l_prec != TDBEM_M2L_FP64 && o.m2l_prec != TDBEM_M2L_FP32 && o.m2l_prec != TDBEM_M2L_BF16 &&
+      o.m2l_prec != TDBEM_M2L_BF16X3)
     throw Error(TDBEM_E_INVAL, "m2l_prec must be FP64 (0), FP32 (1) or BF16 (2)");
   Fmm* f = new Fmm();
   try {
@@ -1921,8 +1988,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         L.d_mom32.alloc((size_t)L.ncell * P);
         TDBEM_HIP(hipMemsetAsync(L.d_mom32.p, 0, L.d_mom32.n * sizeof(float), st));
       }
-      if (f->prec == 2) {  // the padding columns P .. Pp-1 stay zero
-        L.d_mom16.alloc((size_t)L.ncell * f->Pp);
+      if (f->prec >= 2) {  // the padding columns P .. Pp-1 stay zero; split products: two terms
+        L.d_mom16.alloc((size_t)(f->prec == 3 ? 2 : 1) * L.ncell * f->Pp);
         TDBEM_HIP(hipMemsetAsync(L.d_mom16.p, 0, L.d_mom16.n * sizeof(uint16_t), st));
       }
       L.d_ring.alloc((size_t)f->R * L.ncell * P);
@@ -1938,10 +2005,10 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         std::vector<int64_t> uoff(std::max(nslot, 1) + 1, 0);
         for (int sl = 0; sl < nslot; ++sl) {
           const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16;
-          uoff[sl + 1] = uoff[sl] + (f->prec == 2 ? (int64_t)RBs * KB32 * 512 : (int64_t)RBs * KB * 64);
+          uoff[sl + 1] = uoff[sl] + (f->prec >= 2 ? (int64_t)RBs * KB32 * 512 : (int64_t)RBs * KB * 64);
         }
         const size_t tot = (size_t)std::max<int64_t>(uoff[nslot > 0 ? nslot : 0], 1);
-        if (f->prec == 2) L.d_U16.alloc(tot);
+        if (f->prec >= 2) L.d_U16.alloc((f->prec == 3 ? 2 : 1) * tot);  // split products: second terms after tot
         else if (f->prec == 1) L.d_U32.alloc(tot);
         else L.d_Uf.alloc(tot);
         for (int sl = 0; sl < nslot; ++sl) {
@@ -1955,8 +2022,9 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
           const double* Us = L.d_U.p;
           const int64_t n = uoff[sl + 1] - uoff[sl];
           const unsigned nb = (unsigned)((n + 255) / 256);
-          if (f->prec == 2)
-            to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB32, Us, L.d_U16.p + uoff[sl]);
+          if (f->prec >= 2)
+            to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB32, Us, L.d_U16.p + uoff[sl],
+                                                         f->prec == 3 ? L.d_U16.p + tot + uoff[sl] : nullptr);
           else if (f->prec == 1)
             to_fragments_kernel<float><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, Us, L.d_U32.p + uoff[sl]);
           else
@@ -2063,7 +2131,8 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
     const int first = (beta + 1) % Ml == 0;
     p2m_kernel<<<L.ncell, ((f->Ps + 63) / 64) * 64, 0, st>>>(f->Ps, f->pt, first, f->Cd, tw, f->d_leaf_ptr.p,
                                                               f->d_leaf_elems.p, f->d_A.p, f->d_B.p, f->d_tau.p,
-                                                              f->d_sig.p, L.d_mom.p, L.d_mom32.p, L.d_mom16.p, f->Pp);
+                                                              f->d_sig.p, L.d_mom.p, L.d_mom32.p, L.d_mom16.p, f->Pp,
+                                                              f->prec == 3 ? (int64_t)L.ncell * f->Pp : 0);
     TDBEM_HIP(hipGetLastError());
   }
   delete p2m_scope;
@@ -2091,7 +2160,7 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
       ProfScope ps(ctx, K_M2M);
       m2m_kernel<<<Pl.ncell, sep_threads(P), shm, st>>>(f->ps, f->pt, k & 1, Pl.d_child_ptr.p, Pl.d_child.p,
                                                          L.d_octant.p, S, T, L.d_mom.p, Pl.d_mom.p, Pl.d_mom32.p,
-                                                         Pl.d_mom16.p, f->Pp);
+                                                         Pl.d_mom16.p, f->Pp, f->prec == 3 ? (int64_t)Pl.ncell * f->Pp : 0);
       TDBEM_HIP(hipGetLastError());
     }
     {
@@ -2173,8 +2242,8 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
 int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
   Fmm* f = ctx->fmm;
   if (!f || n < 1 || n > f->D - 1 || n >= 16 || choice < 0 || choice >= 2 * M2L_VARIANTS) return TDBEM_E_INVAL;
-  if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec != 2) return TDBEM_E_INVAL;
-  if ((choice >> 1) < M2L_FIRST_DIRECT && f->prec == 2) return TDBEM_E_INVAL;
+  if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec < 2) return TDBEM_E_INVAL;
+  if ((choice >> 1) < M2L_FIRST_DIRECT && f->prec >= 2) return TDBEM_E_INVAL;
   f->m2l_choice[n] = choice;
   return TDBEM_OK;
 }

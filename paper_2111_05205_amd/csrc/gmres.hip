@@ -304,6 +304,7 @@ __global__ __launch_bounds__(GM_THREADS) void gmres_kernel(int ns, int W, const 
     stat->iters = it;
     stat->resid = rel;
     stat->flags = flags;
+    stat->xmax = 0.0;
   }
 }
 
@@ -613,6 +614,7 @@ __global__ __launch_bounds__(GC_THREADS) void gmres_coop_kernel(
     stat->iters = it;
     stat->resid = rel;
     stat->flags = flags;
+    stat->xmax = 0.0;
   }
 }
 

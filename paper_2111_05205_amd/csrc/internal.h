@@ -53,8 +53,9 @@ struct DevBuf {
 // Per-step record kept on the device during a march.
 struct StepStat {
   int iters;
-  int flags;  // bit0: not converged, bit1: non-finite
+  int flags;    // bit0: not converged, bit1: non-finite, bit2/3: starting point rejected/replaced, bit4: growth
   double resid;
+  double xmax;  // max_i |x_i| of the step (reset by the solve, raised by the store)
 };
 
 struct Fmm;  // space-time FMM state (fmm.hip)
@@ -122,6 +123,7 @@ struct tdbem_ctx {
   tdbem::DevBuf<double> d_b, d_x, d_V, d_forc, d_zero, d_gpart;
   int gmres_wg = 1;  // workgroups of the per-step solve (1: single-workgroup kernel)
   tdbem::DevBuf<tdbem::StepStat> d_stat;
+  tdbem::DevBuf<double> d_growth_ref;  // largest max|x| of the rows up to beta - growth_lag (growth check)
 
   tdbem::Fmm* fmm = nullptr;
 

@@ -118,3 +118,32 @@ def test_binding_signatures_match_the_header():
         assert at is not None, name
         assert len(at) == len(ps), name
         assert ["*" in p for p in ps] == [is_ptr(t) for t in at], name
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Size and field offsets of every struct the binding mirrors, as the C compiler lays
+    them out from include/tdbem.h (a field added on one side only shifts the rest)."""
+    import shutil
+    import subprocess
+    import pytest
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from paper_2111_05205_amd import _native as N
+    pairs = [("tdbem_mesh", N.Mesh), ("tdbem_opts", N.Opts), ("tdbem_incident", N.Incident),
+             ("tdbem_step_info", N.StepInfo), ("tdbem_run_info", N.RunInfo), ("tdbem_info", N.Info)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tdbem.h"', "int main(void) {"]
+    want = []
+    for cname, cls in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {fname}));')
+            want.append(getattr(cls, fname).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == want

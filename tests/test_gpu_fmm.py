@@ -155,6 +155,46 @@ def test_fmm_bf16_m2l_products(pp):
     g.close()
 
 
+@pytest.mark.parametrize("pp", [3, 4])
+def test_fmm_bf16x3_m2l_products(pp):
+    """Split BF16 products: both factors of a dense near-future product as x = hi + lo in bf16,
+    products hi*hi + hi*lo + lo*hi with FP32 accumulation, every BF16 tile shape, one item per
+    workgroup and persistent.  Against the oracle forming the same three products (in FP64), and
+    against the exact FP64 oracle FMM, which it must approach to FP32-like accuracy."""
+    from oracle import mlp as OM
+
+    def prod3(X, U):
+        Xh, Uh = OM.bf16(X), OM.bf16(U)
+        Xl, Ul = OM.bf16(X - Xh), OM.bf16(U - Uh)
+        return Xh @ Uh.T + Xh @ Ul.T + Xl @ Uh.T
+    P = _P()
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    R = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, pp, pp)
+    ns = tri.shape[0]
+    u = synth.random_history(ns, 24, seed=5)
+    q = synth.random_history(ns, 24, seed=6)
+    want = R.history_rhs(21, u, q)
+    Rb = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, pp, pp, near_product=prod3)
+    want_b = Rb.history_rhs(21, u, q)
+    dev = torch.device("cuda")
+    g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=pp, p_t=pp, m2l_prec=P.M2L_BF16X3, nt_max=32)
+    errs, errs_b = {}, {}
+    for choice in range(16, 24):
+        g.set_m2l_variant(1, choice)
+        g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
+        got = g.fmm_eval(21).cpu().numpy()
+        errs[choice] = _rel(got, want)
+        errs_b[choice] = _rel(got, want_b)
+    eff = _rel(want_b, want)
+    print("BF16X3 history sum vs FP64 oracle FMM:", errs, "vs the split-product oracle:", errs_b,
+          "split effect in the oracle:", eff)
+    assert eff < 1e-4
+    assert all(e < 0.2 * eff for e in errs_b.values()), errs_b
+    assert all(e < 1e-4 for e in errs.values()), errs
+    g.close()
+
+
 @pytest.mark.parametrize("depth,pp", [(3, 3), (3, 4)])
 def test_dense_block_count_matches_the_oracle_operators(depth, pp):
     """The library evaluates a near-future block (eq. Uabmn) as a dense product only where the
