@@ -95,11 +95,12 @@ def cpu_baseline(w, rows_sample=5120, chunk=256, seed=0, window=None):
 
 def measured_traffic(prec, workload="sphere5k"):
     """HBM bytes per M2L launch from the committed rocprofv3 counter summary of this
-    workload, if it was taken on the current M2L source (else None)."""
+    workload and product precision, if it was taken on the current M2L source (else None)."""
     import hashlib
-    if prec != 1:
+    name = {1: "fp32", 3: "bf16x3"}.get(prec)
+    if name is None:
         return None
-    path = os.path.join(ROOT, "profiles", f"m2l_fp32_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"m2l_{name}_{workload}_traffic.json")
     try:
         rec = json.load(open(path))
         src = m2l_kernel_source()
@@ -369,17 +370,35 @@ def batch_bench(args):
     solvers = []
     t0 = time.perf_counter()
     n_direct = 0
+
+    def make(w, mu):
+        kw = dict(nt_max=w["nt"], gmres_tol=args.gmres_tol, graph=args.batch_mode == "graphs",
+                  stream=torch.cuda.Stream())
+        if args.batch_leaf_ratio > 0:
+            return P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=1, p_s=3, p_t=3,
+                           m2l_prec=P.M2L_FP32, leaf_ratio=args.batch_leaf_ratio, mu=mu, **kw)
+        return P.create_fmm(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], p_s=3, p_t=3,
+                            m2l_prec=P.M2L_FP32, **kw)
     for w in insts:
-        kw = dict(nt_max=w["nt"], gmres_tol=args.gmres_tol, graph=True, stream=torch.cuda.Stream())
         try:
-            s = P.create_fmm(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], p_s=3, p_t=3,
-                             m2l_prec=P.M2L_FP32, **kw)
+            s = make(w, 0)
         except P.TDBEMError:
             # the surface spans only a few c*dt: no octree level is wide enough, all pairs are near
-            s = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0, **kw)
+            s = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0,
+                        nt_max=w["nt"], gmres_tol=args.gmres_tol, graph=args.batch_mode == "graphs",
+                        stream=torch.cuda.Stream())
             n_direct += 1
         solvers.append(s)
+    if args.batch_leaf_ratio > 0:
+        # one mu for every FMM instance, so that equal normalised levels share their operators
+        mus = [s.info()["mu"] for s in solvers if s.info()["use_fmm"]]
+        mu = max(mus) if mus else 0
+        for i, (w, s) in enumerate(zip(insts, solvers)):
+            if s.info()["use_fmm"] and s.info()["mu"] != mu:
+                s.close()
+                solvers[i] = make(w, mu)
     setup_s = time.perf_counter() - t0
+    fmm_infos = [s.info() for s in solvers if s.info()["use_fmm"]]
     nts = [w["nt"] for w in insts]
     incs = [w["inc"] for w in insts]
     work = sum(s.ns * nt for s, nt in zip(solvers, nts))
@@ -412,15 +431,40 @@ def batch_bench(args):
         Pn = info["p_s"] ** 3 * info["p_t"]
         flops += 2 * Pn * Pn * m2l_dense_blocks(info, range(0, nt - 1), info["m_leaf"], info["depth"])
     achieved = flops / (wall * 1e-3) / 1e12
+    acc = None
+    if not args.no_accuracy:
+        # FMM march against the direct march, every eighth instance (outside the timed region)
+        errs = []
+        for k in range(0, len(insts), 8):
+            w, s = insts[k], solvers[k]
+            if not s.info()["use_fmm"]:
+                continue
+            s.reset()
+            x, _ = s.run(w["nt"], inc=w["inc"])
+            dref = P.TDBEM(w["xyz"], w["tri"], w["c"], w["dt"], w["d"], w["bie"], w["bc"], use_fmm=0,
+                           nt_max=w["nt"], gmres_tol=1e-12)
+            xd, _ = dref.run(w["nt"], inc=w["inc"])
+            errs.append(float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd)))
+            dref.close()
+        acc = {"instances": len(errs), "rel_l2_fmm_vs_direct_median": float(np.median(errs)) if errs else None,
+               "rel_l2_fmm_vs_direct_max": max(errs) if errs else None,
+               "sample": "every eighth instance, whole march against the direct (no-FMM) march"}
     out = {"metric": METRIC, "value": round(work / (wall * 1e-3), 1), "unit": "Ns*Nt/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64 (M2L products f32)", "data": "synthetic",
            "config": {"workload": "batch64: 64 independent scatterers (ellipsoids / rounded cubes, Ns 500-8000, "
                                   "Nt 128-512, d 1 or 2, Burton-Miller Neumann), FMM with 3 Chebyshev nodes per "
-                                  "axis, deepest octree the step allows, each march a captured graph on its own "
-                                  "stream",
+                                  "axis, " + ("leaf side %.2f c dt (normalised operators shared between instances)"
+                                             % args.batch_leaf_ratio if args.batch_leaf_ratio > 0 else
+                                             "deepest octree the step allows") + ", " +
+                                  ("each march a captured graph on its own stream" if args.batch_mode == "graphs"
+                                   else "all marches in lock step, one M2L launch per step for all instances"),
                       "instances": len(solvers), "direct_instances": n_direct, "sum_ns_nt": work,
-                      "setup_s": round(setup_s, 1),
+                      "setup_s": round(setup_s, 1), "leaf_ratio": args.batch_leaf_ratio,
+                      "mode": args.batch_mode,
+                      "shared_operator_levels": sum(1 for i in fmm_infos for l in range(2, i["depth"] + 1)
+                                                    if i["m2l_ops_users"][l] > 1),
+                      "operator_levels": sum(i["depth"] - 1 for i in fmm_infos),
                       "gmres_tol": args.gmres_tol, "gmres_iters_per_batch": iters // args.steps,
                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
            "roofline": {"kernel": "m2l_gemm (all instances)", "bound": "mfma", "achieved": round(achieved, 3),
@@ -428,6 +472,8 @@ def batch_bench(args):
                         "traffic": None, "note": "algorithmic M2L flops of the whole batch over its wall time"},
            "sequential": {"value": round(work / seq, 1), "ms_per_step": round(seq * 1e3, 3)},
            "batch_speedup_vs_sequential": round(seq * 1e3 / wall, 3)}
+    if acc:
+        out["accuracy"] = acc
     print(json.dumps(out), flush=True)
 
 
@@ -443,6 +489,12 @@ def main():
                          "FP64 M2L + extrapolated "
                          "starting point; both: time both, value = mixed")
     ap.add_argument("--gmres-tol", type=float, default=1e-8)
+    ap.add_argument("--batch-leaf-ratio", type=float, default=2.5,
+                    help="batch64: leaf side in units of c dt, so that instances share normalised M2L operators "
+                         "(0: per-instance operators, deepest octree the step allows)")
+    ap.add_argument("--batch-mode", default="graphs", choices=["graphs", "lockstep"],
+                    help="batch64: every march a captured graph on its own stream, or all marches in lock step "
+                         "with one M2L launch per step for every instance")
     ap.add_argument("--mixed-m2l", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="near-future product precision of the mixed form on the large instance: FP32, or split "
                          "BF16 (x = hi + lo, three bf16 products)")

@@ -115,6 +115,14 @@ typedef struct {
                           max_i |x_i^gamma| over gamma <= beta - growth_lag; 0: off (only non-finite or
                           |x| > 1e100 fail) */
   int growth_lag;    /* steps between the checked row and the newest reference row (>= 1 when growth_limit > 0) */
+  double leaf_ratio; /* > 0 (FMM): normalised operators.  The octree's leaf side is leaf_ratio * c * dt (the
+                        depth follows from the mesh extent and opts.depth is ignored) and the dense near-future
+                        M2L operators are formed in units of c*dt and dt.  U of eq. Uabmn is homogeneous of
+                        degree d-1 in (x, c t), so in these units a level's operators depend only on its
+                        distance from the leaves: contexts on one device with equal leaf_ratio, M_leaf, mu, d,
+                        p_s, p_t, interp and m2l_prec share them (process-wide, held while any such context
+                        lives), and each context scales its products by (c dt)^(d-1).  0: per-context
+                        operators in physical units (default) */
 } tdbem_opts;
 
 /* Interpolation functions l_a of eq. U_intp.  LAGRANGE: polynomials on the p Chebyshev
@@ -170,6 +178,8 @@ typedef struct {
   int64_t m2l_dense_blocks[16]; /* per level: sum over interaction pairs of the near-future gaps evaluated as dense
                                    P x P products (the wavefront crosses the pair's node set there; the other gaps
                                    are zero at every node pair, or wavefront-free and evaluated in separable form) */
+  int m2l_ops_users[16];        /* per level: live contexts that use this level's dense operator set (1: its own;
+                                   more: shared normalised operators, opts.leaf_ratio) */
 } tdbem_info;
 
 /* Build a context: copies and validates the mesh (closed, consistently

@@ -163,14 +163,19 @@ class ReferenceFMM:
     """History part of the MOT right-hand side with near pairs direct and far pairs by the FMM."""
 
     def __init__(self, xyz, tri, c, dt, d, bie, depth, p_s, p_t, mu=0, m2l="alg1", bc=None, src_ext=None,
-                 near_round=None, interp="lagrange", near_product=None):
+                 near_round=None, interp="lagrange", near_product=None, leaf_ratio=None):
         """near_round: None, or a function applied to both factors (moments and operator) of
         the near-future products (eq. m2l_near) whose operator block is truncated at some node
         pairs and not zero at all of them (where the wavefront crosses the pair's node set),
         e.g. rounding to a lower precision; every other block is a polynomial at the nodes
         or zero, and those products and the derivative products stay exact.
         near_product: None, or a function (X, U) -> X @ U.T as a lower-precision path forms
-        the products of those same blocks (e.g. from split factors)."""
+        the products of those same blocks (e.g. from split factors).
+        leaf_ratio: None, or the leaf side in units of c dt: the root cube (centred as usual) gets
+        half side leaf_ratio c dt 2^D / 2 with the smallest D >= 2 that holds the mesh, and depth
+        is ignored (the sizing under which the operators of a level, in units of c dt and dt,
+        depend only on its distance from the leaves)."""
+        self.leaf_ratio = leaf_ratio
         self.near_round = near_round
         self.near_product = near_product
         self.geom = g = Geometry(xyz, tri)
@@ -205,7 +210,15 @@ class ReferenceFMM:
         lo, hi = xyz.min(0), xyz.max(0)
         self.center = (lo + hi) / 2.0
         ext = float(((hi - lo) / 2.0).max())
-        self.H = 2.0 ** np.ceil(np.log2(ext))
+        if self.leaf_ratio:
+            hl = 0.5 * self.leaf_ratio * self.c * self.dt
+            D = 2
+            while D < 12 and hl * 2 ** D < ext:
+                D += 1
+            self.D = D
+            self.H = hl * 2 ** D
+        else:
+            self.H = 2.0 ** np.ceil(np.log2(ext))
         n = 2 ** D
         idx = np.floor((g.x - (self.center - self.H)) / (2.0 * self.H) * n).astype(np.int64)
         self.leaf_idx = np.clip(idx, 0, n - 1)

@@ -101,7 +101,7 @@ class TDBEM:
     def __init__(self, xyz, tri, c, dt, d, bie=BMBIE, bc=NEUMANN, *, use_fmm=0, depth=4, p_s=4, p_t=4, mu=0,
                  m2l_prec=M2L_FP64, gmres_tol=1e-12, gmres_restart=30, gmres_maxiter=300, nt_max=4096,
                  guess=GUESS_EXTRAP, graph=False, stream=None, device=None, face_bc=None, near_form=0,
-                 near_prec=0, interp=0, growth_limit=0.0, growth_lag=1):
+                 near_prec=0, interp=0, growth_limit=0.0, growth_lag=1, leaf_ratio=0.0):
         """face_bc: None, or per face 1 (q given, u unknown) / 0 (u given, q unknown): a mixed
         boundary condition (tdbem_create_mixed; bc is then ignored)."""
         torch = _torch()
@@ -113,7 +113,8 @@ class TDBEM:
                       tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         o = N.Opts(int(use_fmm), int(depth), int(p_s), int(p_t), int(mu), int(m2l_prec), float(gmres_tol),
                    int(gmres_restart), int(gmres_maxiter), int(nt_max), int(guess), int(bool(graph)),
-                   int(near_form), int(near_prec), int(interp), float(growth_limit), int(growth_lag))
+                   int(near_form), int(near_prec), int(interp), float(growth_limit), int(growth_lag),
+                   float(leaf_ratio))
         self.stream = stream  # a torch.cuda.Stream the context works on (kept alive), or None
         if stream is not None:
             stream = stream.cuda_stream
@@ -173,6 +174,7 @@ class TDBEM:
         out["il_pairs"] = list(i.il_pairs)
         out["m2l_variant"] = list(i.m2l_variant)
         out["m2l_dense_blocks"] = list(i.m2l_dense_blocks)
+        out["m2l_ops_users"] = list(i.m2l_ops_users)
         return out
 
     def reset(self):

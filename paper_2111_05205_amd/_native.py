@@ -26,7 +26,7 @@ class Opts(ctypes.Structure):
                 ("gmres_restart", ctypes.c_int), ("gmres_maxiter", ctypes.c_int), ("nt_max", ctypes.c_int),
                 ("guess", ctypes.c_int), ("graph", ctypes.c_int), ("near_form", ctypes.c_int),
                 ("near_prec", ctypes.c_int), ("interp", ctypes.c_int), ("growth_limit", ctypes.c_double),
-                ("growth_lag", ctypes.c_int)]
+                ("growth_lag", ctypes.c_int), ("leaf_ratio", ctypes.c_double)]
 
 
 class Incident(ctypes.Structure):
@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
                 ("near_pairs", ctypes.c_int64), ("near_coefs", ctypes.c_int64), ("a_nnz", ctypes.c_int64),
                 ("il_pairs", ctypes.c_int64 * 16), ("m2l_matrix_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
                 ("m2l_variant", ctypes.c_int * 16), ("gmres_workgroups", ctypes.c_int),
-                ("m2l_dense_blocks", ctypes.c_int64 * 16)]
+                ("m2l_dense_blocks", ctypes.c_int64 * 16), ("m2l_ops_users", ctypes.c_int * 16)]
 
 
 PROF_KINDS = ["near_history", "gmres", "l2p", "p2m", "m2l_gemm", "m2l_reduce", "m2m", "l2l", "other", "mlp",

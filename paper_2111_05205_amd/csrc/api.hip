@@ -249,7 +249,9 @@ static tdbem_opts default_opts() {
   return o;
 }
 
-static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, StepStat* stat) {
+// One collocation step.  defer: stop the FMM after P2M and M2M and return the number of
+// levels whose M2L is still to be launched (fmm_batch_m2l), then fmm_advance_post.
+static int do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, StepStat* stat, bool defer = false) {
   const int alpha = ctx->alpha, beta = alpha - 1;
   if (alpha > ctx->nt_max - 1) fail(TDBEM_E_STATE, "step beyond nt_max");
   launch_near_history(ctx, alpha, forcing, ctx->d_b.p);
@@ -297,8 +299,13 @@ static void do_step(tdbem_ctx* ctx, const double* forcing, const double* bcv, St
   else if (ctx->bc == TDBEM_NEUMANN) { ctx->hist_u = true; if (bcv) ctx->hist_q = true; }
   else { ctx->hist_q = true; if (bcv) ctx->hist_u = true; }
   if (feat && ctx->rec_target) launch_mlp_target(ctx, beta, ctx->rec_target + (size_t)beta * ctx->ns);
-  if (ctx->fmm) fmm_advance(ctx, beta);
+  int ndue = 0;
+  if (ctx->fmm) {
+    if (defer) ndue = fmm_advance_pre(ctx, beta);
+    else fmm_advance(ctx, beta);
+  }
   ctx->alpha = alpha + 1;
+  return ndue;
 }
 
 // ---------------------------------------------------------------------------
@@ -797,17 +804,83 @@ int tdbem_run_batch(tdbem_ctx* const* ctxs, int n, const int* nt, const tdbem_in
         TDBEM_HIP(hipEventRecord(e0[i], ctxs[i]->stream));
         if (graphed[i]) run_launch(ctxs[i], nt[i], forc[i]);
       }));
-    // contexts without a graph: one step of each in turn
+    // contexts without a graph: one step of each in turn; FMM contexts that agree on the
+    // launch shape share one M2L launch per step (on a stream of the batch, joined to and
+    // from the contexts' streams by events)
     int amax = 0;
     for (int i = 0; i < n; ++i) amax = std::max(amax, nt[i] - 1);
-    for (int alpha = 1; alpha <= amax && first_rc == TDBEM_OK; ++alpha)
+    std::vector<tdbem_ctx*> lock;
+    std::vector<int> lock_idx;
+    for (int i = 0; i < n; ++i)
+      if (!graphed[i] && ctxs[i]->fmm) { lock.push_back(ctxs[i]); lock_idx.push_back(i); }
+    FmmBatch* fb = nullptr;
+    if (lock.size() >= 2) {
+      try {
+        fb = fmm_batch_create(lock.data(), (int)lock.size());
+      } catch (const Error&) {
+        fb = nullptr;  // different launch shapes: each context launches its own products
+      }
+    }
+    hipStream_t bst = nullptr;
+    std::vector<hipEvent_t> ev_pre;
+    hipEvent_t ev_m2l = nullptr;
+    if (fb) {
+      note(guarded(lock[0], [&] {
+        TDBEM_HIP(hipStreamCreateWithFlags(&bst, hipStreamNonBlocking));
+        TDBEM_HIP(hipEventCreateWithFlags(&ev_m2l, hipEventDisableTiming));
+        ev_pre.assign(lock.size(), nullptr);
+        for (auto& e : ev_pre) TDBEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      }));
+    }
+    std::vector<int> ndue(lock.size(), 0);
+    for (int alpha = 1; alpha <= amax && first_rc == TDBEM_OK; ++alpha) {
       for (int i = 0; i < n; ++i) {
         tdbem_ctx* c = ctxs[i];
         if (graphed[i] || c->alpha != alpha || alpha > nt[i] - 1) continue;
+        if (fb && c->fmm) continue;  // stepped below
         note(guarded(c, [&] {
           do_step(c, forc[i] ? forc[i] + (size_t)(alpha - 1) * c->ns : c->d_zero.p, nullptr, c->d_stat.p + (alpha - 1));
         }));
       }
+      if (!fb) continue;
+      bool any = false;
+      for (size_t j = 0; j < lock.size(); ++j) {
+        tdbem_ctx* c = lock[j];
+        const int i = lock_idx[j];
+        ndue[j] = 0;
+        if (c->alpha != alpha || alpha > nt[i] - 1) continue;
+        note(guarded(c, [&] {
+          ndue[j] = do_step(c, forc[i] ? forc[i] + (size_t)(alpha - 1) * c->ns : c->d_zero.p, nullptr,
+                            c->d_stat.p + (alpha - 1), true);
+          TDBEM_HIP(hipEventRecord(ev_pre[j], c->stream));
+          TDBEM_HIP(hipStreamWaitEvent(bst, ev_pre[j], 0));
+          // the separable products on the context's stream, beside the batch's dense products
+          if (ndue[j] > 0) fmm_advance_sep(c, alpha - 1, ndue[j], c->stream);
+        }));
+        any = true;
+      }
+      if (!any || first_rc != TDBEM_OK) continue;
+      note(guarded(lock[0], [&] {
+        fmm_batch_m2l(fb, ndue.data(), bst);
+        TDBEM_HIP(hipEventRecord(ev_m2l, bst));
+      }));
+      for (size_t j = 0; j < lock.size(); ++j) {
+        tdbem_ctx* c = lock[j];
+        const int i = lock_idx[j];
+        if (c->alpha != alpha + 1 || alpha > nt[i] - 1) continue;  // stepped at this alpha
+        note(guarded(c, [&] {
+          TDBEM_HIP(hipStreamWaitEvent(c->stream, ev_m2l, 0));
+          fmm_advance_post(c, alpha - 1, ndue[j]);
+        }));
+      }
+    }
+    if (fb) {
+      if (bst) TDBEM_HIP_NOTHROW(hipStreamSynchronize(bst));
+      for (auto& e : ev_pre) if (e) (void)hipEventDestroy(e);
+      if (ev_m2l) (void)hipEventDestroy(ev_m2l);
+      if (bst) (void)hipStreamDestroy(bst);
+      fmm_batch_destroy(fb);
+    }
     for (int i = 0; i < n; ++i) note(guarded(ctxs[i], [&] { TDBEM_HIP(hipEventRecord(e1[i], ctxs[i]->stream)); }));
     for (int i = 0; i < n; ++i) TDBEM_HIP_NOTHROW(hipStreamSynchronize(ctxs[i]->stream));
     if (wall_ms) *wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -838,6 +911,7 @@ struct CkptHeader {
   double c, dt;
   int32_t mu, m_leaf, m2l_prec, interp;
   uint64_t mesh_hash;  // FNV-1a over the face vertex coordinates in face order
+  double leaf_ratio;   // the tree's sizing (0: bounding box)
 };
 
 static uint64_t mesh_hash(const tdbem_ctx* ctx) {
@@ -852,13 +926,15 @@ static uint64_t mesh_hash(const tdbem_ctx* ctx) {
 static void ckpt_fill_config(const tdbem_ctx* ctx, CkptHeader& h) {
   h.ns = ctx->ns; h.d = ctx->d; h.bie = ctx->bie; h.bc = ctx->bc;
   h.use_fmm = ctx->fmm ? 1 : 0;
-  h.depth = ctx->fmm ? ctx->opts.depth : 0;
+
   h.p_s = ctx->fmm ? ctx->opts.p_s : 0;
   h.p_t = ctx->fmm ? ctx->opts.p_t : 0;
   h.c = ctx->c; h.dt = ctx->dt;
   tdbem_info info{};
   if (ctx->fmm) fmm_info(ctx, &info);
   h.mu = info.mu; h.m_leaf = info.m_leaf;
+  h.depth = ctx->fmm ? info.depth : 0;  // the tree's depth (set by leaf_ratio when that is > 0)
+  h.leaf_ratio = ctx->fmm ? ctx->opts.leaf_ratio : 0.0;
   h.m2l_prec = ctx->fmm ? ctx->opts.m2l_prec : 0;
   h.interp = ctx->fmm ? ctx->opts.interp : 0;  // moments and locals are coefficients of this basis
   h.mesh_hash = mesh_hash(ctx);
@@ -884,7 +960,7 @@ int tdbem_checkpoint(tdbem_ctx* ctx, void* host_buf, size_t* bytes) {
     }
     CkptHeader h{};
     std::memcpy(h.magic, "TDBEMCK1", 8);
-    h.version = 2;
+    h.version = 3;
     ckpt_fill_config(ctx, h);
     h.nstate = (int32_t)st.size();
     h.alpha = ctx->alpha; h.hist_u = ctx->hist_u; h.hist_q = ctx->hist_q; h.mlp = ctx->mlp_loaded;
@@ -917,7 +993,7 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
     if (bytes < sizeof(CkptHeader)) fail(TDBEM_E_INVAL, "restore: buffer smaller than a checkpoint header");
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof(h));
-    if (std::memcmp(h.magic, "TDBEMCK1", 8) != 0 || h.version != 2) fail(TDBEM_E_INVAL, "restore: not a checkpoint");
+    if (std::memcmp(h.magic, "TDBEMCK1", 8) != 0 || h.version != 3) fail(TDBEM_E_INVAL, "restore: not a checkpoint");
     std::vector<std::pair<double*, size_t>> st;
     if (ctx->fmm) fmm_state_buffers(ctx, st);
     int64_t sd = 0;
@@ -927,6 +1003,7 @@ int tdbem_restore(tdbem_ctx* ctx, const void* host_buf, size_t bytes) {
     if (h.ns != mine.ns || h.d != mine.d || h.bie != mine.bie || h.bc != mine.bc || h.use_fmm != mine.use_fmm ||
         h.depth != mine.depth || h.p_s != mine.p_s || h.p_t != mine.p_t || h.mu != mine.mu ||
         h.m_leaf != mine.m_leaf || h.m2l_prec != mine.m2l_prec || h.interp != mine.interp || h.c != mine.c ||
+        h.leaf_ratio != mine.leaf_ratio ||
         h.dt != mine.dt || h.nstate != (int32_t)st.size() || h.state_doubles != sd)
       fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a context with a different configuration");
     if (h.mesh_hash != mine.mesh_hash) fail(TDBEM_E_INVAL, "restore: checkpoint was taken on a different mesh");

@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <cmath>
@@ -90,6 +91,20 @@ __device__ inline uint16_t bf16_lo(double x, uint16_t hi) {
   return bf16_rne(x - (double)__uint_as_float((uint32_t)hi << 16));
 }
 
+// The dense near-future operators of one level (eq. m2l_near, the gaps gf .. g0-1 of
+// each offset) with their gap ranges and storage offsets.  In normalised units
+// (lengths / (c dt), times / dt) they depend only on the level's distance from the
+// leaves, and contexts that agree on it share one set.
+struct LevelOps {
+  std::vector<std::array<int, 3>> slots;  // offsets the operators are formed for
+  std::vector<int> gf, g0;                // gap range of each slot's dense blocks
+  std::vector<int64_t> uoff;              // first operator element of each slot (nslot + 1 entries)
+  int64_t tot = 0;                        // elements of one operator copy
+  DevBuf<double> Uf;                      // FP64 operators in MFMA fragment order
+  DevBuf<float> U32;                      // FP32 (mixed precision)
+  DevBuf<uint16_t> U16;                   // BF16 fragments (split products: the second terms after tot)
+};
+
 struct FmmLevel {
   int ncell = 0;
   std::vector<std::array<int, 3>> key;      // integer cell coordinates
@@ -107,9 +122,10 @@ struct FmmLevel {
   DevBuf<int32_t> d_pairs_by_slot;          // pair indices grouped by slot
   DevBuf<int32_t> d_src_by_slot;            // their source cells (so the two loads are independent)
   int ntiles128 = 0, ntiles64 = 0, ntiles32 = 0;
-  DevBuf<double> d_U;                       // one slot's (mu+1) P x P near-future operators (set-up only)
-  DevBuf<double> d_Uf, d_stage;             // FP64: operators in MFMA fragment order, per-pair products
-  DevBuf<float> d_U32, d_stage32;           // FP32 (mixed precision): the same
+  std::shared_ptr<LevelOps> ops;            // dense near-future operators (own, or shared)
+  std::vector<int> canon;                   // slot of this level -> slot of ops
+  DevBuf<double> d_stage;                   // FP64 per-pair products
+  DevBuf<float> d_stage32;                  // FP32 / BF16 per-pair products
   DevBuf<double> d_Ktf;                     // derivative products' spatial kernels r^{-1} (and r, d = 3), fragment order
   DevBuf<double> d_tm, d_tsum;              // time moments [j][cell][b] and their node sums [j][cell]
   DevBuf<double> d_V;                       // separable pair products [product][pair][Ps]
@@ -126,7 +142,7 @@ struct FmmLevel {
   int64_t dense_blocks = 0;                 // sum over interaction pairs of their dense blocks
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_dp;
   DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
-  DevBuf<uint16_t> d_U16, d_mom16;          // BF16 M2L: operators in fragment order; moments [cell][Pp] (zero padded)
+  DevBuf<uint16_t> d_mom16;                 // BF16 M2L: moments [cell][Pp] (zero padded; split products: two copies)
 };
 
 struct Fmm {
@@ -135,6 +151,8 @@ struct Fmm {
   // accumulation); the derivative products are FP64 in every case
   int prec = 0;
   int interp = TDBEM_INTERP_LAGRANGE;
+  double leaf_ratio = 0.0;                 // > 0: leaf side / (c dt), normalised (shareable) operators
+  double oscale = 1.0;                     // factor of the dense products: (c dt)^(d-1) with normalised operators
   int Gn = 0;                              // near-future operator blocks, mu + 1
   int Pp = 0;                              // row stride of the BF16 moment copy: P rounded up to 32
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
@@ -612,7 +630,30 @@ struct M2LWork {
   M2LLevelWork lev[M2L_MAXLEV];
   int nlev;
   int total;                     // work items over all levels
+  // several contexts in one launch: nlev descriptors in device memory, entry e's items
+  // numbered from gitem0[e] (NULL: the nlev descriptors above)
+  const M2LLevelWork* glev;
+  const int32_t* gitem0;
 };
+
+// The level descriptor of work item `item` (GLEV: from the device table; a separate
+// instantiation, so that the usual launch reads its descriptors from the kernel arguments).
+template <bool GLEV>
+__device__ inline const M2LLevelWork& item_level(const M2LWork& W, int item) {
+  if constexpr (GLEV) {
+    int lo = 0, hi = W.nlev - 1;  // the last entry whose first item is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (W.gitem0[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    return W.glev[lo];
+  } else {
+    int lv = 0;
+    while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
+    return W.lev[lv];
+  }
+}
 
 // Waves per SIMD that the register allocation aims at for FP32 (without a
 // target the compiler parks values in the accumulation registers and lands a
@@ -622,7 +663,7 @@ constexpr int m2l_waves() {
   return sizeof(T) == 8 || NCB == 8 ? 1 : PERS ? (NCB == 2 ? 2 : 1) : (NCB == 2 && KS == 16) ? 3 : 2;
 }
 
-template <class T, int NCB, int KS, int RPW, bool PERS>
+template <class T, int NCB, int KS, int RPW, bool PERS, bool GLEV = false>
 __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l_mfma_kernel(int P, int GP, int RB, int KB, M2LWork W) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int BN = NCB * 16;              // columns (interaction pairs) per tile
@@ -645,9 +686,7 @@ __global__ __launch_bounds__(256, (m2l_waves<T, NCB, KS, RPW, PERS>())) void m2l
   // row block of U in the XCD's L2.
   const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
   const int item = x8 * q8 + min(x8, r8) + w / 8;
-  int lv = 0;
-  while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
-  const M2LLevelWork& Lw = W.lev[lv];
+  const M2LLevelWork& Lw = item_level<GLEV>(W, item);
   const int local = item - Lw.item0;
   const int64_t per = (int64_t)RB * KB * 64;
   const ItemGeom ig = item_geom(Lw, local, GP, per);
@@ -831,7 +870,7 @@ constexpr int m2l_direct_waves() {
   return sizeof(T) == 8 || PERS || NCB != 2 ? 1 : RPW == 2 ? 3 : 2;
 }
 
-template <class T, int NCB, int RPW, bool PERS>
+template <class T, int NCB, int RPW, bool PERS, bool GLEV = false>
 __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void m2l_direct_kernel(
     int P, int GP, int RB, int KB, M2LWork W) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -846,9 +885,7 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
   do {
   const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
   const int item = x8 * q8 + min(x8, r8) + w / 8;
-  int lv = 0;
-  while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
-  const M2LLevelWork& Lw = W.lev[lv];
+  const M2LLevelWork& Lw = item_level<GLEV>(W, item);
   const int local = item - Lw.item0;
   const int64_t per = (int64_t)RB * KB * 64;
   const ItemGeom ig = item_geom(Lw, local, GP, per);
@@ -997,7 +1034,7 @@ __global__ __launch_bounds__(256, (m2l_direct_waves<T, NCB, RPW, PERS>())) void 
 // loop; fragments of the next K step are loaded while the current one multiplies.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-template <int NCB, int RPW, bool PERS, bool X3>
+template <int NCB, int RPW, bool PERS, bool X3, bool GLEV = false>
 __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB, int KB32, M2LWork W) {
   typedef float f4_t __attribute__((ext_vector_type(4)));
   constexpr int BN = NCB * 16;
@@ -1008,9 +1045,7 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
   do {
   const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
   const int item = x8 * q8 + min(x8, r8) + w / 8;
-  int lv = 0;
-  while (lv + 1 < W.nlev && item >= W.lev[lv + 1].item0) ++lv;
-  const M2LLevelWork& Lw = W.lev[lv];
+  const M2LLevelWork& Lw = item_level<GLEV>(W, item);
   const int local = item - Lw.item0;
   const ItemGeom ig = item_geom(Lw, local, GP, (int64_t)RB * KB32 * 512);
   const int tile = ig.tile, rowblk = ig.rowblk, rows = ig.rows, RBs = (rows + 15) >> 4;
@@ -1147,32 +1182,32 @@ constexpr int M2L_FIRST_DIRECT = 8;  // variants from here on use m2l_direct_ker
 static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32, 32, 32, 64, 64};
 static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4, 2, 4, 2, 4};
 
-template <class T, bool PERS>
+template <class T, bool PERS, bool GLEV = false>
 static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
   switch (v) {
-    case 0: m2l_mfma_kernel<T, 8, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 1: m2l_mfma_kernel<T, 4, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 2: m2l_mfma_kernel<T, 4, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 3: m2l_mfma_kernel<T, 2, 16, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 4: m2l_mfma_kernel<T, 2, 32, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 5: m2l_mfma_kernel<T, 2, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 6: m2l_mfma_kernel<T, 4, 16, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 7: m2l_mfma_kernel<T, 2, 32, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 8: m2l_direct_kernel<T, 2, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 9: m2l_direct_kernel<T, 2, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    case 10: m2l_direct_kernel<T, 4, 2, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
-    default: m2l_direct_kernel<T, 4, 4, PERS><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 0: m2l_mfma_kernel<T, 8, 16, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 1: m2l_mfma_kernel<T, 4, 16, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 2: m2l_mfma_kernel<T, 4, 32, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 3: m2l_mfma_kernel<T, 2, 16, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 4: m2l_mfma_kernel<T, 2, 32, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 5: m2l_mfma_kernel<T, 2, 16, 4, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 6: m2l_mfma_kernel<T, 4, 16, 4, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 7: m2l_mfma_kernel<T, 2, 32, 4, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 8: m2l_direct_kernel<T, 2, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 9: m2l_direct_kernel<T, 2, 4, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    case 10: m2l_direct_kernel<T, 4, 2, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
+    default: m2l_direct_kernel<T, 4, 4, PERS, GLEV><<<grid, 256, 0, st>>>(P, GP, RB, KB, W); break;
   }
 }
 
 // BF16 contexts use the tile shapes of variants 8 .. 11 (columns x rows per workgroup).
-template <bool PERS, bool X3>
+template <bool PERS, bool X3, bool GLEV = false>
 static void launch_m2l_bf16_tile(int v, int grid, hipStream_t st, int Pp, int GP, int RB, int KB32, const M2LWork& W) {
   switch (v) {
-    case 8: m2l_bf16_kernel<2, 2, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    case 9: m2l_bf16_kernel<2, 4, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    case 10: m2l_bf16_kernel<4, 2, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    default: m2l_bf16_kernel<4, 4, PERS, X3><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 8: m2l_bf16_kernel<2, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 9: m2l_bf16_kernel<2, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 10: m2l_bf16_kernel<4, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    default: m2l_bf16_kernel<4, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
   }
 }
 
@@ -1207,7 +1242,7 @@ template <class ST>
 __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Gn, int R, int k,
                                                          const int32_t* __restrict__ il_ptr,
                                                          const int32_t* __restrict__ pair_gr,
-                                                         const ST* __restrict__ stage, int ncell,
+                                                         const ST* __restrict__ stage, int ncell, double scale,
                                                          double* __restrict__ ring) {
   const int O = blockIdx.x, g = blockIdx.y, gap = g + 1;
   const int a = blockIdx.z * blockDim.x + threadIdx.x;
@@ -1226,7 +1261,7 @@ __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Gn, int R, i
     const int r0 = pair_gr[p];
     if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) s0 += (double)sp[(int64_t)p * ld];
   }
-  ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += s0 + s1;
+  ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += scale * (s0 + s1);
 }
 
 // Time moments of the completed source interval's moments, per cell:
@@ -1430,14 +1465,24 @@ __global__ __launch_bounds__(64) void l2p_kernel(int Ps, int pt, int bie, double
 
 static void build_tree(tdbem_ctx* ctx, Fmm* f) {
   const Geometry& g = ctx->geo;
-  const int ns = g.ns, D = f->D;
   double ext = 0.0;
   for (int k = 0; k < 3; ++k) {
     f->center[k] = 0.5 * (g.ext_lo[k] + g.ext_hi[k]);
     ext = std::max(ext, 0.5 * (g.ext_hi[k] - g.ext_lo[k]));
   }
   if (!(ext > 0.0)) throw Error(TDBEM_E_INVAL, "degenerate mesh extent");
-  f->H = std::pow(2.0, std::ceil(std::log2(ext)));
+  if (f->leaf_ratio > 0.0) {
+    // leaf half side leaf_ratio * c dt / 2; the fewest levels whose root holds the mesh
+    const double hl = 0.5 * f->leaf_ratio * ctx->cdt;
+    int D = 2;
+    while (D < 12 && hl * (double)(1 << D) < ext) ++D;
+    if (hl * (double)(1 << D) < ext) throw Error(TDBEM_E_INVAL, "leaf_ratio too small for this mesh (depth > 12)");
+    f->D = D;
+    f->H = hl * (double)(1 << D);
+  } else {
+    f->H = std::pow(2.0, std::ceil(std::log2(ext)));
+  }
+  const int ns = g.ns, D = f->D;
   f->e_max = g.e_max;
   const int n = 1 << D;
   std::vector<std::array<int, 3>> li(ns);
@@ -1534,9 +1579,14 @@ static void build_hierarchy(tdbem_ctx* ctx, Fmm* f) {
                                "largest centroid-to-vertex distance");
   f->m_leaf = m_leaf;
   // smallest mu with c (t - s) - r > 0 for every node pair of interval k+mu+1, every level and offset
+  // (normalised operators: lengths in units of c dt and times in units of dt, so that
+  // every context with the same normalised hierarchy finds the same mu)
+  const bool nrm = f->leaf_ratio > 0.0;
+  const double cc = nrm ? 1.0 : ctx->c, dtt = nrm ? 1.0 : ctx->dt;
   int need = 1;
   for (int l = 2; l <= f->D; ++l) {
-    const double hs = hs_of(f, l), Ml = (double)m_leaf * (1 << (f->D - l)), ht = Ml * ctx->dt / 2.0;
+    const double Ml = (double)m_leaf * (1 << (f->D - l)), ht = Ml * dtt / 2.0;
+    const double hs = nrm ? 0.5 * f->leaf_ratio * (double)(1 << (f->D - l)) : hs_of(f, l);
     double smin = 1e300, smax = -1e300, tmin = 1e300;
     for (int a = 0; a < f->ps; ++a) { smin = std::min(smin, f->om_s[a]); smax = std::max(smax, f->om_s[a]); }
     for (int m = 0; m < f->pt; ++m)
@@ -1545,7 +1595,7 @@ static void build_hierarchy(tdbem_ctx* ctx, Fmm* f) {
     const double ax = 6.0 * hs + hs * (smax - smin);
     const double rmax = std::sqrt(3.0) * ax;
     int m = 1;
-    while (ctx->c * (((m + 1) * Ml + 1.0) * ctx->dt + ht * tmin) - rmax <= 0.0) ++m;
+    while (cc * (((m + 1) * Ml + 1.0) * dtt + ht * tmin) - rmax <= 0.0) ++m;
     need = std::max(need, m);
   }
   if (ctx->opts.mu > 0 && ctx->opts.mu < need)
@@ -1596,19 +1646,15 @@ static void upload(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
 // launch does their near-future products.  choice = 2 * variant + persistent.
 static int cols_index(int cols) { return cols == 128 ? 0 : cols == 64 ? 1 : 2; }
 
-static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
-  const int P = f->P, G = f->Gn;
+// The work descriptor of level l for tile variant v; false if the level has no items.
+static bool level_work(const Fmm* f, int l, int v, int item0, M2LLevelWork& Lw, int& nitems) {
   const bool lo = f->prec == 1, b16 = f->prec >= 2, x3 = f->prec == 3;
-  const int v = choice >> 1, persistent = choice & 1;
   const int rows = 64 * kVariantRpw[v];
-  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
   const int cols = kVariantCols[v], ci = cols_index(cols), ri = rows == 128 ? 0 : 1;
-  M2LWork W{};
-  int total = 0;
-  for (int l = f->D; l > f->D - n && l >= 2; --l) {
-    const FmmLevel& L = f->lev[l];
-    if (L.npair == 0 || L.nitems[ci][ri] == 0) continue;
-    M2LLevelWork& Lw = W.lev[W.nlev++];
+  const FmmLevel& L = f->lev[l];
+  if (L.npair == 0 || L.nitems[ci][ri] == 0) return false;
+  Lw = M2LLevelWork{};
+  {
     Lw.ntiles = cols == 128 ? L.ntiles128 : cols == 64 ? L.ntiles64 : L.ntiles32;
     Lw.tiles = cols == 128 ? L.d_tiles128.p : cols == 64 ? L.d_tiles64.p : L.d_tiles32.p;
     Lw.pairs_by_slot = L.d_pairs_by_slot.p;
@@ -1616,22 +1662,42 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
     Lw.mom = L.d_mom.p;
     Lw.mom32 = L.d_mom32.p;
     Lw.mom16 = L.d_mom16.p;
+    const LevelOps& ops = *L.ops;
     if (x3) {  // second terms after the first (same layouts)
-      Lw.Uf_lo = L.d_U16.p + L.d_U16.n / 2;
+      Lw.Uf_lo = ops.U16.p + ops.tot;
       Lw.mom16_lo = L.d_mom16.p + L.d_mom16.n / 2;
     }
-    if (lo) { Lw.Uf = L.d_U32.p; Lw.stage = L.d_stage32.p; }
-    else if (b16) { Lw.Uf = L.d_U16.p; Lw.stage = L.d_stage32.p; }
-    else { Lw.Uf = L.d_Uf.p; Lw.stage = L.d_stage.p; }
+    if (lo) { Lw.Uf = ops.U32.p; Lw.stage = L.d_stage32.p; }
+    else if (b16) { Lw.Uf = ops.U16.p; Lw.stage = L.d_stage32.p; }
+    else { Lw.Uf = ops.Uf.p; Lw.stage = L.d_stage.p; }
     Lw.items = L.d_items[ci][ri].p;
     Lw.uoff = L.d_uoff.p;
     Lw.srows = L.d_srows.p;
     Lw.soff = L.d_soff.p;
-    Lw.item0 = total;
-    total += L.nitems[ci][ri];
+    Lw.item0 = item0;
+    nitems = L.nitems[ci][ri];
   }
-  W.total = total;
+  return true;
+}
+
+// Launch of a filled work descriptor (tile variant and persistence from choice).
+static void launch_m2l_work(const Fmm* f, int choice, const M2LWork& W, hipStream_t st) {
+  const int P = f->P, G = f->Gn;
+  const bool lo = f->prec == 1, b16 = f->prec >= 2, x3 = f->prec == 3;
+  const int v = choice >> 1, persistent = choice & 1;
+  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
+  const int total = W.total;
   if (total == 0) return;
+  if (W.glev) {  // several contexts: one item per workgroup, descriptors from the device table
+    if (b16) {
+      const int KB32 = (P + 31) / 32;
+      if (x3) launch_m2l_bf16_tile<false, true, true>(v, total, st, f->Pp, G * P, RB, KB32, W);
+      else launch_m2l_bf16_tile<false, false, true>(v, total, st, f->Pp, G * P, RB, KB32, W);
+    } else if (lo) launch_m2l_tile<float, false, true>(v, total, st, P, G * P, RB, KB, W);
+    else launch_m2l_tile<double, false, true>(v, total, st, P, G * P, RB, KB, W);
+    TDBEM_HIP(hipGetLastError());
+    return;
+  }
   const bool pers = persistent && total > f->persistent_grid;
   const int grid = pers ? f->persistent_grid : total;
   if (b16) {
@@ -1646,6 +1712,20 @@ static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
   } else if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
   else launch_m2l_variant<double>(v, pers, grid, st, P, G * P, RB, KB, W);
   TDBEM_HIP(hipGetLastError());
+}
+
+static void launch_m2l_levels(const Fmm* f, int n, int choice, hipStream_t st) {
+  M2LWork W{};
+  int total = 0;
+  for (int l = f->D; l > f->D - n && l >= 2; --l) {
+    int ni = 0;
+    if (level_work(f, l, choice >> 1, total, W.lev[W.nlev], ni)) {
+      ++W.nlev;
+      total += ni;
+    }
+  }
+  W.total = total;
+  launch_m2l_work(f, choice, W, st);
 }
 
 // Separable pair products of one level (see m2l_sep_expand_kernel):
@@ -1743,27 +1823,25 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
   if (e1) (void)hipEventDestroy(e1);
 }
 
-// For every slot (offset) of level l: gf, the first near-future gap with a node
-// pair past the wavefront (c (t - s) - r > 0), and g0, the first gap with every
-// node pair past it, over the same node coordinates as m2l_matrix_kernel; then
-// the work items of the dense products (each slot's gaps gf .. g0-1), the per-pair
-// gap ranges in target order, and the per-slot row tables.
-static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector<int32_t>& tiles128,
-                          const std::vector<int32_t>& tiles64, const std::vector<int32_t>& tiles32, hipStream_t st) {
-  FmmLevel& L = f->lev[l];
-  const int nslot = (int)L.slot_off.size(), ps = f->ps, Ps = f->Ps, P = f->P;
-  const double hs = hs_of(f, l), Ml = (double)f->m_leaf * (1 << (f->D - l)), ht = Ml * ctx->dt / 2.0;
+// Gap range of each slot's dense blocks: gap g (1..mu+1) of an offset is zero at
+// every node pair while c (t - s) <= r there (g < gf), a polynomial at every node
+// pair once c (t - s) > r everywhere (g >= g0), and a dense block in between, with
+// the node coordinates of m2l_matrix_kernel (lengths and times in the units of c, dt, hs).
+static void gap_ranges(const Fmm* f, const std::vector<std::array<int, 3>>& slots, double c, double dt, double hs,
+                       double Ml, std::vector<int>& gfv, std::vector<int>& g0v) {
+  const int nslot = (int)slots.size(), ps = f->ps, Ps = f->Ps;
+  const double ht = Ml * dt / 2.0;
   double dmin = 1e300, dmax = -1e300;
   for (int m = 0; m < f->pt; ++m)
     for (int n = 0; n < f->pt; ++n) {
       dmin = std::min(dmin, f->om_t[m] - f->om_t[n]);
       dmax = std::max(dmax, f->om_t[m] - f->om_t[n]);
     }
-  L.gf.assign(nslot, 1);
-  L.g0.assign(nslot, 1);
+  gfv.assign(nslot, 1);
+  g0v.assign(nslot, 1);
   for (int sl = 0; sl < nslot; ++sl) {
     double rmin = 1e300, rmax = 0.0;
-    const auto& o = L.slot_off[sl];
+    const auto& o = slots[sl];
     for (int a = 0; a < Ps; ++a)
       for (int b = 0; b < Ps; ++b) {
         const int aa[3] = {a % ps, (a / ps) % ps, a / (ps * ps)}, bb[3] = {b % ps, (b / ps) % ps, b / (ps * ps)};
@@ -1778,21 +1856,135 @@ static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector
       }
     int gf = f->mu + 2, g0 = f->mu + 2;
     for (int g = f->mu + 1; g >= 1; --g) {
-      const double t0 = (g * Ml + 1.0) * ctx->dt;
-      if (ctx->c * (t0 + ht * dmax) - rmin > 0.0) gf = g;
-      if (ctx->c * (t0 + ht * dmin) - rmax > 0.0) g0 = g;
+      const double t0 = (g * Ml + 1.0) * dt;
+      if (c * (t0 + ht * dmax) - rmin > 0.0) gf = g;
+      if (c * (t0 + ht * dmin) - rmax > 0.0) g0 = g;
     }
     if (g0 > f->mu + 1) throw Error(TDBEM_E_INVAL, "expansion gap not past the wavefront for some offset");
-    L.gf[sl] = std::min(gf, g0);
-    L.g0[sl] = g0;
+    gfv[sl] = std::min(gf, g0);
+    g0v[sl] = g0;
   }
-  std::vector<int32_t> srows(std::max(nslot, 1), 0), soff(std::max(nslot, 1), 0);
+}
+
+// The dense operators of ops.slots at one level: gap ranges, then each slot's FP64
+// (mu+1)-block stack built in a one-slot buffer and its dense rows converted to the
+// products' precision and fragment order (no copy of the whole level in FP64).
+static void build_level_ops(const tdbem_ctx* ctx, const Fmm* f, LevelOps& ops, double c, double dt, double hs,
+                            double Ml, hipStream_t st) {
+  const int P = f->P, G = f->Gn, nslot = (int)ops.slots.size();
+  gap_ranges(f, ops.slots, c, dt, hs, Ml, ops.gf, ops.g0);
+  const int KB = m2l_kblocks(P), KB32 = (P + 31) / 32;
+  ops.uoff.assign(nslot + 1, 0);
   for (int sl = 0; sl < nslot; ++sl) {
+    const int rows = (ops.g0[sl] - ops.gf[sl]) * P, RBs = (rows + 15) / 16;
+    ops.uoff[sl + 1] = ops.uoff[sl] + (f->prec >= 2 ? (int64_t)RBs * KB32 * 512 : (int64_t)RBs * KB * 64);
+  }
+  ops.tot = std::max<int64_t>(ops.uoff[nslot], 1);
+  const size_t tot = (size_t)ops.tot;
+  if (f->prec >= 2) ops.U16.alloc((f->prec == 3 ? 2 : 1) * tot);  // split products: second terms after tot
+  else if (f->prec == 1) ops.U32.alloc(tot);
+  else ops.Uf.alloc(tot);
+  std::vector<int32_t> so;
+  for (auto& v : ops.slots) { so.push_back(v[0]); so.push_back(v[1]); so.push_back(v[2]); }
+  DevBuf<int32_t> d_so;
+  upload(d_so, so, st);
+  DevBuf<double> d_U;  // one slot's (mu+1) P x P near-future operators
+  d_U.alloc((size_t)G * P * P);
+  for (int sl = 0; sl < nslot; ++sl) {
+    const int rows = (ops.g0[sl] - ops.gf[sl]) * P, RBs = (rows + 15) / 16, row0 = (ops.gf[sl] - 1) * P;
+    if (rows == 0) continue;
+    dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, 1);
+    m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, c, hs, Ml * dt / 2.0, dt, (int)Ml,
+                                            f->nodes, d_so.p + 3 * sl, d_U.p);
+    TDBEM_HIP(hipGetLastError());
+    const int64_t n = ops.uoff[sl + 1] - ops.uoff[sl];
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (f->prec >= 2)
+      to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB32, d_U.p, ops.U16.p + ops.uoff[sl],
+                                                   f->prec == 3 ? ops.U16.p + tot + ops.uoff[sl] : nullptr);
+    else if (f->prec == 1)
+      to_fragments_kernel<float><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, d_U.p, ops.U32.p + ops.uoff[sl]);
+    else
+      to_fragments_kernel<double><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, d_U.p, ops.Uf.p + ops.uoff[sl]);
+    TDBEM_HIP(hipGetLastError());
+  }
+  TDBEM_HIP(hipStreamSynchronize(st));  // the one-slot buffer and d_so are released at return
+}
+
+// The 316 interaction-list offsets (cells one box apart excluded), in a fixed order.
+static const std::vector<std::array<int, 3>>& all_offsets() {
+  static const std::vector<std::array<int, 3>> v = [] {
+    std::vector<std::array<int, 3>> o;
+    for (int x = -3; x <= 3; ++x)
+      for (int y = -3; y <= 3; ++y)
+        for (int z = -3; z <= 3; ++z)
+          if (std::max({std::abs(x), std::abs(y), std::abs(z)}) >= 2) o.push_back({x, y, z});
+    return o;
+  }();
+  return v;
+}
+
+// Normalised operator sets shared between contexts: (device, p_s, p_t, interp, d, mu,
+// precision, M_l, h_s / (c dt)).  The map holds no reference: a set lives while a context uses it.
+typedef std::tuple<int, int, int, int, int, int, int, int, double> OpsKey;
+static std::mutex g_ops_mu;
+static std::map<OpsKey, std::weak_ptr<LevelOps>> g_ops_cache;
+
+// The level's operators: its own set in physical units, or (opts.leaf_ratio > 0) the
+// normalised set of the 316 offsets shared with every context that agrees on the key.
+static void level_ops(const tdbem_ctx* ctx, Fmm* f, int l, hipStream_t st) {
+  FmmLevel& L = f->lev[l];
+  const double Ml = (double)f->m_leaf * (1 << (f->D - l));
+  const int nslot = (int)L.slot_off.size();
+  L.canon.assign(nslot, 0);
+  if (f->leaf_ratio > 0.0) {
+    const double hsn = 0.5 * f->leaf_ratio * (double)(1 << (f->D - l));  // h_s / (c dt), exact
+    int dev = 0;
+    TDBEM_HIP(hipGetDevice(&dev));
+    const OpsKey key{dev, f->ps, f->pt, f->interp, ctx->d, f->mu, f->prec, (int)Ml, hsn};
+    std::lock_guard<std::mutex> lk(g_ops_mu);
+    L.ops = g_ops_cache[key].lock();
+    if (!L.ops) {
+      L.ops = std::make_shared<LevelOps>();
+      L.ops->slots = all_offsets();
+      build_level_ops(ctx, f, *L.ops, 1.0, 1.0, hsn, Ml, st);
+      g_ops_cache[key] = L.ops;
+    }
+    const auto& all = all_offsets();
+    for (int sl = 0; sl < nslot; ++sl)
+      L.canon[sl] = (int)(std::find(all.begin(), all.end(), L.slot_off[sl]) - all.begin());
+  } else {
+    L.ops = std::make_shared<LevelOps>();
+    L.ops->slots = L.slot_off;
+    build_level_ops(ctx, f, *L.ops, ctx->c, ctx->dt, hs_of(f, l), Ml, st);
+    for (int sl = 0; sl < nslot; ++sl) L.canon[sl] = sl;
+  }
+}
+
+// Per context, from the level's operator set: each slot's gap range, dense rows and
+// operator offset, the per-pair gap ranges in target order, and the work items of the
+// dense products (each slot's gaps gf .. g0-1).
+static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector<int32_t>& tiles128,
+                          const std::vector<int32_t>& tiles64, const std::vector<int32_t>& tiles32, hipStream_t st) {
+  (void)ctx;
+  FmmLevel& L = f->lev[l];
+  const int nslot = (int)L.slot_off.size(), P = f->P;
+  const LevelOps& ops = *L.ops;
+  L.gf.assign(nslot, 1);
+  L.g0.assign(nslot, 1);
+  std::vector<int32_t> srows(std::max(nslot, 1), 0), soff(std::max(nslot, 1), 0);
+  std::vector<int64_t> uoff(std::max(nslot, 1), 0);
+  for (int sl = 0; sl < nslot; ++sl) {
+    const int c = L.canon[sl];
+    L.gf[sl] = ops.gf[c];
+    L.g0[sl] = ops.g0[c];
     srows[sl] = (L.g0[sl] - L.gf[sl]) * P;
     soff[sl] = (L.gf[sl] - 1) * P;
+    uoff[sl] = ops.uoff[c];
   }
   upload(L.d_srows, srows, st);
   upload(L.d_soff, soff, st);
+  upload(L.d_uoff, uoff, st);
   std::vector<int32_t> gr(std::max<int64_t>(L.npair, 1), 0);
   L.dense_blocks = 0;
   for (int64_t p = 0; p < L.npair; ++p) {
@@ -1824,7 +2016,8 @@ static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector
 
 Fmm* fmm_create(tdbem_ctx* ctx) {
   const tdbem_opts& o = ctx->opts;
-  if (o.depth < 2 || o.depth > 12) throw Error(TDBEM_E_INVAL, "depth must be in [2, 12]");
+  if (!(o.leaf_ratio >= 0.0)) throw Error(TDBEM_E_INVAL, "leaf_ratio must be >= 0");
+  if (o.leaf_ratio == 0.0 && (o.depth < 2 || o.depth > 12)) throw Error(TDBEM_E_INVAL, "depth must be in [2, 12]");
   if (o.p_s < 2 || o.p_s > MAXP || o.p_t < 2 || o.p_t > MAXP)
     throw Error(TDBEM_E_INVAL, "p_s and p_t must be in [2, 8]");
   if (o.p_t <= ctx->d) throw Error(TDBEM_E_INVAL, "p_t must exceed the B-spline order d");
@@ -1837,7 +2030,9 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     throw Error(TDBEM_E_INVAL, "m2l_prec must be FP64 (0), FP32 (1) or BF16 (2)");
   Fmm* f = new Fmm();
   try {
-    f->D = o.depth;
+    f->D = o.depth;  // with leaf_ratio > 0 the tree sets it
+    f->leaf_ratio = o.leaf_ratio;
+    f->oscale = o.leaf_ratio > 0.0 ? std::pow(ctx->cdt, ctx->d - 1) : 1.0;
     f->prec = o.m2l_prec;
     f->ps = o.p_s;
     f->pt = o.p_t;
@@ -1982,6 +2177,7 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_tsum.alloc((size_t)L.ncell * (ctx->d + 1));
       const int nv = (ctx->d + 1) + std::max(0, ctx->d - 1) + std::max(0, ctx->d - 2);
       L.d_V.alloc((size_t)std::max<int64_t>(L.npair, 1) * nv * f->Ps);
+      level_ops(ctx, f, l, st);
       classify_gaps(ctx, f, l, tiles128, tiles64, tiles32, st);
       L.d_mom.alloc((size_t)L.ncell * P);
       if (f->prec == 1) {
@@ -1996,48 +2192,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
-      {
-        // dense blocks only: each slot's gaps gf .. g0-1, its FP64 operator stack built in
-        // a per-slot buffer and converted slot by slot (no master copy of the whole level)
-        const int KB = m2l_kblocks(P), KB32 = (P + 31) / 32;
-        const double Ml = (double)f->m_leaf * (1 << (f->D - l));
-        L.d_U.alloc((size_t)G * P * P);
-        std::vector<int64_t> uoff(std::max(nslot, 1) + 1, 0);
-        for (int sl = 0; sl < nslot; ++sl) {
-          const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16;
-          uoff[sl + 1] = uoff[sl] + (f->prec >= 2 ? (int64_t)RBs * KB32 * 512 : (int64_t)RBs * KB * 64);
-        }
-        const size_t tot = (size_t)std::max<int64_t>(uoff[nslot > 0 ? nslot : 0], 1);
-        if (f->prec >= 2) L.d_U16.alloc((f->prec == 3 ? 2 : 1) * tot);  // split products: second terms after tot
-        else if (f->prec == 1) L.d_U32.alloc(tot);
-        else L.d_Uf.alloc(tot);
-        for (int sl = 0; sl < nslot; ++sl) {
-          const int rows = (L.g0[sl] - L.gf[sl]) * P, RBs = (rows + 15) / 16, row0 = (L.gf[sl] - 1) * P;
-          if (rows == 0) continue;
-          dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, 1);
-          m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, ctx->c, hs_of(f, l),
-                                                  Ml * ctx->dt / 2.0, ctx->dt, (int)Ml, nodes, d_so.p + 3 * sl,
-                                                  L.d_U.p);
-          TDBEM_HIP(hipGetLastError());
-          const double* Us = L.d_U.p;
-          const int64_t n = uoff[sl + 1] - uoff[sl];
-          const unsigned nb = (unsigned)((n + 255) / 256);
-          if (f->prec >= 2)
-            to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB32, Us, L.d_U16.p + uoff[sl],
-                                                         f->prec == 3 ? L.d_U16.p + tot + uoff[sl] : nullptr);
-          else if (f->prec == 1)
-            to_fragments_kernel<float><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, Us, L.d_U32.p + uoff[sl]);
-          else
-            to_fragments_kernel<double><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, Us, L.d_Uf.p + uoff[sl]);
-          TDBEM_HIP(hipGetLastError());
-        }
-        uoff.resize(std::max(nslot, 1));
-        upload(L.d_uoff, uoff, st);
-        if (f->prec != 0) L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
-        else L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
-        TDBEM_HIP(hipStreamSynchronize(st));
-        L.d_U.release();  // the per-slot FP64 stack is no longer needed
-      }
+      if (f->prec != 0) L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+      else L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
       for (DevBuf<double>* b : {&L.d_mom, &L.d_ring, &L.d_lp, &L.d_aux})
         TDBEM_HIP(hipMemsetAsync(b->p, 0, b->n * sizeof(double), st));
       TDBEM_HIP(hipStreamSynchronize(st));  // temporaries (d_so) are released at scope end
@@ -2111,10 +2267,35 @@ void fmm_far(tdbem_ctx* ctx, int alpha, double* out) {
 
 static int sep_threads(int P) { return std::min(1024, ((P + 63) / 64) * 64); }
 
+// Levels whose source interval ends after sample beta: D, D-1, ..., D-n+1.
+static int due_levels(const Fmm* f, int beta) {
+  int ndue = 0;
+  for (int l = f->D; l >= 2; --l) {
+    const int Ml = f->m_leaf * (1 << (f->D - l));
+    if ((beta + 2) % Ml != 0) break;
+    ++ndue;
+  }
+  return ndue;
+}
+
 void fmm_advance(tdbem_ctx* ctx, int beta) {
+  // all on the context's stream: running the separable products on a second stream beside
+  // the dense ones gained 1% on one large context and serialised the captured marches of a
+  // many-context batch
+  Fmm* f = ctx->fmm;
+  const int ndue = fmm_advance_pre(ctx, beta);
+  if (ndue > 0) {
+    fmm_advance_sep(ctx, beta, ndue, ctx->stream);
+    ProfScope ps(ctx, K_M2L_GEMM);
+    launch_m2l_levels(f, ndue, f->m2l_choice[ndue], ctx->stream);
+  }
+  fmm_advance_post(ctx, beta, ndue);
+}
+
+int fmm_advance_pre(tdbem_ctx* ctx, int beta) {
   Fmm* f = ctx->fmm;
   hipStream_t st = ctx->stream;
-  const int D = f->D, P = f->P, G = f->G;
+  const int D = f->D, P = f->P;
   // densities of the new sample and P2M into the leaf source interval
   ProfScope* p2m_scope = new ProfScope(ctx, K_P2M);
   densities_kernel<<<(ctx->ns + 255) / 256, 256, 0, st>>>(ctx->ns, beta, ctx->d, ctx->bw, ctx->d_hu.p, ctx->d_hq.p,
@@ -2138,16 +2319,8 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
   delete p2m_scope;
   const double* S = f->d_S.p;
   const double* T = S + 2 * f->ps * f->ps;
-  const double* St = T + 2 * f->pt * f->pt;
-  const double* Tt = St + 2 * f->ps * f->ps;
   const size_t shm = 2 * (size_t)P * sizeof(double);
-  // levels whose source interval ends now: D, D-1, ..., D-ndue+1
-  int ndue = 0;
-  for (int l = D; l >= 2; --l) {
-    const int Ml = f->m_leaf * (1 << (D - l));
-    if ((beta + 2) % Ml != 0) break;
-    ++ndue;
-  }
+  const int ndue = due_levels(f, beta);
   if (ndue > 0) {
     // M2M first (bottom-up: a parent's moments are complete before its own
     // products); it only reads each level's moments, so one M2L launch can then
@@ -2163,39 +2336,62 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
                                                          Pl.d_mom16.p, f->Pp, f->prec == 3 ? (int64_t)Pl.ncell * f->Pp : 0);
       TDBEM_HIP(hipGetLastError());
     }
-    {
-      ProfScope ps(ctx, K_M2L_GEMM);
-      launch_m2l_levels(f, ndue, f->m2l_choice[ndue], st);
-    }
+  }
+  return ndue;
+}
+
+// Separable products of the due levels (the wavefront-free near-future gaps and the
+// derivative products L^{(p)}_{k+mu+1,k}, FP64) on stream st.  They read the moments and
+// write the locals and derivative terms, which the dense products do not touch, so in a
+// lock-step batch they run on each context's stream beside the batch's dense products;
+// the reduction of the dense products comes after them.
+void fmm_advance_sep(tdbem_ctx* ctx, int beta, int ndue, hipStream_t st) {
+  Fmm* f = ctx->fmm;
+  const int D = f->D;
+  for (int l = D; l > D - ndue; --l) {
+    const int Ml = f->m_leaf * (1 << (D - l));
+    const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
+    FmmLevel& L = f->lev[l];
+    if (L.npair == 0) continue;
+    ProfScope ps(ctx, K_M2L_DERIV, st);
+    const double ht = Ml * ctx->dt / 2.0;
+    m2l_time_moments_kernel<<<L.ncell, 64, 0, st>>>(f->Ps, f->pt, ctx->d, ht, f->nodes, L.ncell, L.d_mom.p,
+                                                    L.d_tm.p, L.d_tsum.p);
+    TDBEM_HIP(hipGetLastError());
+    launch_sep_products(f, L, ctx->d, st);
+    m2l_sep_expand_kernel<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
+        f->Ps, f->pt, ctx->d, f->mu, f->R, k, ctx->c, ctx->dt, Ml, ht, f->nodes, L.ncell, L.npair,
+        L.d_il_ptr.p, L.d_il_src.p, L.d_pair_gr.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
+    TDBEM_HIP(hipGetLastError());
+  }
+}
+
+void fmm_advance_post(tdbem_ctx* ctx, int beta, int ndue) {
+  Fmm* f = ctx->fmm;
+  hipStream_t st = ctx->stream;
+  const int D = f->D, P = f->P;
+  const double* S = f->d_S.p;
+  const double* T = S + 2 * f->ps * f->ps;
+  const double* St = T + 2 * f->pt * f->pt;
+  const double* Tt = St + 2 * f->ps * f->ps;
+  (void)T;
+  const size_t shm = 2 * (size_t)P * sizeof(double);
+  if (ndue > 0) {
     for (int l = D; l > D - ndue; --l) {
       const int Ml = f->m_leaf * (1 << (D - l));
       const int k = (beta + 2) / Ml - 1;  // completed source interval at level l
       FmmLevel& L = f->lev[l];
       if (L.npair > 0) {
-        {
-          // separable products: the wavefront-free near-future gaps and the derivative
-          // products L^{(p)}_{k+mu+1,k}, FP64
-          ProfScope ps(ctx, K_M2L_DERIV);
-          const double ht = Ml * ctx->dt / 2.0;
-          m2l_time_moments_kernel<<<L.ncell, 64, 0, st>>>(f->Ps, f->pt, ctx->d, ht, f->nodes, L.ncell, L.d_mom.p,
-                                                          L.d_tm.p, L.d_tsum.p);
-          TDBEM_HIP(hipGetLastError());
-          launch_sep_products(f, L, ctx->d, st);
-          m2l_sep_expand_kernel<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
-              f->Ps, f->pt, ctx->d, f->mu, f->R, k, ctx->c, ctx->dt, Ml, ht, f->nodes, L.ncell, L.npair,
-              L.d_il_ptr.p, L.d_il_src.p, L.d_pair_gr.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
-          TDBEM_HIP(hipGetLastError());
-        }
         ProfScope ps(ctx, K_M2L_RED);
         if (L.dense_blocks > 0) {
           dim3 g2(L.ncell, f->Gn, (P + 255) / 256);
           const int bs = std::min(256, ((P + 63) / 64) * 64);
           if (f->prec != 0)
             m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_pair_gr.p,
-                                                         L.d_stage32.p, L.ncell, L.d_ring.p);
+                                                         L.d_stage32.p, L.ncell, f->oscale, L.d_ring.p);
           else
             m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_pair_gr.p,
-                                                          L.d_stage.p, L.ncell, L.d_ring.p);
+                                                          L.d_stage.p, L.ncell, f->oscale, L.d_ring.p);
           TDBEM_HIP(hipGetLastError());
         }
         const int64_t nrec = (int64_t)L.ncell * P;
@@ -2221,6 +2417,82 @@ void fmm_advance(tdbem_ctx* ctx, int beta) {
   }
 }
 
+// Several contexts in lock step: the due levels of all of them in one M2L launch.
+// The launch shape (P, mu + 1 blocks, precision, tile variant) is common, so the
+// contexts must agree on P, mu and precision; equal M_leaf makes their interval ends
+// coincide.  Descriptor tables are built once per distinct pattern of due levels
+// and kept on the device.
+struct FmmBatch {
+  std::vector<tdbem_ctx*> ctxs;
+  int choice = 0;                          // tile variant (2 * variant + persistent)
+  struct Table { DevBuf<M2LLevelWork> lev; DevBuf<int32_t> item0; int nlev = 0, total = 0; };
+  std::map<std::vector<int>, std::unique_ptr<Table>> tables;
+};
+
+FmmBatch* fmm_batch_create(tdbem_ctx* const* ctxs, int n) {
+  if (n < 1) throw Error(TDBEM_E_INVAL, "empty batch");
+  const Fmm* f0 = ctxs[0]->fmm;
+  for (int i = 0; i < n; ++i) {
+    const Fmm* f = ctxs[i]->fmm;
+    if (!f || f->P != f0->P || f->Gn != f0->Gn || f->prec != f0->prec || f->m_leaf != f0->m_leaf ||
+        f->Pp != f0->Pp)
+      throw Error(TDBEM_E_INVAL, "batch M2L: contexts differ in P, mu, precision or M_leaf");
+  }
+  auto* b = new FmmBatch();
+  b->ctxs.assign(ctxs, ctxs + n);
+  // the tile of the context with the most interaction pairs, for its leaf-level launch
+  int best = 0;
+  int64_t most = -1;
+  for (int i = 0; i < n; ++i) {
+    const Fmm* f = ctxs[i]->fmm;
+    if (f->lev[f->D].npair > most) { most = f->lev[f->D].npair; best = i; }
+  }
+  b->choice = ctxs[best]->fmm->m2l_choice[1] & ~1;  // one item per workgroup (the grid covers all items)
+  return b;
+}
+
+void fmm_batch_destroy(FmmBatch* b) { delete b; }
+
+void fmm_batch_m2l(FmmBatch* b, const int* ndue, hipStream_t st) {
+  const int n = (int)b->ctxs.size();
+  std::vector<int> key(ndue, ndue + n);
+  auto it = b->tables.find(key);
+  if (it == b->tables.end()) {
+    std::vector<M2LLevelWork> lev;
+    std::vector<int32_t> first;
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+      const Fmm* f = b->ctxs[i]->fmm;
+      for (int l = f->D; l > f->D - ndue[i] && l >= 2; --l) {
+        M2LLevelWork Lw{};
+        int ni = 0;
+        if (!level_work(f, l, b->choice >> 1, total, Lw, ni)) continue;
+        lev.push_back(Lw);
+        first.push_back(total);
+        total += ni;
+      }
+    }
+    auto t = std::make_unique<FmmBatch::Table>();
+    t->nlev = (int)lev.size();
+    t->total = total;
+    if (!lev.empty()) {
+      t->lev.alloc(lev.size());
+      t->item0.alloc(first.size());
+      TDBEM_HIP(hipMemcpy(t->lev.p, lev.data(), lev.size() * sizeof(M2LLevelWork), hipMemcpyHostToDevice));
+      TDBEM_HIP(hipMemcpy(t->item0.p, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    it = b->tables.emplace(key, std::move(t)).first;
+  }
+  const FmmBatch::Table& t = *it->second;
+  if (t.total == 0) return;
+  M2LWork W{};
+  W.nlev = t.nlev;
+  W.total = t.total;
+  W.glev = t.lev.p;
+  W.gitem0 = t.item0.p;
+  launch_m2l_work(b->ctxs[0]->fmm, b->choice, W, st);
+}
+
 void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   const Fmm* f = ctx->fmm;
   info->depth = f->D;
@@ -2233,8 +2505,10 @@ void fmm_info(const tdbem_ctx* ctx, tdbem_info* info) {
   for (int l = 2; l <= f->D && l < 16; ++l) {
     info->il_pairs[l] = f->lev[l].npair;
     info->m2l_dense_blocks[l] = f->lev[l].dense_blocks;
-    bytes += (int64_t)f->lev[l].d_Uf.n * sizeof(double) + (int64_t)f->lev[l].d_U32.n * sizeof(float) +
-             (int64_t)f->lev[l].d_U16.n * sizeof(uint16_t);
+    const LevelOps* ops = f->lev[l].ops.get();
+    info->m2l_ops_users[l] = (int)f->lev[l].ops.use_count();
+    if (ops) bytes += (int64_t)ops->Uf.n * sizeof(double) + (int64_t)ops->U32.n * sizeof(float) +
+                      (int64_t)ops->U16.n * sizeof(uint16_t);
   }
   info->m2l_matrix_bytes = bytes;
 }

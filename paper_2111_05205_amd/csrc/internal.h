@@ -165,9 +165,10 @@ enum ProfKind { K_NEAR = 0, K_GMRES = 1, K_L2P = 2, K_P2M = 3, K_M2L_GEMM = 4, K
 struct ProfScope {
   tdbem_ctx* c;
   int kind;
+  hipStream_t s;  // the stream the bracketed launches go to (default: the context's)
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ProfScope(tdbem_ctx* ctx, int k) : c(ctx), kind(k) {
-    if (c->prof && ((c->prof_mask >> k) & 1u) && take(e0) && take(e1)) (void)hipEventRecord(e0, c->stream);
+  ProfScope(tdbem_ctx* ctx, int k, hipStream_t stream = nullptr) : c(ctx), kind(k), s(stream ? stream : ctx->stream) {
+    if (c->prof && ((c->prof_mask >> k) & 1u) && take(e0) && take(e1)) (void)hipEventRecord(e0, s);
   }
   bool take(hipEvent_t& e) {
     if (!c->ev_pool.empty()) {
@@ -179,7 +180,7 @@ struct ProfScope {
   }
   ~ProfScope() {
     if (c->prof && e0 && e1) {
-      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventRecord(e1, s);
       c->prof_ev.push_back({kind, {e0, e1}});
     }
   }
@@ -232,6 +233,18 @@ void fmm_reset(tdbem_ctx* ctx);
 void fmm_far(tdbem_ctx* ctx, int alpha, double* out);
 // the coefficient row beta has been stored: update moments and run interval-end translations
 void fmm_advance(tdbem_ctx* ctx, int beta);
+// the same in three parts: P2M and M2M (returns the number of levels whose interval ends),
+// their M2L launch (fmm_advance or fmm_batch_m2l), then everything after the products
+int fmm_advance_pre(tdbem_ctx* ctx, int beta);
+void fmm_advance_sep(tdbem_ctx* ctx, int beta, int ndue, hipStream_t st);  // separable products, beside the M2L
+void fmm_advance_post(tdbem_ctx* ctx, int beta, int ndue);
+// contexts marching in lock step with one M2L launch per step for all of them (equal P,
+// mu, precision and M_leaf; fmm_batch_create throws otherwise)
+struct FmmBatch;
+FmmBatch* fmm_batch_create(tdbem_ctx* const* ctxs, int n);
+void fmm_batch_destroy(FmmBatch* b);
+// the products of ndue[i] levels of context i (0: none) in one launch on st
+void fmm_batch_m2l(FmmBatch* b, const int* ndue, hipStream_t st);
 void fmm_info(const tdbem_ctx* ctx, tdbem_info* info);
 int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice);
 void fmm_near_pairs(const tdbem_ctx* ctx, std::vector<int64_t>& row_ptr, std::vector<int32_t>& pair_j);

@@ -439,3 +439,18 @@ def test_hermite_fmm_approximates_direct_history_sum(fmm3, marched):
     R = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 3, 3, 3, bc=mot.NEUMANN, interp="hermite")
     err = np.linalg.norm(R.history_rhs(32, u, q) - ref) / np.linalg.norm(ref)
     assert err < 0.1, err
+
+
+def test_leaf_ratio_tree_sizing():
+    """leaf_ratio: leaf side = leaf_ratio c dt, the fewest levels (>= 2) whose root holds the mesh,
+    every face in a leaf; scaling mesh and dt together scales the tree and keeps depth, M_leaf, mu."""
+    xyz, tri = synth.icosphere(3)
+    dt = synth.mean_edge_length(xyz, tri)
+    trees = []
+    for s in (1.0, 3.0):
+        R = F.ReferenceFMM(s * xyz, tri, 1.0, s * dt, 2, 1, 0, 3, 3, leaf_ratio=2.5)
+        ext = float(((s * xyz).max(0) - (s * xyz).min(0)).max() / 2)
+        assert np.isclose(2 * R.hs(R.D), 2.5 * s * dt)
+        assert R.H >= ext and (R.D == 2 or R.H / 2 < ext)
+        trees.append((R.D, R.m_leaf, R.mu, [len(c) for c in R.cells]))
+    assert trees[0] == trees[1]
