@@ -1155,6 +1155,141 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
   } while (w < total);
 }
 
+// The same products with the moment fragments staged through LDS: per K step the
+// workgroup loads each of its NCB column blocks' fragments (hi, and lo for X3) once,
+// instead of once per wave, into one of two LDS buffers (one barrier per step; the
+// buffer written at step s was last read at step s - 1).  Dead columns are staged as zeros.
+template <int NCB, int RPW, bool PERS, bool X3, bool GLEV = false>
+__global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, int RB, int KB32, M2LWork W) {
+  typedef float f4_t __attribute__((ext_vector_type(4)));
+  constexpr int BN = NCB * 16;
+  constexpr int NH = X3 ? 2 : 1;           // hi (and lo) copies of the moments
+  constexpr int NF = NH * NCB * 64;        // B fragments (16 bytes each) per K step
+  constexpr int FPT = (NF + 255) / 256;    // of them per thread
+  __shared__ int pid[BN];
+  __shared__ uint4 Bs[2][NF];
+  const int total = W.total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int w = blockIdx.x;
+  do {
+  const int q8 = total / 8, r8 = total % 8, x8 = w % 8;
+  const int item = x8 * q8 + min(x8, r8) + w / 8;
+  const M2LLevelWork& Lw = item_level<GLEV>(W, item);
+  const int local = item - Lw.item0;
+  const ItemGeom ig = item_geom(Lw, local, GP, (int64_t)RB * KB32 * 512);
+  const int tile = ig.tile, rowblk = ig.rowblk, rows = ig.rows, RBs = (rows + 15) >> 4;
+  const int32_t* __restrict__ tiles = Lw.tiles;
+  const int32_t* __restrict__ pairs_by_slot = Lw.pairs_by_slot;
+  const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
+  float* __restrict__ stage = static_cast<float*>(Lw.stage) + ig.soff;
+  const int first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
+  if constexpr (PERS) __syncthreads();  // the previous item's readers of pid and Bs are done
+  const int rb0 = (rowblk * 4 + wave) * RPW;
+  if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
+  // this thread's B fragments: f = tid + 256 i -> copy h, column block cb, lane l
+  const uint4* bsrc[FPT];
+  bool blive[FPT];
+#pragma unroll
+  for (int i = 0; i < FPT; ++i) {
+    const int f = tid + 256 * i;
+    const int ff = f < NF ? f : 0;
+    const int h = ff / (NCB * 64), cb = (ff / 64) % NCB, l = ff % 64;
+    const int col = cb * 16 + (l & 15);
+    blive[i] = f < NF && col < cnt;
+    const uint16_t* base = h ? Lw.mom16_lo : Lw.mom16;
+    bsrc[i] = reinterpret_cast<const uint4*>(base + (int64_t)src_by_slot[first + min(col, cnt - 1)] * Pp +
+                                             8 * (l >> 4));
+  }
+  const uint4* Ar[RPW];
+  const uint4* Arl[X3 ? RPW : 1];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int64_t aoff = (int64_t)min(rb0 + r, RBs - 1) * KB32 * 64 + lane;
+    Ar[r] = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Lw.Uf) + ig.uoff) + aoff;
+    if constexpr (X3) Arl[r] = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Lw.Uf_lo) + ig.uoff) + aoff;
+  }
+  f4_t acc[RPW][NCB];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+  uint4 fa[2][RPW], fal[2][X3 ? RPW : 1], fb[FPT];
+  auto load_a = [&](int set, int s) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      fa[set][r] = Ar[r][(int64_t)s * 64];
+      if constexpr (X3) fal[set][r] = Arl[r][(int64_t)s * 64];
+    }
+  };
+  auto load_b = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < FPT; ++i) fb[i] = bsrc[i][4 * s];
+  };
+  auto stage_b = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < FPT; ++i)
+      if (tid + 256 * i < NF) Bs[buf][tid + 256 * i] = blive[i] ? fb[i] : uint4{0u, 0u, 0u, 0u};
+  };
+  auto products = [&](int set, int buf) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, Bs[buf][cb * 64 + lane]);
+      if constexpr (X3) {
+        const bf16x8_t bvl = __builtin_bit_cast(bf16x8_t, Bs[buf][(NCB + cb) * 64 + lane]);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {  // the two small terms first
+          acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fal[set][r]), bv,
+                                                               acc[r][cb], 0, 0, 0);
+          acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fa[set][r]), bvl,
+                                                               acc[r][cb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fa[set][r]), bv,
+                                                             acc[r][cb], 0, 0, 0);
+    }
+  };
+  // K step s uses register set s % 2 and LDS buffer s % 2
+  auto step = [&](auto setc, int s) {
+    constexpr int set = decltype(setc)::value;
+    const bool more = s + 1 < KB32;
+    if (more) {
+      load_a(set ^ 1, s + 1);
+      load_b(s + 1);
+    }
+    products(set, set);
+    if (more) stage_b(set ^ 1);
+    __syncthreads();
+  };
+  load_a(0, 0);
+  load_b(0);
+  stage_b(0);
+  __syncthreads();
+  for (int s = 0; s < KB32; s += 2) {
+    step(std::integral_constant<int, 0>{}, s);
+    if (s + 1 < KB32) step(std::integral_constant<int, 1>{}, s + 1);
+  }
+#pragma unroll
+  for (int h = 0; h < RPW; ++h)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int p = pid[cb * 16 + (lane & 15)];
+      const int row0 = (rb0 + h) * 16 + 4 * (lane >> 4);
+      if (p < 0) continue;
+      if (((GP | ig.soff) & 3) == 0 && row0 + 3 < rows) {
+        *reinterpret_cast<f4_t*>(stage + (int64_t)p * GP + row0) = acc[h][cb];
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < rows) stage[(int64_t)p * GP + row0 + r] = acc[h][cb][r];
+    }
+    if constexpr (!PERS) break;
+    w += gridDim.x;
+  } while (w < total);
+}
+
 // Operators in the BF16 fragment order above (rows GP of each slot's GPsrc-row stack from row0).
 // Uf_lo: NULL, or where the second bf16 term of each value goes (split products).
 __global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int RB, int KB32,
@@ -1177,10 +1312,11 @@ __global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
 // wave).  The variant and whether the launch is persistent are chosen by
 // timing (autotuning).
-constexpr int M2L_VARIANTS = 12;
+constexpr int M2L_VARIANTS = 16;
 constexpr int M2L_FIRST_DIRECT = 8;  // variants from here on use m2l_direct_kernel (P % 4 == 0)
-static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32, 32, 32, 64, 64};
-static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4, 2, 4, 2, 4};
+constexpr int M2L_FIRST_BF16_LDS = 12;  // BF16 only: the shapes of 8 .. 11 with the moments staged in LDS
+static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32, 32, 32, 64, 64, 32, 32, 64, 64};
+static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4, 2, 4, 2, 4, 2, 4, 2, 4};
 
 template <class T, bool PERS, bool GLEV = false>
 static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
@@ -1200,14 +1336,19 @@ static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int 
   }
 }
 
-// BF16 contexts use the tile shapes of variants 8 .. 11 (columns x rows per workgroup).
+// BF16 contexts use the tile shapes of variants 8 .. 11 (columns x rows per workgroup), and
+// 12 .. 15, the same shapes with the moment fragments staged in LDS.
 template <bool PERS, bool X3, bool GLEV = false>
 static void launch_m2l_bf16_tile(int v, int grid, hipStream_t st, int Pp, int GP, int RB, int KB32, const M2LWork& W) {
   switch (v) {
     case 8: m2l_bf16_kernel<2, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
     case 9: m2l_bf16_kernel<2, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
     case 10: m2l_bf16_kernel<4, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    default: m2l_bf16_kernel<4, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 11: m2l_bf16_kernel<4, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 12: m2l_bf16_lds_kernel<2, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 13: m2l_bf16_lds_kernel<2, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 14: m2l_bf16_lds_kernel<4, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    default: m2l_bf16_lds_kernel<4, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
   }
 }
 
@@ -1805,6 +1946,7 @@ static void autotune_m2l(Fmm* f, hipStream_t st) {
     for (int c = 0; c < 2 * M2L_VARIANTS; ++c) {
       if ((c & 1) && m2l_work_items(f, n, c >> 1) <= f->persistent_grid) continue;
       if ((c >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec < 2) continue;
+      if ((c >> 1) >= M2L_FIRST_BF16_LDS && f->prec < 2) continue;
       if ((c >> 1) < M2L_FIRST_DIRECT && f->prec >= 2) continue;  // BF16: the four LDS-free shapes
       launch_m2l_levels(f, n, c, st);  // warm-up
       TDBEM_HIP(hipEventRecord(e0, st));
@@ -2517,6 +2659,7 @@ int fmm_set_m2l_variant(tdbem_ctx* ctx, int n, int choice) {
   Fmm* f = ctx->fmm;
   if (!f || n < 1 || n > f->D - 1 || n >= 16 || choice < 0 || choice >= 2 * M2L_VARIANTS) return TDBEM_E_INVAL;
   if ((choice >> 1) >= M2L_FIRST_DIRECT && f->P % 4 != 0 && f->prec < 2) return TDBEM_E_INVAL;
+  if ((choice >> 1) >= M2L_FIRST_BF16_LDS && f->prec < 2) return TDBEM_E_INVAL;
   if ((choice >> 1) < M2L_FIRST_DIRECT && f->prec >= 2) return TDBEM_E_INVAL;
   f->m2l_choice[n] = choice;
   return TDBEM_OK;

@@ -120,7 +120,8 @@ def test_fmm_fp32_m2l_products(s3):
 def test_fmm_bf16_m2l_products(pp):
     """BF16 near-future products (operators and moments rounded to bf16, FP32 accumulation on
     v_mfma_f32_16x16x32_bf16), derivative products and everything else FP64: every BF16 tile
-    shape, one item per workgroup and persistent, against the FP64 oracle FMM.  p = 3 gives
+    shape (moments read per lane, or staged through LDS), one item per workgroup and persistent,
+    against the FP64 oracle FMM.  p = 3 gives
     P = 81 (K padded to 96), p = 4 P = 256."""
     P = _P()
     xyz, tri = synth.icosphere(2)
@@ -139,7 +140,7 @@ def test_fmm_bf16_m2l_products(pp):
     dev = torch.device("cuda")
     g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=pp, p_t=pp, m2l_prec=P.M2L_BF16, nt_max=32)
     errs, errs_b = {}, {}
-    for choice in range(16, 24):
+    for choice in range(16, 32):  # BF16 tiles 8..11 and their LDS-staged forms 12..15
         g.set_m2l_variant(1, choice)
         g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
         got = g.fmm_eval(21).cpu().numpy()
@@ -180,7 +181,7 @@ def test_fmm_bf16x3_m2l_products(pp):
     dev = torch.device("cuda")
     g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=pp, p_t=pp, m2l_prec=P.M2L_BF16X3, nt_max=32)
     errs, errs_b = {}, {}
-    for choice in range(16, 24):
+    for choice in range(16, 32):  # BF16 tiles 8..11 and their LDS-staged forms 12..15
         g.set_m2l_variant(1, choice)
         g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
         got = g.fmm_eval(21).cpu().numpy()
