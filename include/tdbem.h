@@ -174,7 +174,8 @@ typedef struct {
                            8 32x16x128, 9 32x16x256, 10 64x16x128, 11 64x16x256 (each lane reads its
                            moments directly, no LDS or barrier in the K loop); BF16 contexts use these
                            four shapes with K steps of 32, and 12 .. 15, the same four with the moment
-                           fragments staged through LDS once per workgroup */
+                           fragments staged through LDS once per workgroup, 16 128x32x128 and
+                           17 128x32x256 likewise */
   int gmres_workgroups; /* workgroups of the per-step solve (1: single-workgroup kernel; autotuned above 2048 faces) */
   int64_t m2l_dense_blocks[16]; /* per level: sum over interaction pairs of the near-future gaps evaluated as dense
                                    P x P products (the wavefront crosses the pair's node set there; the other gaps

@@ -1312,11 +1312,12 @@ __global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
 // wave).  The variant and whether the launch is persistent are chosen by
 // timing (autotuning).
-constexpr int M2L_VARIANTS = 16;
+constexpr int M2L_VARIANTS = 18;
 constexpr int M2L_FIRST_DIRECT = 8;  // variants from here on use m2l_direct_kernel (P % 4 == 0)
-constexpr int M2L_FIRST_BF16_LDS = 12;  // BF16 only: the shapes of 8 .. 11 with the moments staged in LDS
-static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32, 32, 32, 64, 64, 32, 32, 64, 64};
-static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4, 2, 4, 2, 4, 2, 4, 2, 4};
+constexpr int M2L_FIRST_BF16_LDS = 12;  // BF16 only: moments staged in LDS (8 .. 11's shapes, and 128 columns)
+static const int kVariantCols[M2L_VARIANTS] = {128, 64, 64, 32, 32, 32, 64, 32, 32, 32, 64, 64, 32, 32, 64, 64,
+                                               128, 128};
+static const int kVariantRpw[M2L_VARIANTS] = {2, 2, 2, 2, 2, 4, 4, 4, 2, 4, 2, 4, 2, 4, 2, 4, 2, 4};
 
 template <class T, bool PERS, bool GLEV = false>
 static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int RB, int KB, const M2LWork& W) {
@@ -1337,7 +1338,7 @@ static void launch_m2l_tile(int v, int grid, hipStream_t st, int P, int GP, int 
 }
 
 // BF16 contexts use the tile shapes of variants 8 .. 11 (columns x rows per workgroup), and
-// 12 .. 15, the same shapes with the moment fragments staged in LDS.
+// 12 .. 17, those shapes and 128 x 128, 128 x 256 with the moment fragments staged in LDS.
 template <bool PERS, bool X3, bool GLEV = false>
 static void launch_m2l_bf16_tile(int v, int grid, hipStream_t st, int Pp, int GP, int RB, int KB32, const M2LWork& W) {
   switch (v) {
@@ -1348,7 +1349,9 @@ static void launch_m2l_bf16_tile(int v, int grid, hipStream_t st, int Pp, int GP
     case 12: m2l_bf16_lds_kernel<2, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
     case 13: m2l_bf16_lds_kernel<2, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
     case 14: m2l_bf16_lds_kernel<4, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
-    default: m2l_bf16_lds_kernel<4, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 15: m2l_bf16_lds_kernel<4, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    case 16: m2l_bf16_lds_kernel<8, 2, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
+    default: m2l_bf16_lds_kernel<8, 4, PERS, X3, GLEV><<<grid, 256, 0, st>>>(Pp, GP, RB, KB32, W); break;
   }
 }
 

@@ -140,7 +140,7 @@ def test_fmm_bf16_m2l_products(pp):
     dev = torch.device("cuda")
     g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=pp, p_t=pp, m2l_prec=P.M2L_BF16, nt_max=32)
     errs, errs_b = {}, {}
-    for choice in range(16, 32):  # BF16 tiles 8..11 and their LDS-staged forms 12..15
+    for choice in range(16, 36):  # BF16 tiles 8..11, their LDS-staged forms 12..15, and 16..17
         g.set_m2l_variant(1, choice)
         g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
         got = g.fmm_eval(21).cpu().numpy()
@@ -181,7 +181,7 @@ def test_fmm_bf16x3_m2l_products(pp):
     dev = torch.device("cuda")
     g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=pp, p_t=pp, m2l_prec=P.M2L_BF16X3, nt_max=32)
     errs, errs_b = {}, {}
-    for choice in range(16, 32):  # BF16 tiles 8..11 and their LDS-staged forms 12..15
+    for choice in range(16, 36):  # BF16 tiles 8..11, their LDS-staged forms 12..15, and 16..17
         g.set_m2l_variant(1, choice)
         g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
         got = g.fmm_eval(21).cpu().numpy()
