@@ -1395,16 +1395,18 @@ __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Gn, int R, i
   const ST* sp = stage + (int64_t)g * P + a;
   const int64_t ld = (int64_t)Gn * P;
   double s0 = 0.0, s1 = 0.0;
+  int n = 0;  // contributing pairs (the same for every thread of the block)
   int p = p0;
   for (; p + 1 < p1; p += 2) {
     const int r0 = pair_gr[p], r1 = pair_gr[p + 1];
-    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) s0 += (double)sp[(int64_t)p * ld];
-    if (gap >= (r1 & 0xffff) && gap < (r1 >> 16)) s1 += (double)sp[(int64_t)(p + 1) * ld];
+    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) { s0 += (double)sp[(int64_t)p * ld]; ++n; }
+    if (gap >= (r1 & 0xffff) && gap < (r1 >> 16)) { s1 += (double)sp[(int64_t)(p + 1) * ld]; ++n; }
   }
   if (p < p1) {
     const int r0 = pair_gr[p];
-    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) s0 += (double)sp[(int64_t)p * ld];
+    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) { s0 += (double)sp[(int64_t)p * ld]; ++n; }
   }
+  if (n == 0) return;  // no dense block of this cell at this gap: the local stays as it is
   ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += scale * (s0 + s1);
 }
 
