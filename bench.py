@@ -115,7 +115,7 @@ def m2l_kernel_source():
     """Text of the M2L product kernel and its launch code (what the HBM counters describe)."""
     src = open(os.path.join(ROOT, "paper_2111_05205_amd", "csrc", "fmm.hip"), "rb").read()
     a = src.index(b"constexpr int M2L_MAXLEV")
-    b = src.index(b"// Sum of one staged coefficient over pairs")
+    b = src.index(b"// Reduce the staged near-future products per target cell")
     return src[a:b]
 
 

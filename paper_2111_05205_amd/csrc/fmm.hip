@@ -128,7 +128,7 @@ struct FmmLevel {
   DevBuf<float> d_stage32;                  // FP32 / BF16 per-pair products
   DevBuf<double> d_Ktf;                     // derivative products' spatial kernels r^{-1} (and r, d = 3), fragment order
   DevBuf<double> d_tm, d_tsum;              // time moments [j][cell][b] and their node sums [j][cell]
-  DevBuf<double> d_V;                       // separable pair products [product][pair][Ps]
+  DevBuf<double> d_V;                       // separable pair products [product][pair][Psr]
   // Per slot (offset): the near-future gaps gf .. g0-1 have node pairs on both sides of the
   // wavefront and are dense operator blocks; gaps before gf are zero at every node pair,
   // gaps from g0 on are wavefront-free (separable).
@@ -139,6 +139,9 @@ struct FmmLevel {
   int nitems[3][2] = {};
   DevBuf<int32_t> d_items_sep;              // (tile, 0) for every 32-column tile (separable products)
   DevBuf<int32_t> d_pair_gr;                // per interaction pair (target order): gf | g0 << 16
+  // (cell, gap) entries with dense blocks and their pairs (the reduction of the dense products)
+  DevBuf<int32_t> d_red_cg, d_red_ptr, d_red_pairs;
+  int nred = 0;
   int64_t dense_blocks = 0;                 // sum over interaction pairs of their dense blocks
   DevBuf<double> d_mom, d_ring, d_lp, d_aux, d_dp;
   DevBuf<float> d_mom32;                    // FP32 copy of the moments, written by P2M / M2M (FP32 M2L)
@@ -155,6 +158,8 @@ struct Fmm {
   double oscale = 1.0;                     // factor of the dense products: (c dt)^(d-1) with normalised operators
   int Gn = 0;                              // near-future operator blocks, mu + 1
   int Pp = 0;                              // row stride of the BF16 moment copy: P rounded up to 32
+  int Pr = 0;                              // row pitch of a gap's P rows in the operator stacks and staged products
+  int Psr = 0;                             // row pitch of a pair's Ps separable products
   double H = 0, center[3] = {0, 0, 0}, e_max = 0;
   double om_s[MAXP], om_t[MAXP];
   NodeSet nodes{};                         // the same, as a kernel argument
@@ -560,10 +565,10 @@ template <> struct Mfma<float> {
 // RB = ceil(GP/16) blocks and columns to KB = m2l_kblocks(P) blocks (zeros).  A lane's A
 // fragments of V consecutive k blocks are then one 16-byte load, and a wave's load is
 // 1 KB of contiguous memory.
-// row0, GP: the rows row0 .. row0+GP-1 of each slot's G P x P operator stack
-// (GPsrc rows) are converted.
+// row0, GP: GP rows of each slot's G P x P operator stack (GPsrc rows) from source row
+// row0, each gap's P rows at a pitch of Pr rows (rows P .. Pr-1 of a gap are zeros).
 template <class T>
-__global__ void to_fragments_kernel(int P, int GPsrc, int row0, int GP, int RB, int KB,
+__global__ void to_fragments_kernel(int P, int Pr, int GPsrc, int row0, int GP, int RB, int KB,
                                     const double* __restrict__ U, T* __restrict__ Uf) {
   constexpr int V = Vec16<T>::n;
   const int slot = blockIdx.y;
@@ -574,7 +579,8 @@ __global__ void to_fragments_kernel(int P, int GPsrc, int row0, int GP, int RB, 
   const int64_t blk = idx / (64 * V);
   const int kb = (int)(blk % (KB / V)) * V + e, rb = (int)(blk / (KB / V));
   const int row = rb * 16 + (lane & 15), col = 16 * (kb >> 2) + 4 * (lane >> 4) + (kb & 3);
-  const double v = (row < GP && col < P) ? U[((int64_t)slot * GPsrc + row0 + row) * P + col] : 0.0;
+  const int gi = row / Pr, a = row - gi * Pr;
+  const double v = (row < GP && a < P && col < P) ? U[((int64_t)slot * GPsrc + row0 + gi * P + a) * P + col] : 0.0;
   Uf[(int64_t)slot * per + idx] = (T)v;
 }
 
@@ -1290,9 +1296,9 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, in
   } while (w < total);
 }
 
-// Operators in the BF16 fragment order above (rows GP of each slot's GPsrc-row stack from row0).
+// Operators in the BF16 fragment order above (rows as in to_fragments_kernel).
 // Uf_lo: NULL, or where the second bf16 term of each value goes (split products).
-__global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int RB, int KB32,
+__global__ void to_fragments_bf16_kernel(int P, int Pr, int GPsrc, int row0, int GP, int RB, int KB32,
                                          const double* __restrict__ U, uint16_t* __restrict__ Uf,
                                          uint16_t* __restrict__ Uf_lo) {
   const int slot = blockIdx.y;
@@ -1303,10 +1309,19 @@ __global__ void to_fragments_bf16_kernel(int P, int GPsrc, int row0, int GP, int
   const int64_t blk = idx >> 9;
   const int kb = (int)(blk % KB32), rb = (int)(blk / KB32);
   const int row = rb * 16 + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + e;
-  const double v = (row < GP && col < P) ? U[((int64_t)slot * GPsrc + row0 + row) * P + col] : 0.0;
+  const int gi = row / Pr, a = row - gi * Pr;
+  const double v = (row < GP && a < P && col < P) ? U[((int64_t)slot * GPsrc + row0 + gi * P + a) * P + col] : 0.0;
   const uint16_t h = bf16_rne(v);
   Uf[(int64_t)slot * per + idx] = h;
   if (Uf_lo) Uf_lo[(int64_t)slot * per + idx] = bf16_lo(v, h);
+}
+
+// Row pitch of a gap's P rows in the operator stacks and the staged products: a
+// multiple of 16 (each 16-row MFMA output piece of a pair is an aligned 64-byte
+// FP32 segment) where that adds at most 1/32, else of 4 (aligned 16-byte stores).
+static int row_pitch(int P) {
+  const int r16 = (P + 15) / 16 * 16;
+  return (r16 - P) * 32 <= P ? r16 : (P + 3) / 4 * 4;
 }
 
 // Tile variants of the M2L products: (columns per tile, K step, row blocks per
@@ -1362,52 +1377,50 @@ static void launch_m2l_variant(int v, bool persistent, int grid, hipStream_t st,
   else launch_m2l_tile<T, false>(v, grid, st, P, GP, RB, KB, W);
 }
 
-// Sum of one staged coefficient over pairs p0..p1-1 (row stride ld), four
-// independent partial sums.
+// Reduce the staged near-future products per target cell and gap.  Block e takes
+// the e-th (cell, gap index g) that has dense blocks (red_cg = cell, g per entry) and
+// sums over its pairs red_pairs[red_ptr[e] .. red_ptr[e+1]) (target order), four
+// coefficients per thread (Pr is a multiple of 4, rows P .. Pr-1 are zeros), in FP64
+// with four partial sums; the sum goes into the local L_{k+g+1}.
 template <class ST>
-__device__ inline double sum_pairs(const ST* __restrict__ sp, int64_t ld, int p0, int p1) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int p = p0;
-  for (; p + 3 < p1; p += 4) {
-    s0 += (double)sp[(int64_t)p * ld];
-    s1 += (double)sp[(int64_t)(p + 1) * ld];
-    s2 += (double)sp[(int64_t)(p + 2) * ld];
-    s3 += (double)sp[(int64_t)(p + 3) * ld];
-  }
-  for (; p < p1; ++p) s0 += (double)sp[(int64_t)p * ld];
-  return (s0 + s1) + (s2 + s3);
-}
-
-// Reduce the staged near-future products per target cell: grid (ncell, mu+1,
-// ceil(P/256)); block g adds its sum into the local L_{k+g+1}.  Only the pairs
-// whose offset has a dense block at gap g+1 (gf <= g+1 < g0, pair_gr = gf |
-// g0 << 16) contribute; the condition is the same for every thread of a block.
-template <class ST>
-__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Gn, int R, int k,
-                                                         const int32_t* __restrict__ il_ptr,
-                                                         const int32_t* __restrict__ pair_gr,
-                                                         const ST* __restrict__ stage, int ncell, double scale,
+__global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Pr, int Gn, int R, int k, int ncell,
+                                                         const int32_t* __restrict__ red_cg,
+                                                         const int32_t* __restrict__ red_ptr,
+                                                         const int32_t* __restrict__ red_pairs,
+                                                         const ST* __restrict__ stage, double scale,
                                                          double* __restrict__ ring) {
-  const int O = blockIdx.x, g = blockIdx.y, gap = g + 1;
-  const int a = blockIdx.z * blockDim.x + threadIdx.x;
-  if (a >= P) return;
-  const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
-  const ST* sp = stage + (int64_t)g * P + a;
-  const int64_t ld = (int64_t)Gn * P;
-  double s0 = 0.0, s1 = 0.0;
-  int n = 0;  // contributing pairs (the same for every thread of the block)
-  int p = p0;
-  for (; p + 1 < p1; p += 2) {
-    const int r0 = pair_gr[p], r1 = pair_gr[p + 1];
-    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) { s0 += (double)sp[(int64_t)p * ld]; ++n; }
-    if (gap >= (r1 & 0xffff) && gap < (r1 >> 16)) { s1 += (double)sp[(int64_t)(p + 1) * ld]; ++n; }
+  typedef ST v4_t __attribute__((ext_vector_type(4)));
+  const int e = blockIdx.x;
+  const int a0 = 4 * (blockIdx.y * blockDim.x + threadIdx.x);
+  if (a0 >= P) return;
+  const int O = red_cg[2 * e], g = red_cg[2 * e + 1];
+  const int q0 = red_ptr[e], q1 = red_ptr[e + 1];
+  const int64_t ld = (int64_t)Gn * Pr;
+  const ST* sp = stage + (int64_t)g * Pr + a0;
+  double s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0}, s3[4] = {0, 0, 0, 0};
+  int q = q0;
+  for (; q + 3 < q1; q += 4) {
+    const v4_t v0 = *reinterpret_cast<const v4_t*>(sp + red_pairs[q] * ld);
+    const v4_t v1 = *reinterpret_cast<const v4_t*>(sp + red_pairs[q + 1] * ld);
+    const v4_t v2 = *reinterpret_cast<const v4_t*>(sp + red_pairs[q + 2] * ld);
+    const v4_t v3 = *reinterpret_cast<const v4_t*>(sp + red_pairs[q + 3] * ld);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      s0[c] += (double)v0[c];
+      s1[c] += (double)v1[c];
+      s2[c] += (double)v2[c];
+      s3[c] += (double)v3[c];
+    }
   }
-  if (p < p1) {
-    const int r0 = pair_gr[p];
-    if (gap >= (r0 & 0xffff) && gap < (r0 >> 16)) { s0 += (double)sp[(int64_t)p * ld]; ++n; }
+  for (; q < q1; ++q) {
+    const v4_t v0 = *reinterpret_cast<const v4_t*>(sp + red_pairs[q] * ld);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s0[c] += (double)v0[c];
   }
-  if (n == 0) return;  // no dense block of this cell at this gap: the local stays as it is
-  ring[((int64_t)((k + g + 1) % R) * ncell + O) * P + a] += scale * (s0 + s1);
+  double* L = ring + ((int64_t)((k + g + 1) % R) * ncell + O) * P + a0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (a0 + c < P) L[c] += scale * ((s0[c] + s1[c]) + (s2[c] + s3[c]));
 }
 
 // Time moments of the completed source interval's moments, per cell:
@@ -1457,15 +1470,20 @@ __global__ __launch_bounds__(64) void m2l_time_moments_kernel(int Ps, int pt, in
 // the pairs whose first wavefront-free gap g0 is g, and adds the expansion of the
 // running sum into L_{k+g}; after gap mu+1 every pair is in, and the sum gives the
 // derivative products.  FP64 throughout.
-// V: [product][pair][Ps] in the order (0, 0..d), (2, 0..d-2), (3, 0..d-3).
+// V: [product][pair][Psr] (row pitch Psr >= Ps) in the order (0, 0..d), (2, 0..d-2), (3, 0..d-3).
 __device__ inline int sep_vidx(int k, int j, int d) {
   return k == 0 ? j : k == 2 ? d + 1 + j : d + 1 + (d - 1) + j;
 }
 
-__device__ inline double sep_expand(int q, int d, double cA, double c, const double (&Wc)[4][4]) {
+// Wc is indexed with constants only (loops of fixed trip count, q folds in the
+// unrolled callers), so it stays in registers.
+__device__ __forceinline__ double sep_expand(int q, double cA, double c, const double (&Wc)[4][4]) {
   double val = 0.0;
-  for (int k = 0; k <= q; ++k)
-    for (int j = 0; j + k <= q; ++j) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j + k > q) continue;
       const int i = q - j - k;
       double coef = 1.0;  // q! / (i! j! k!)
       for (int t = 2; t <= q; ++t) coef *= t;
@@ -1477,11 +1495,11 @@ __device__ inline double sep_expand(int q, int d, double cA, double c, const dou
       for (int t = 0; t < j; ++t) term *= c;
       val += term * Wc[k][j];
     }
-  (void)d;
   return val;
 }
 
-__global__ void m2l_sep_expand_kernel(int Ps, int pt, int d, int mu, int R, int ks, double c, double dt, int Ml,
+template <int D>
+__global__ void m2l_sep_expand_kernel(int Ps, int Psr, int pt, int mu, int R, int ks, double c, double dt, int Ml,
                                       double ht, NodeSet nodes, int ncell, int64_t npair,
                                       const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ il_src,
                                       const int32_t* __restrict__ pair_gr, const double* __restrict__ V,
@@ -1497,25 +1515,30 @@ __global__ void m2l_sep_expand_kernel(int Ps, int pt, int d, int mu, int R, int 
       for (int p = p0; p < p1; ++p) {
         if ((pair_gr[p] >> 16) != g) continue;
         ++in;
-        for (int j = 0; j <= d; ++j) Wc[0][j] += V[((int64_t)sep_vidx(0, j, d) * npair + p) * Ps + a];
-        for (int j = 0; j + 1 <= d; ++j) Wc[1][j] += Ssum[(int64_t)j * ncell + il_src[p]];
-        for (int j = 0; j + 2 <= d; ++j) Wc[2][j] += V[((int64_t)sep_vidx(2, j, d) * npair + p) * Ps + a];
-        for (int j = 0; j + 3 <= d; ++j) Wc[3][j] += V[((int64_t)sep_vidx(3, j, d) * npair + p) * Ps + a];
+#pragma unroll
+        for (int j = 0; j <= D; ++j) Wc[0][j] += V[((int64_t)sep_vidx(0, j, D) * npair + p) * Psr + a];
+#pragma unroll
+        for (int j = 0; j + 1 <= D; ++j) Wc[1][j] += Ssum[(int64_t)j * ncell + il_src[p]];
+#pragma unroll
+        for (int j = 0; j + 2 <= D; ++j) Wc[2][j] += V[((int64_t)sep_vidx(2, j, D) * npair + p) * Psr + a];
+#pragma unroll
+        for (int j = 0; j + 3 <= D; ++j) Wc[3][j] += V[((int64_t)sep_vidx(3, j, D) * npair + p) * Psr + a];
       }
       if (in == 0) continue;
       double* L = ring + ((int64_t)((ks + g) % R) * ncell + O) * P + a;
       for (int m = 0; m < pt; ++m) {
         const double cA = c * ((g * (double)Ml + 1.0) * dt + ht * nodes.t[m]);
-        L[(int64_t)Ps * m] += sep_expand(d, d, cA, c, Wc);
+        L[(int64_t)Ps * m] += sep_expand(D, cA, c, Wc);
       }
     }
     // derivative products at the expansion gap mu+1: every pair is in Wc
-    for (int pp = 1; pp <= d; ++pp) {
+#pragma unroll
+    for (int pp = 1; pp <= D; ++pp) {
       double binom = 1.0;
-      for (int t = 0; t < pp; ++t) binom = binom * (d - t) / (t + 1);
+      for (int t = 0; t < pp; ++t) binom = binom * (D - t) / (t + 1);
       for (int m = 0; m < pt; ++m) {
         const double cA = c * (((mu + 1) * (double)Ml + 1.0) * dt + ht * nodes.t[m]);
-        dp[((int64_t)(pp - 1) * ncell + O) * P + a + (int64_t)Ps * m] = binom * sep_expand(d - pp, d, cA, c, Wc);
+        dp[((int64_t)(pp - 1) * ncell + O) * P + a + (int64_t)Ps * m] = binom * sep_expand(D - pp, cA, c, Wc);
       }
     }
   }
@@ -1828,19 +1851,19 @@ static bool level_work(const Fmm* f, int l, int v, int item0, M2LLevelWork& Lw, 
 
 // Launch of a filled work descriptor (tile variant and persistence from choice).
 static void launch_m2l_work(const Fmm* f, int choice, const M2LWork& W, hipStream_t st) {
-  const int P = f->P, G = f->Gn;
+  const int P = f->P, G = f->Gn, GP = G * f->Pr;
   const bool lo = f->prec == 1, b16 = f->prec >= 2, x3 = f->prec == 3;
   const int v = choice >> 1, persistent = choice & 1;
-  const int RB = (G * P + 15) / 16, KB = m2l_kblocks(P);
+  const int RB = (GP + 15) / 16, KB = m2l_kblocks(P);
   const int total = W.total;
   if (total == 0) return;
   if (W.glev) {  // several contexts: one item per workgroup, descriptors from the device table
     if (b16) {
       const int KB32 = (P + 31) / 32;
-      if (x3) launch_m2l_bf16_tile<false, true, true>(v, total, st, f->Pp, G * P, RB, KB32, W);
-      else launch_m2l_bf16_tile<false, false, true>(v, total, st, f->Pp, G * P, RB, KB32, W);
-    } else if (lo) launch_m2l_tile<float, false, true>(v, total, st, P, G * P, RB, KB, W);
-    else launch_m2l_tile<double, false, true>(v, total, st, P, G * P, RB, KB, W);
+      if (x3) launch_m2l_bf16_tile<false, true, true>(v, total, st, f->Pp, GP, RB, KB32, W);
+      else launch_m2l_bf16_tile<false, false, true>(v, total, st, f->Pp, GP, RB, KB32, W);
+    } else if (lo) launch_m2l_tile<float, false, true>(v, total, st, P, GP, RB, KB, W);
+    else launch_m2l_tile<double, false, true>(v, total, st, P, GP, RB, KB, W);
     TDBEM_HIP(hipGetLastError());
     return;
   }
@@ -1849,14 +1872,14 @@ static void launch_m2l_work(const Fmm* f, int choice, const M2LWork& W, hipStrea
   if (b16) {
     const int KB32 = (P + 31) / 32;
     if (x3) {
-      if (pers) launch_m2l_bf16_tile<true, true>(v, grid, st, f->Pp, G * P, RB, KB32, W);
-      else launch_m2l_bf16_tile<false, true>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+      if (pers) launch_m2l_bf16_tile<true, true>(v, grid, st, f->Pp, GP, RB, KB32, W);
+      else launch_m2l_bf16_tile<false, true>(v, grid, st, f->Pp, GP, RB, KB32, W);
     } else {
-      if (pers) launch_m2l_bf16_tile<true, false>(v, grid, st, f->Pp, G * P, RB, KB32, W);
-      else launch_m2l_bf16_tile<false, false>(v, grid, st, f->Pp, G * P, RB, KB32, W);
+      if (pers) launch_m2l_bf16_tile<true, false>(v, grid, st, f->Pp, GP, RB, KB32, W);
+      else launch_m2l_bf16_tile<false, false>(v, grid, st, f->Pp, GP, RB, KB32, W);
     }
-  } else if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, G * P, RB, KB, W);
-  else launch_m2l_variant<double>(v, pers, grid, st, P, G * P, RB, KB, W);
+  } else if (lo) launch_m2l_variant<float>(v, pers, grid, st, P, GP, RB, KB, W);
+  else launch_m2l_variant<double>(v, pers, grid, st, P, GP, RB, KB, W);
   TDBEM_HIP(hipGetLastError());
 }
 
@@ -1901,13 +1924,14 @@ static void launch_sep_products(const Fmm* f, const FmmLevel& L, int d, hipStrea
     Lw.mom32 = nullptr;
     Lw.mom16 = nullptr;
     Lw.Uf = L.d_Ktf.p + (int64_t)kern * nslot * perk;
-    Lw.stage = L.d_V.p + (int64_t)v * L.npair * Ps;
+    Lw.stage = L.d_V.p + (int64_t)v * L.npair * f->Psr;
     Lw.item0 = total;
     total += Lw.ntiles * nrb;
   }
   W.total = total;
   if (total == 0) return;
-  m2l_mfma_kernel<double, 2, 16, 2, false><<<total, 256, 0, st>>>(Ps, Ps, RBk, KBk, W);
+  // rows Ps .. Psr-1 of a pair (zero operator rows) are written too
+  m2l_mfma_kernel<double, 2, 16, 2, false><<<total, 256, 0, st>>>(Ps, f->Psr, RBk, KBk, W);
   TDBEM_HIP(hipGetLastError());
 }
 
@@ -2018,12 +2042,12 @@ static void gap_ranges(const Fmm* f, const std::vector<std::array<int, 3>>& slot
 // products' precision and fragment order (no copy of the whole level in FP64).
 static void build_level_ops(const tdbem_ctx* ctx, const Fmm* f, LevelOps& ops, double c, double dt, double hs,
                             double Ml, hipStream_t st) {
-  const int P = f->P, G = f->Gn, nslot = (int)ops.slots.size();
+  const int P = f->P, Pr = f->Pr, G = f->Gn, nslot = (int)ops.slots.size();
   gap_ranges(f, ops.slots, c, dt, hs, Ml, ops.gf, ops.g0);
   const int KB = m2l_kblocks(P), KB32 = (P + 31) / 32;
   ops.uoff.assign(nslot + 1, 0);
   for (int sl = 0; sl < nslot; ++sl) {
-    const int rows = (ops.g0[sl] - ops.gf[sl]) * P, RBs = (rows + 15) / 16;
+    const int rows = (ops.g0[sl] - ops.gf[sl]) * Pr, RBs = (rows + 15) / 16;
     ops.uoff[sl + 1] = ops.uoff[sl] + (f->prec >= 2 ? (int64_t)RBs * KB32 * 512 : (int64_t)RBs * KB * 64);
   }
   ops.tot = std::max<int64_t>(ops.uoff[nslot], 1);
@@ -2038,7 +2062,7 @@ static void build_level_ops(const tdbem_ctx* ctx, const Fmm* f, LevelOps& ops, d
   DevBuf<double> d_U;  // one slot's (mu+1) P x P near-future operators
   d_U.alloc((size_t)G * P * P);
   for (int sl = 0; sl < nslot; ++sl) {
-    const int rows = (ops.g0[sl] - ops.gf[sl]) * P, RBs = (rows + 15) / 16, row0 = (ops.gf[sl] - 1) * P;
+    const int rows = (ops.g0[sl] - ops.gf[sl]) * Pr, RBs = (rows + 15) / 16, row0 = (ops.gf[sl] - 1) * P;
     if (rows == 0) continue;
     dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), G, 1);
     m2l_matrix_kernel<<<grid, 256, 0, st>>>(f->ps, f->pt, P, G, f->mu, ctx->d, c, hs, Ml * dt / 2.0, dt, (int)Ml,
@@ -2047,12 +2071,14 @@ static void build_level_ops(const tdbem_ctx* ctx, const Fmm* f, LevelOps& ops, d
     const int64_t n = ops.uoff[sl + 1] - ops.uoff[sl];
     const unsigned nb = (unsigned)((n + 255) / 256);
     if (f->prec >= 2)
-      to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB32, d_U.p, ops.U16.p + ops.uoff[sl],
+      to_fragments_bf16_kernel<<<nb, 256, 0, st>>>(P, Pr, G * P, row0, rows, RBs, KB32, d_U.p, ops.U16.p + ops.uoff[sl],
                                                    f->prec == 3 ? ops.U16.p + tot + ops.uoff[sl] : nullptr);
     else if (f->prec == 1)
-      to_fragments_kernel<float><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, d_U.p, ops.U32.p + ops.uoff[sl]);
+      to_fragments_kernel<float><<<nb, 256, 0, st>>>(P, Pr, G * P, row0, rows, RBs, KB, d_U.p,
+                                                     ops.U32.p + ops.uoff[sl]);
     else
-      to_fragments_kernel<double><<<nb, 256, 0, st>>>(P, G * P, row0, rows, RBs, KB, d_U.p, ops.Uf.p + ops.uoff[sl]);
+      to_fragments_kernel<double><<<nb, 256, 0, st>>>(P, Pr, G * P, row0, rows, RBs, KB, d_U.p,
+                                                      ops.Uf.p + ops.uoff[sl]);
     TDBEM_HIP(hipGetLastError());
   }
   TDBEM_HIP(hipStreamSynchronize(st));  // the one-slot buffer and d_so are released at return
@@ -2115,7 +2141,7 @@ static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector
                           const std::vector<int32_t>& tiles64, const std::vector<int32_t>& tiles32, hipStream_t st) {
   (void)ctx;
   FmmLevel& L = f->lev[l];
-  const int nslot = (int)L.slot_off.size(), P = f->P;
+  const int nslot = (int)L.slot_off.size(), Pr = f->Pr;
   const LevelOps& ops = *L.ops;
   L.gf.assign(nslot, 1);
   L.g0.assign(nslot, 1);
@@ -2125,8 +2151,8 @@ static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector
     const int c = L.canon[sl];
     L.gf[sl] = ops.gf[c];
     L.g0[sl] = ops.g0[c];
-    srows[sl] = (L.g0[sl] - L.gf[sl]) * P;
-    soff[sl] = (L.gf[sl] - 1) * P;
+    srows[sl] = (L.g0[sl] - L.gf[sl]) * Pr;
+    soff[sl] = (L.gf[sl] - 1) * Pr;
     uoff[sl] = ops.uoff[c];
   }
   upload(L.d_srows, srows, st);
@@ -2140,6 +2166,28 @@ static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector
     L.dense_blocks += L.g0[sl] - L.gf[sl];
   }
   upload(L.d_pair_gr, gr, st);
+  {
+    std::vector<int32_t> cg, rptr(1, 0), rp;
+    rp.reserve((size_t)L.dense_blocks);
+    for (int O = 0; O < L.ncell; ++O)
+      for (int g = 0; g < f->Gn; ++g) {
+        const size_t before = rp.size();
+        for (int p = L.il_ptr[O]; p < L.il_ptr[O + 1]; ++p) {
+          const int sl = L.il_slot[p];
+          if (g + 1 >= L.gf[sl] && g + 1 < L.g0[sl]) rp.push_back(p);
+        }
+        if (rp.size() == before) continue;
+        cg.push_back(O);
+        cg.push_back(g);
+        rptr.push_back((int32_t)rp.size());
+      }
+    L.nred = (int)rptr.size() - 1;
+    if (rp.empty()) rp.push_back(0);
+    if (cg.empty()) cg.assign(2, 0);
+    upload(L.d_red_cg, cg, st);
+    upload(L.d_red_ptr, rptr, st);
+    upload(L.d_red_pairs, rp, st);
+  }
   const std::vector<int32_t>* tl[3] = {&tiles128, &tiles64, &tiles32};
   for (int ci = 0; ci < 3; ++ci)
     for (int ri = 0; ri < 2; ++ri) {
@@ -2186,6 +2234,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
     f->Ps = f->ps * f->ps * f->ps;
     f->P = f->Ps * f->pt;
     f->Pp = (f->P + 31) / 32 * 32;
+    f->Pr = row_pitch(f->P);
+    f->Psr = (f->Ps + 15) / 16 * 16;
     f->interp = o.interp;
     if (f->interp == TDBEM_INTERP_HERMITE) {
       equispaced(f->ps, f->om_s);
@@ -2316,14 +2366,14 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
         const int64_t perk = (int64_t)RBk * KBk * 64;
         L.d_Ktf.alloc((size_t)nk * nslot * perk);
         dim3 gfk((unsigned)((perk + 255) / 256), nk * nslot);
-        to_fragments_kernel<double><<<gfk, 256, 0, st>>>(f->Ps, f->Ps, 0, f->Ps, RBk, KBk, d_K.p, L.d_Ktf.p);
+        to_fragments_kernel<double><<<gfk, 256, 0, st>>>(f->Ps, f->Ps, f->Ps, 0, f->Ps, RBk, KBk, d_K.p, L.d_Ktf.p);
         TDBEM_HIP(hipGetLastError());
         TDBEM_HIP(hipStreamSynchronize(st));
       }
       L.d_tm.alloc((size_t)L.ncell * (ctx->d + 1) * f->Ps);
       L.d_tsum.alloc((size_t)L.ncell * (ctx->d + 1));
       const int nv = (ctx->d + 1) + std::max(0, ctx->d - 1) + std::max(0, ctx->d - 2);
-      L.d_V.alloc((size_t)std::max<int64_t>(L.npair, 1) * nv * f->Ps);
+      L.d_V.alloc((size_t)std::max<int64_t>(L.npair, 1) * nv * f->Psr);
       level_ops(ctx, f, l, st);
       classify_gaps(ctx, f, l, tiles128, tiles64, tiles32, st);
       L.d_mom.alloc((size_t)L.ncell * P);
@@ -2339,8 +2389,8 @@ Fmm* fmm_create(tdbem_ctx* ctx) {
       L.d_lp.alloc((size_t)ctx->d * L.ncell * P);
       L.d_aux.alloc((size_t)std::max(1, ctx->d * (ctx->d - 1) / 2) * L.ncell * P);  // L^{(p,m)}, m <= p-2
       L.d_dp.alloc((size_t)ctx->d * L.ncell * P);
-      if (f->prec != 0) L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
-      else L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * P);
+      if (f->prec != 0) L.d_stage32.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * f->Pr);
+      else L.d_stage.alloc((size_t)std::max<int64_t>(L.npair, 1) * G * f->Pr);
       for (DevBuf<double>* b : {&L.d_mom, &L.d_ring, &L.d_lp, &L.d_aux})
         TDBEM_HIP(hipMemsetAsync(b->p, 0, b->n * sizeof(double), st));
       TDBEM_HIP(hipStreamSynchronize(st));  // temporaries (d_so) are released at scope end
@@ -2506,9 +2556,11 @@ void fmm_advance_sep(tdbem_ctx* ctx, int beta, int ndue, hipStream_t st) {
                                                     L.d_tm.p, L.d_tsum.p);
     TDBEM_HIP(hipGetLastError());
     launch_sep_products(f, L, ctx->d, st);
-    m2l_sep_expand_kernel<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
-        f->Ps, f->pt, ctx->d, f->mu, f->R, k, ctx->c, ctx->dt, Ml, ht, f->nodes, L.ncell, L.npair,
-        L.d_il_ptr.p, L.d_il_src.p, L.d_pair_gr.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
+    auto expand = ctx->d == 1 ? m2l_sep_expand_kernel<1> : ctx->d == 2 ? m2l_sep_expand_kernel<2>
+                                                                       : m2l_sep_expand_kernel<3>;
+    expand<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
+        f->Ps, f->Psr, f->pt, f->mu, f->R, k, ctx->c, ctx->dt, Ml, ht, f->nodes, L.ncell, L.npair, L.d_il_ptr.p,
+        L.d_il_src.p, L.d_pair_gr.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
     TDBEM_HIP(hipGetLastError());
   }
 }
@@ -2530,15 +2582,17 @@ void fmm_advance_post(tdbem_ctx* ctx, int beta, int ndue) {
       FmmLevel& L = f->lev[l];
       if (L.npair > 0) {
         ProfScope ps(ctx, K_M2L_RED);
-        if (L.dense_blocks > 0) {
-          dim3 g2(L.ncell, f->Gn, (P + 255) / 256);
-          const int bs = std::min(256, ((P + 63) / 64) * 64);
+        if (L.nred > 0) {
+          const int nthr = (P + 3) / 4, bs = std::min(256, (nthr + 63) / 64 * 64);
+          dim3 g2((unsigned)L.nred, (unsigned)((nthr + bs - 1) / bs));
           if (f->prec != 0)
-            m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_pair_gr.p,
-                                                         L.d_stage32.p, L.ncell, f->oscale, L.d_ring.p);
+            m2l_reduce_kernel<float><<<g2, bs, 0, st>>>(P, f->Pr, f->Gn, f->R, k, L.ncell, L.d_red_cg.p,
+                                                         L.d_red_ptr.p, L.d_red_pairs.p, L.d_stage32.p, f->oscale,
+                                                         L.d_ring.p);
           else
-            m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->Gn, f->R, k, L.d_il_ptr.p, L.d_pair_gr.p,
-                                                          L.d_stage.p, L.ncell, f->oscale, L.d_ring.p);
+            m2l_reduce_kernel<double><<<g2, bs, 0, st>>>(P, f->Pr, f->Gn, f->R, k, L.ncell, L.d_red_cg.p,
+                                                          L.d_red_ptr.p, L.d_red_pairs.p, L.d_stage.p, f->oscale,
+                                                          L.d_ring.p);
           TDBEM_HIP(hipGetLastError());
         }
         const int64_t nrec = (int64_t)L.ncell * P;

@@ -87,12 +87,24 @@ def test_fmm_march_accuracy_and_fp32_products(w5k, direct_march):
     assert e6 <= 0.0031 and e / e6 > 10, (e, e6)
     s32 = _ctx(w5k, m2l_prec=P.M2L_FP32)
     x32, _ = s32.run(w5k["nt"], inc=w5k["inc"])
-    d = np.linalg.norm(x32.cpu().numpy() - x64) / np.linalg.norm(x64)
-    # near-future blocks in FP32, derivative blocks (fed to the recurrence) in FP64: measured 1.1e-4
-    assert d < 3e-4, d
-    # the solution decays after the pulse has passed (stable BMBIE, Neumann)
+    x32 = x32.cpu().numpy()
+    # Near-future blocks in FP32, derivative blocks (fed to the recurrence) in FP64.  While the
+    # pulse is on the surface (steps whose solution norm is >= 1% of the largest) the two
+    # marches differ by ~3e-6.  After it has passed, the history sums are differences of
+    # large past terms: the FP32 products' relative error in them reaches 4e-5 .. 9e-5 (the
+    # same for either reduction order), and the small late-time solution of the FP32 march
+    # depends on rounding-level detail (whole-march differences from 3e-6 to 8e-4 between
+    # builds that differ only in the order of FP64 sums), so the bar is on the pulse window.
+    nrm = np.linalg.norm(x64, axis=1)
+    pulse = nrm >= 1e-2 * nrm.max()
+    d = np.linalg.norm(x32[pulse] - x64[pulse]) / np.linalg.norm(x64[pulse])
+    assert d < 3e-5, d
+    e32 = np.linalg.norm(x32 - u_direct) / np.linalg.norm(u_direct)
+    assert abs(e32 - e) < 0.02 * e, (e32, e)  # FP32 products do not change the FMM's accuracy
+    # the solution decays after the pulse has passed (stable BMBIE, Neumann), in both forms
     peak = np.abs(x64).max()
     assert np.abs(x64[-10:]).max() < 0.05 * peak
+    assert np.abs(x32[-10:]).max() < 0.05 * peak
 
 
 def test_smoke_entry_point():
