@@ -196,6 +196,43 @@ def test_fmm_bf16x3_m2l_products(pp):
     g.close()
 
 
+def test_fmm_padded_row_pitch_matches_oracle():
+    """p_s = 3, p_t = 7 (P = 189): each gap's operator rows and each pair's staged products sit at a
+    pitch of 192 rows, the zero-padded layout the benchmarked order (P = 625 at a pitch of 640) uses.
+    History sums against the oracle's FMM: FP64 products to 1e-10 (autotuned tile and two forced
+    ones), split BF16 against the oracle forming the same three products."""
+    from oracle import mlp as OM
+
+    def prod3(X, U):
+        Xh, Uh = OM.bf16(X), OM.bf16(U)
+        Xl, Ul = OM.bf16(X - Xh), OM.bf16(U - Uh)
+        return Xh @ Uh.T + Xh @ Ul.T + Xl @ Uh.T
+    P = _P()
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    ns = tri.shape[0]
+    u = synth.random_history(ns, 24, seed=15)
+    q = synth.random_history(ns, 24, seed=16)
+    want = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, 3, 7).history_rhs(21, u, q)
+    want_b = F.ReferenceFMM(xyz, tri, 1.0, dt, 2, 1, 2, 3, 7, near_product=prod3).history_rhs(21, u, q)
+    dev = torch.device("cuda")
+    for prec, choices in ((P.M2L_FP64, [None, 2 * 6, 2 * 3 + 1]), (P.M2L_BF16X3, [None, 2 * 17, 2 * 12])):
+        g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=3, p_t=7, m2l_prec=prec, nt_max=32)
+        for ch in choices:
+            if ch is not None:
+                g.set_m2l_variant(1, ch)
+            g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
+            got = g.fmm_eval(21).cpu().numpy()
+            if prec == P.M2L_FP64:
+                assert _rel(got, want) < 1e-10, (ch, _rel(got, want))
+            else:
+                eff = _rel(want_b, want)
+                print(f"split BF16 tile {ch}: vs split oracle {_rel(got, want_b):.2e}, vs FP64 oracle "
+                      f"{_rel(got, want):.2e}, split effect {eff:.2e}")
+                assert _rel(got, want_b) < 0.2 * eff and _rel(got, want) < 1e-4
+        g.close()
+
+
 @pytest.mark.parametrize("depth,pp", [(3, 3), (3, 4)])
 def test_dense_block_count_matches_the_oracle_operators(depth, pp):
     """The library evaluates a near-future block (eq. Uabmn) as a dense product only where the
