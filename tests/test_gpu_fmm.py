@@ -233,6 +233,39 @@ def test_fmm_padded_row_pitch_matches_oracle():
         g.close()
 
 
+def test_fmm_bf16x3_every_tile_at_p5():
+    """p_s = p_t = 5 (P = 625, each gap's rows at a pitch of 640), the benchmarked order, where the
+    oracle's FMM is too slow for a test: every BF16 tile, one item per workgroup and persistent,
+    gives the same sums bit for bit (the same products in the same K order), and the split-BF16
+    sums stay within the split-product error of the FP64 products (pinned to the oracle's FMM at
+    other orders, the 640-row pitch at P = 189)."""
+    P = _P()
+    xyz, tri = synth.icosphere(2)
+    dt = synth.mean_edge_length(xyz, tri)
+    ns = tri.shape[0]
+    u = synth.random_history(ns, 24, seed=25)
+    q = synth.random_history(ns, 24, seed=26)
+    dev = torch.device("cuda")
+
+    def sums(g):
+        g.set_history(torch.tensor(u[:20], device=dev), torch.tensor(q[:20], device=dev))
+        return g.fmm_eval(21).cpu().numpy()
+    g64 = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=5, p_t=5, m2l_prec=P.M2L_FP64, nt_max=32)
+    want = sums(g64)
+    g64.close()
+    g = P.TDBEM(xyz, tri, 1.0, dt, 2, 1, 1, use_fmm=1, depth=2, p_s=5, p_t=5, m2l_prec=P.M2L_BF16X3, nt_max=32)
+    got = {}
+    for choice in range(16, 36):
+        g.set_m2l_variant(1, choice)
+        got[choice] = sums(g)
+    g.close()
+    ref = got[16]  # 32 columns x 128 rows, no LDS stage, every K step multiplied
+    assert all(np.array_equal(v, ref) for v in got.values()), [c for c, v in got.items() if not np.array_equal(v, ref)]
+    e = _rel(ref, want)
+    print(f"split BF16 vs FP64 products at P = 625: {e:.2e}")
+    assert 1e-8 < e < 2e-4, e
+
+
 @pytest.mark.parametrize("depth,pp", [(3, 3), (3, 4)])
 def test_dense_block_count_matches_the_oracle_operators(depth, pp):
     """The library evaluates a near-future block (eq. Uabmn) as a dense product only where the
