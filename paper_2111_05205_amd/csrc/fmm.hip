@@ -139,6 +139,7 @@ struct FmmLevel {
   int nitems[3][2] = {};
   DevBuf<int32_t> d_items_sep;              // (tile, 0) for every 32-column tile (separable products)
   DevBuf<int32_t> d_pair_gr;                // per interaction pair (target order): gf | g0 << 16
+  DevBuf<int32_t> d_sep_order;              // each target cell's pairs in order of g0 (stable)
   // (cell, gap) entries with dense blocks and their pairs (the reduction of the dense products)
   DevBuf<int32_t> d_red_cg, d_red_ptr, d_red_pairs;
   int nred = 0;
@@ -1516,29 +1517,52 @@ template <int D>
 __global__ void m2l_sep_expand_kernel(int Ps, int Psr, int pt, int mu, int R, int ks, double c, double dt, int Ml,
                                       double ht, NodeSet nodes, int ncell, int64_t npair,
                                       const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ il_src,
-                                      const int32_t* __restrict__ pair_gr, const double* __restrict__ V,
-                                      const double* __restrict__ Ssum, double* __restrict__ ring,
-                                      double* __restrict__ dp) {
+                                      const int32_t* __restrict__ pair_gr, const int32_t* __restrict__ sep_order,
+                                      const double* __restrict__ V, const double* __restrict__ Ssum,
+                                      double* __restrict__ ring, double* __restrict__ dp) {
   const int O = blockIdx.x;
   const int p0 = il_ptr[O], p1 = il_ptr[O + 1];
   const int P = Ps * pt;
+  // one pair's terms, loaded before any of them is added (so that several pairs' loads overlap)
+  struct Terms { double v[4][4]; };
+  auto fetch = [&](int p, int a, Terms& t) {
+#pragma unroll
+    for (int j = 0; j <= D; ++j) t.v[0][j] = V[((int64_t)sep_vidx(0, j, D) * npair + p) * Psr + a];
+#pragma unroll
+    for (int j = 0; j + 1 <= D; ++j) t.v[1][j] = Ssum[(int64_t)j * ncell + il_src[p]];
+#pragma unroll
+    for (int j = 0; j + 2 <= D; ++j) t.v[2][j] = V[((int64_t)sep_vidx(2, j, D) * npair + p) * Psr + a];
+#pragma unroll
+    for (int j = 0; j + 3 <= D; ++j) t.v[3][j] = V[((int64_t)sep_vidx(3, j, D) * npair + p) * Psr + a];
+  };
   for (int a = threadIdx.x; a < Ps; a += blockDim.x) {
     double Wc[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    int in = 0;  // pairs added so far (the same for every thread)
+    auto add = [&](const Terms& t) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((k == 0 && j <= D) || (k == 1 && j + 1 <= D) || (k >= 2 && j + k <= D)) Wc[k][j] += t.v[k][j];
+    };
+    // the cell's pairs in order of their first wavefront-free gap g0 (target order within a g0)
+    int q = p0;
     for (int g = 1; g <= mu + 1; ++g) {
-      for (int p = p0; p < p1; ++p) {
-        if ((pair_gr[p] >> 16) != g) continue;
-        ++in;
-#pragma unroll
-        for (int j = 0; j <= D; ++j) Wc[0][j] += V[((int64_t)sep_vidx(0, j, D) * npair + p) * Psr + a];
-#pragma unroll
-        for (int j = 0; j + 1 <= D; ++j) Wc[1][j] += Ssum[(int64_t)j * ncell + il_src[p]];
-#pragma unroll
-        for (int j = 0; j + 2 <= D; ++j) Wc[2][j] += V[((int64_t)sep_vidx(2, j, D) * npair + p) * Psr + a];
-#pragma unroll
-        for (int j = 0; j + 3 <= D; ++j) Wc[3][j] += V[((int64_t)sep_vidx(3, j, D) * npair + p) * Psr + a];
+      int qe = q;
+      while (qe < p1 && (pair_gr[sep_order[qe]] >> 16) == g) ++qe;
+      for (; q + 1 < qe; q += 2) {
+        Terms t0, t1;
+        fetch(sep_order[q], a, t0);
+        fetch(sep_order[q + 1], a, t1);
+        add(t0);
+        add(t1);
       }
-      if (in == 0) continue;
+      if (q < qe) {
+        Terms t0;
+        fetch(sep_order[q], a, t0);
+        add(t0);
+        ++q;
+      }
+      if (q == p0) continue;  // no pair added yet (the same for every thread)
       double* L = ring + ((int64_t)((ks + g) % R) * ncell + O) * P + a;
       for (int m = 0; m < pt; ++m) {
         const double cA = c * ((g * (double)Ml + 1.0) * dt + ht * nodes.t[m]);
@@ -2180,6 +2204,16 @@ static void classify_gaps(const tdbem_ctx* ctx, Fmm* f, int l, const std::vector
     L.dense_blocks += L.g0[sl] - L.gf[sl];
   }
   upload(L.d_pair_gr, gr, st);
+  {  // each target cell's pairs in order of g0, target order within one g0
+    std::vector<int32_t> order(std::max<int64_t>(L.npair, 1), 0);
+    for (int O = 0; O < L.ncell; ++O) {
+      const int b = L.il_ptr[O], e = L.il_ptr[O + 1];
+      for (int p = b; p < e; ++p) order[p] = p;
+      std::stable_sort(order.begin() + b, order.begin() + e,
+                       [&](int x, int y) { return L.g0[L.il_slot[x]] < L.g0[L.il_slot[y]]; });
+    }
+    upload(L.d_sep_order, order, st);
+  }
   {
     std::vector<int32_t> cg, rptr(1, 0), rp;
     rp.reserve((size_t)L.dense_blocks);
@@ -2574,7 +2608,7 @@ void fmm_advance_sep(tdbem_ctx* ctx, int beta, int ndue, hipStream_t st) {
                                                                        : m2l_sep_expand_kernel<3>;
     expand<<<L.ncell, std::min(256, ((f->Ps + 63) / 64) * 64), 0, st>>>(
         f->Ps, f->Psr, f->pt, f->mu, f->R, k, ctx->c, ctx->dt, Ml, ht, f->nodes, L.ncell, L.npair, L.d_il_ptr.p,
-        L.d_il_src.p, L.d_pair_gr.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
+        L.d_il_src.p, L.d_pair_gr.p, L.d_sep_order.p, L.d_V.p, L.d_tsum.p, L.d_ring.p, L.d_dp.p);
     TDBEM_HIP(hipGetLastError());
   }
 }
