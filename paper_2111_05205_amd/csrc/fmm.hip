@@ -1400,7 +1400,10 @@ __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Pr, int Gn, 
   const ST* sp = stage + (int64_t)g * Pr + a0;
   double s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0}, s3[4] = {0, 0, 0, 0};
   int q = q0;
-  for (; q + 7 < q1; q += 8) {  // eight rows in flight; pair q + j goes to partial sum j mod 4
+  // FP32 rows: eight in flight (pair q + j goes to partial sum j mod 4); FP64 rows are twice
+  // the registers, and four in flight keep the occupancy up
+  if constexpr (sizeof(ST) == 4)
+  for (; q + 7 < q1; q += 8) {
     v4_t v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const v4_t*>(sp + red_pairs[q + j] * ld);
