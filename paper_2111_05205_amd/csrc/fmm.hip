@@ -1402,20 +1402,21 @@ __global__ __launch_bounds__(256) void m2l_reduce_kernel(int P, int Pr, int Gn, 
   int q = q0;
   // FP32 rows: eight in flight (pair q + j goes to partial sum j mod 4); FP64 rows are twice
   // the registers, and four in flight keep the occupancy up
-  if constexpr (sizeof(ST) == 4)
-  for (; q + 7 < q1; q += 8) {
-    v4_t v[8];
+  if constexpr (sizeof(ST) == 4) {
+    for (; q + 7 < q1; q += 8) {
+      v4_t v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const v4_t*>(sp + red_pairs[q + j] * ld);
+      for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const v4_t*>(sp + red_pairs[q + j] * ld);
 #pragma unroll
-    for (int j = 0; j < 8; j += 4)
+      for (int j = 0; j < 8; j += 4)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        s0[c] += (double)v[j][c];
-        s1[c] += (double)v[j + 1][c];
-        s2[c] += (double)v[j + 2][c];
-        s3[c] += (double)v[j + 3][c];
-      }
+        for (int c = 0; c < 4; ++c) {
+          s0[c] += (double)v[j][c];
+          s1[c] += (double)v[j + 1][c];
+          s2[c] += (double)v[j + 2][c];
+          s3[c] += (double)v[j + 3][c];
+        }
+    }
   }
   for (; q + 3 < q1; q += 4) {
     const v4_t v0 = *reinterpret_cast<const v4_t*>(sp + red_pairs[q] * ld);
