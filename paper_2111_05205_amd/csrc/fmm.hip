@@ -1162,10 +1162,18 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_kernel(int Pp, int GP, int RB
   } while (w < total);
 }
 
+// One 1 KB fragment chunk from global memory straight into LDS: lane l copies the
+// 16 bytes at g (its own address) to lds + 16 l (lds the same for the whole wave).
+__device__ __forceinline__ void copy_to_lds16(const uint4* g, uint4* lds) {
+  __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0);
+}
+
 // The same products with the moment fragments staged through LDS: per K step the
-// workgroup loads each of its NCB column blocks' fragments (hi, and lo for X3) once,
-// instead of once per wave, into one of two LDS buffers (one barrier per step; the
-// buffer written at step s was last read at step s - 1).  Dead columns are staged as zeros.
+// workgroup copies each of its NCB column blocks' fragments (hi, and lo for X3) once,
+// instead of once per wave, from global memory straight into one of two LDS buffers
+// (global_load_lds_dwordx4: no registers in between; one barrier per step, which also
+// waits for the copies; the buffer written at step s was last read at step s - 1).
+// Columns past the tile's pairs repeat its last pair (finite values, never stored).
 template <int NCB, int RPW, bool PERS, bool X3, bool GLEV = false>
 __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, int RB, int KB32, M2LWork W) {
   typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -1174,7 +1182,8 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, in
   constexpr int NF = NH * NCB * 64;        // B fragments (16 bytes each) per K step
   constexpr int FPT = (NF + 255) / 256;    // of them per thread
   __shared__ int pid[BN];
-  __shared__ uint4 Bs[2][NF];
+  // one LDS object per buffer, so that reads of one need not wait for copies into the other
+  __shared__ uint4 Bs0[NF], Bs1[NF];
   const int total = W.total;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int w = blockIdx.x;
@@ -1190,19 +1199,16 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, in
   const int32_t* __restrict__ src_by_slot = Lw.src_by_slot;
   float* __restrict__ stage = static_cast<float*>(Lw.stage) + ig.soff;
   const int first = tiles[3 * tile + 1], cnt = tiles[3 * tile + 2];
-  if constexpr (PERS) __syncthreads();  // the previous item's readers of pid and Bs are done
+  if constexpr (PERS) __syncthreads();  // the previous item's readers of pid and the buffers are done
   const int rb0 = (rowblk * 4 + wave) * RPW;
   if (tid < BN) pid[tid] = tid < cnt ? pairs_by_slot[first + tid] : -1;
-  // this thread's B fragments: f = tid + 256 i -> copy h, column block cb, lane l
+  // this wave's B chunks: c = wave + 4 i -> copy h = c / NCB, column block cb = c % NCB (lane l: 16 bytes)
   const uint4* bsrc[FPT];
-  bool blive[FPT];
 #pragma unroll
   for (int i = 0; i < FPT; ++i) {
-    const int f = tid + 256 * i;
-    const int ff = f < NF ? f : 0;
-    const int h = ff / (NCB * 64), cb = (ff / 64) % NCB, l = ff % 64;
+    const int c = min(wave + 4 * i, NH * NCB - 1);  // chunks past NH NCB are not copied
+    const int h = c / NCB, cb = c % NCB, l = lane;
     const int col = cb * 16 + (l & 15);
-    blive[i] = f < NF && col < cnt;
     const uint16_t* base = h ? Lw.mom16_lo : Lw.mom16;
     bsrc[i] = reinterpret_cast<const uint4*>(base + (int64_t)src_by_slot[first + min(col, cnt - 1)] * Pp +
                                              8 * (l >> 4));
@@ -1220,7 +1226,7 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, in
   for (int i = 0; i < RPW; ++i)
 #pragma unroll
     for (int j = 0; j < NCB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
-  uint4 fa[2][RPW], fal[2][X3 ? RPW : 1], fb[FPT];
+  uint4 fa[2][RPW], fal[2][X3 ? RPW : 1];
   auto load_a = [&](int set, int s) {
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -1228,21 +1234,20 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, in
       if constexpr (X3) fal[set][r] = Arl[r][(int64_t)s * 64];
     }
   };
-  auto load_b = [&](int s) {
-#pragma unroll
-    for (int i = 0; i < FPT; ++i) fb[i] = bsrc[i][4 * s];
-  };
-  auto stage_b = [&](int buf) {
+  auto copy_b = [&](auto bufc, int s) {
+    uint4* Bd = decltype(bufc)::value ? Bs1 : Bs0;
 #pragma unroll
     for (int i = 0; i < FPT; ++i)
-      if (tid + 256 * i < NF) Bs[buf][tid + 256 * i] = blive[i] ? fb[i] : uint4{0u, 0u, 0u, 0u};
+      if (wave + 4 * i < NH * NCB) copy_to_lds16(bsrc[i] + 4 * s, Bd + (wave + 4 * i) * 64);
   };
-  auto products = [&](int set, int buf) {
+  auto products = [&](auto setc) {
+    constexpr int set = decltype(setc)::value;
+    const uint4* Bb = set ? Bs1 : Bs0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, Bs[buf][cb * 64 + lane]);
+      const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, Bb[cb * 64 + lane]);
       if constexpr (X3) {
-        const bf16x8_t bvl = __builtin_bit_cast(bf16x8_t, Bs[buf][(NCB + cb) * 64 + lane]);
+        const bf16x8_t bvl = __builtin_bit_cast(bf16x8_t, Bb[(NCB + cb) * 64 + lane]);
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {  // the two small terms first
           acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, fal[set][r]), bv,
@@ -1260,18 +1265,15 @@ __global__ __launch_bounds__(256, 2) void m2l_bf16_lds_kernel(int Pp, int GP, in
   // K step s uses register set s % 2 and LDS buffer s % 2
   auto step = [&](auto setc, int s) {
     constexpr int set = decltype(setc)::value;
-    const bool more = s + 1 < KB32;
-    if (more) {
+    if (s + 1 < KB32) {
       load_a(set ^ 1, s + 1);
-      load_b(s + 1);
+      copy_b(std::integral_constant<int, set ^ 1>{}, s + 1);
     }
-    products(set, set);
-    if (more) stage_b(set ^ 1);
+    products(setc);
     __syncthreads();
   };
   load_a(0, 0);
-  load_b(0);
-  stage_b(0);
+  copy_b(std::integral_constant<int, 0>{}, 0);
   __syncthreads();
   for (int s = 0; s < KB32; s += 2) {
     step(std::integral_constant<int, 0>{}, s);
