@@ -103,7 +103,7 @@ def measured_traffic(prec, workload="sphere5k"):
     path = os.path.join(ROOT, "profiles", f"m2l_{name}_{workload}_traffic.json")
     try:
         rec = json.load(open(path))
-        src = m2l_kernel_source()
+        src = m2l_kernel_source(prec)
     except (OSError, ValueError):
         return None
     if rec.get("m2l_kernel_source_sha256") != hashlib.sha256(src).hexdigest():
@@ -111,12 +111,18 @@ def measured_traffic(prec, workload="sphere5k"):
     return rec["hbm_bytes_per_launch"]
 
 
-def m2l_kernel_source():
-    """Text of the M2L product kernel and its launch code (what the HBM counters describe)."""
+def m2l_kernel_source(prec=1):
+    """Text of the M2L product kernels of one precision and their launch code (what the HBM
+    counters describe): the FP32 / FP64 kernels and the launchers for FP32 products, the whole
+    product section (the BF16 kernels included) for the BF16 paths."""
     src = open(os.path.join(ROOT, "paper_2111_05205_amd", "csrc", "fmm.hip"), "rb").read()
     a = src.index(b"constexpr int M2L_MAXLEV")
     b = src.index(b"// Reduce the staged near-future products per target cell")
-    return src[a:b]
+    if prec >= 2:
+        return src[a:b]
+    c = src.index(b"// BF16 near-future products")
+    d = src.index(b"// Tile variants of the M2L products")
+    return src[a:c] + src[d:b]
 
 
 def run_form(P, w, args, prec, guess, params=None):
